@@ -1,0 +1,744 @@
+/*
+ * gmg_oracle.c -- plain FP64 CPU oracle for the multigrid-preconditioned
+ * conjugate-gradient solve of the variable-coefficient diffusion problem
+ *
+ *        -div(k grad phi) = f                       (Eq. 2 of the paper)
+ *
+ * on a structured 3D vertex grid with zero Dirichlet boundary values.
+ *
+ * THIS IS TEST INFRASTRUCTURE.  It exists only so that the test suite, the
+ * smoke check and the CPU-baseline leg of the benchmark can check the GPU
+ * library against something obviously correct.  The GPU library never links,
+ * loads or calls it, and the two share no code, headers or constants.
+ *
+ * Everything here is written for readability, not speed: one loop nest per
+ * mathematical operation, no blocking, no fusion, no reordering beyond what
+ * the definition states.  Loops over z-planes carry an OpenMP "parallel for"
+ * only so that large grids finish in reasonable time; every reduction is
+ * summed per plane and then plane by plane in order, so results do not depend
+ * on the thread count.
+ *
+ * Storage (all arrays C order, x fastest):
+ *   vertex vectors   u[k][j][i],        shape (N, N, N),   h = 1/(N-1)
+ *   x-faces          kx[k][j][i],       shape (N, N, N-1), link (i,j,k)-(i+1,j,k)
+ *   y-faces          ky[k][j][i],       shape (N, N-1, N), link (i,j,k)-(i,j+1,k)
+ *   z-faces          kz[k][j][i],       shape (N-1, N, N), link (i,j,k)-(i,j,k+1)
+ * Interior vertices have all three indices in 1..N-2; every vector value at a
+ * boundary vertex is treated as zero.
+ *
+ * Parity status: every routine below is pinned by the CPU test suite against
+ * closed forms, invariants or brute force (sine-mode eigenvalues, an exact
+ * quadratic solution, dense assembly, the Chebyshev polynomial, the adjoint
+ * of restriction/prolongation, dense two-grid composition, finite
+ * differences).  No routine is "parity unpinned".
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_MAX_LEVELS 16
+#define OR_MAX_COARSE 4096 /* largest dense coarsest system the oracle factors */
+
+/* ------------------------------------------------------------------------ */
+/* index helpers                                                            */
+/* ------------------------------------------------------------------------ */
+static size_t vid(int n, int i, int j, int k) { return ((size_t)k * n + j) * n + i; }
+static size_t xid(int n, int i, int j, int k) { return ((size_t)k * n + j) * (n - 1) + i; }
+static size_t yid(int n, int i, int j, int k) { return ((size_t)k * (n - 1) + j) * n + i; }
+static size_t zid(int n, int i, int j, int k) { return ((size_t)k * n + j) * n + i; }
+static int interior(int n, int i, int j, int k)
+{
+    return i >= 1 && i <= n - 2 && j >= 1 && j <= n - 2 && k >= 1 && k <= n - 2;
+}
+/* value of a vertex vector, zero on (and outside) the boundary */
+static double val(int n, const double *u, int i, int j, int k)
+{
+    return interior(n, i, j, k) ? u[vid(n, i, j, k)] : 0.0;
+}
+static size_t nvert(int n) { return (size_t)n * n * n; }
+
+/* ------------------------------------------------------------------------ */
+/* Operator (Eq. 2, 7-point finite differences as in Sec. 4.1, Disc. A):    */
+/*   (A u)_p = h^-2 sum_{faces f of p} k_f (u_p - u_q(f))                   */
+/* ------------------------------------------------------------------------ */
+void or_apply_raw(int n, const double *kx, const double *ky, const double *kz,
+                  const double *u, double *out)
+{
+    double s = (double)(n - 1) * (double)(n - 1); /* h^-2 */
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < n; k++)
+        for (int j = 0; j < n; j++)
+            for (int i = 0; i < n; i++) {
+                if (!interior(n, i, j, k)) {
+                    out[vid(n, i, j, k)] = 0.0;
+                    continue;
+                }
+                double up = u[vid(n, i, j, k)];
+                double acc = 0.0;
+                acc += kx[xid(n, i - 1, j, k)] * (up - val(n, u, i - 1, j, k));
+                acc += kx[xid(n, i, j, k)] * (up - val(n, u, i + 1, j, k));
+                acc += ky[yid(n, i, j - 1, k)] * (up - val(n, u, i, j - 1, k));
+                acc += ky[yid(n, i, j, k)] * (up - val(n, u, i, j + 1, k));
+                acc += kz[zid(n, i, j, k - 1)] * (up - val(n, u, i, j, k - 1));
+                acc += kz[zid(n, i, j, k)] * (up - val(n, u, i, j, k + 1));
+                out[vid(n, i, j, k)] = s * acc;
+            }
+}
+
+/* Diagonal of A: d_p = h^-2 * (sum of the six face coefficients of p). */
+void or_diag_raw(int n, const double *kx, const double *ky, const double *kz, double *d)
+{
+    double s = (double)(n - 1) * (double)(n - 1);
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < n; k++)
+        for (int j = 0; j < n; j++)
+            for (int i = 0; i < n; i++) {
+                if (!interior(n, i, j, k)) {
+                    d[vid(n, i, j, k)] = 0.0;
+                    continue;
+                }
+                double acc = kx[xid(n, i - 1, j, k)] + kx[xid(n, i, j, k)] + ky[yid(n, i, j - 1, k)] +
+                             ky[yid(n, i, j, k)] + kz[zid(n, i, j, k - 1)] + kz[zid(n, i, j, k)];
+                d[vid(n, i, j, k)] = s * acc;
+            }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Coarse face coefficients for the re-discretized coarse operators         */
+/* (Sec. 2.1.1 and Sec. 4.3 use re-discretized coarse operators; the paper  */
+/* gives no averaging rule).  A coarse x-link spans two fine x-links in     */
+/* series along the line y=2J, z=2K, and the lines beside it at y=2J+a,     */
+/* z=2K+b (a,b in -1..1) are averaged with weights w_a w_b,                 */
+/* w = (1/4, 1/2, 1/4).  Along the link the two fine values p, q combine by */
+/*   rule 0 (arithmetic): (p + q)/2                                          */
+/*   rule 1 (harmonic):   2pq/(p + q)                                        */
+/* Only coarse links with at least one interior end point are set; the      */
+/* others are 0.                                                            */
+/* ------------------------------------------------------------------------ */
+static double along(int rule, double p, double q)
+{
+    if (rule == 1)
+        return (p + q) > 0.0 ? 2.0 * p * q / (p + q) : 0.0;
+    return 0.5 * (p + q);
+}
+static const double W3[3] = {0.25, 0.5, 0.25};
+
+void or_coarsen_k_raw(int n, const double *kx, const double *ky, const double *kz,
+                      int nc, double *kxc, double *kyc, double *kzc, int rule)
+{
+    memset(kxc, 0, sizeof(double) * (size_t)nc * nc * (nc - 1));
+    memset(kyc, 0, sizeof(double) * (size_t)nc * (nc - 1) * nc);
+    memset(kzc, 0, sizeof(double) * (size_t)(nc - 1) * nc * nc);
+    /* x-links: I in 0..nc-2, J and K interior */
+    for (int K = 1; K <= nc - 2; K++)
+        for (int J = 1; J <= nc - 2; J++)
+            for (int I = 0; I <= nc - 2; I++) {
+                double acc = 0.0;
+                for (int b = -1; b <= 1; b++)
+                    for (int a = -1; a <= 1; a++) {
+                        double p = kx[xid(n, 2 * I, 2 * J + a, 2 * K + b)];
+                        double q = kx[xid(n, 2 * I + 1, 2 * J + a, 2 * K + b)];
+                        acc += W3[a + 1] * W3[b + 1] * along(rule, p, q);
+                    }
+                kxc[xid(nc, I, J, K)] = acc;
+            }
+    /* y-links: J in 0..nc-2, I and K interior */
+    for (int K = 1; K <= nc - 2; K++)
+        for (int J = 0; J <= nc - 2; J++)
+            for (int I = 1; I <= nc - 2; I++) {
+                double acc = 0.0;
+                for (int b = -1; b <= 1; b++)
+                    for (int a = -1; a <= 1; a++) {
+                        double p = ky[yid(n, 2 * I + a, 2 * J, 2 * K + b)];
+                        double q = ky[yid(n, 2 * I + a, 2 * J + 1, 2 * K + b)];
+                        acc += W3[a + 1] * W3[b + 1] * along(rule, p, q);
+                    }
+                kyc[yid(nc, I, J, K)] = acc;
+            }
+    /* z-links: K in 0..nc-2, I and J interior */
+    for (int K = 0; K <= nc - 2; K++)
+        for (int J = 1; J <= nc - 2; J++)
+            for (int I = 1; I <= nc - 2; I++) {
+                double acc = 0.0;
+                for (int b = -1; b <= 1; b++)
+                    for (int a = -1; a <= 1; a++) {
+                        double p = kz[zid(n, 2 * I + a, 2 * J + b, 2 * K)];
+                        double q = kz[zid(n, 2 * I + a, 2 * J + b, 2 * K + 1)];
+                        acc += W3[a + 1] * W3[b + 1] * along(rule, p, q);
+                    }
+                kzc[zid(nc, I, J, K)] = acc;
+            }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Restriction (Alg. 1, "restrict residual"): full weighting, the tensor    */
+/* product of (1/4, 1/2, 1/4) around fine vertex 2I.  Coarse boundary = 0.  */
+/* ------------------------------------------------------------------------ */
+void or_restrict_raw(int n, const double *r, int nc, double *rc)
+{
+#pragma omp parallel for schedule(static)
+    for (int K = 0; K < nc; K++)
+        for (int J = 0; J < nc; J++)
+            for (int I = 0; I < nc; I++) {
+                if (!interior(nc, I, J, K)) {
+                    rc[vid(nc, I, J, K)] = 0.0;
+                    continue;
+                }
+                double acc = 0.0;
+                for (int c = -1; c <= 1; c++)
+                    for (int b = -1; b <= 1; b++)
+                        for (int a = -1; a <= 1; a++)
+                            acc += W3[a + 1] * W3[b + 1] * W3[c + 1] *
+                                   val(n, r, 2 * I + a, 2 * J + b, 2 * K + c);
+                rc[vid(nc, I, J, K)] = acc;
+            }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Prolongation and correction (Alg. 1, "prolongate error"): trilinear      */
+/* interpolation, x_fine += P e.  In 1D an even fine index 2I takes e_I; an */
+/* odd one 2I+1 takes (e_I + e_{I+1})/2; 3D is the tensor product.          */
+/* ------------------------------------------------------------------------ */
+static int interp_1d(int i, int *idx, double *w)
+{
+    if ((i & 1) == 0) {
+        idx[0] = i / 2;
+        w[0] = 1.0;
+        return 1;
+    }
+    idx[0] = (i - 1) / 2;
+    w[0] = 0.5;
+    idx[1] = (i + 1) / 2;
+    w[1] = 0.5;
+    return 2;
+}
+
+void or_prolong_add_raw(int nc, const double *e, int n, double *x)
+{
+#pragma omp parallel for schedule(static)
+    for (int k = 1; k <= n - 2; k++)
+        for (int j = 1; j <= n - 2; j++)
+            for (int i = 1; i <= n - 2; i++) {
+                int ii[2], jj[2], kk[2];
+                double wi[2], wj[2], wk[2];
+                int ni = interp_1d(i, ii, wi), nj = interp_1d(j, jj, wj), nk = interp_1d(k, kk, wk);
+                double acc = 0.0;
+                for (int c = 0; c < nk; c++)
+                    for (int b = 0; b < nj; b++)
+                        for (int a = 0; a < ni; a++)
+                            acc += wi[a] * wj[b] * wk[c] * val(nc, e, ii[a], jj[b], kk[c]);
+                x[vid(n, i, j, k)] += acc;
+            }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Chebyshev smoother preconditioned by Jacobi (the smoother of Sec. 4.3 and */
+/* of the PETSc option examples in Sec. 3.3).  Chebyshev acceleration on    */
+/* D^-1 A over the interval [lo, hi], following the published three-term    */
+/* recurrence (Saad, Iterative Methods for Sparse Linear Systems, 2nd ed.,  */
+/* Alg. 12.1):                                                              */
+/*   theta=(hi+lo)/2, delta=(hi-lo)/2, sigma=theta/delta                     */
+/*   r0 = b - A x0, d0 = D^-1 r0 / theta, rho0 = 1/sigma                     */
+/*   x_{j+1} = x_j + d_j;  r_{j+1} = r_j - A d_j;                            */
+/*   rho_{j+1} = 1/(2 sigma - rho_j);                                        */
+/*   d_{j+1} = rho_{j+1} rho_j d_j + (2 rho_{j+1}/delta) D^-1 r_{j+1}        */
+/* degree steps in total; x0 = 0 when x0_zero is set (r0 = b, no matvec).   */
+/* work must hold 4 vertex vectors.                                         */
+/* ------------------------------------------------------------------------ */
+void or_cheb_raw(int n, const double *kx, const double *ky, const double *kz, int degree,
+                 double lo, double hi, const double *b, double *x, int x0_zero, double *work)
+{
+    size_t nv = nvert(n);
+    double *r = work, *d = work + nv, *t = work + 2 * nv, *dg = work + 3 * nv;
+    double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+    or_diag_raw(n, kx, ky, kz, dg);
+    if (x0_zero) {
+        memset(x, 0, sizeof(double) * nv);
+        for (size_t p = 0; p < nv; p++)
+            r[p] = b[p];
+    } else {
+        or_apply_raw(n, kx, ky, kz, x, t);
+        for (size_t p = 0; p < nv; p++)
+            r[p] = b[p] - t[p];
+    }
+    for (size_t p = 0; p < nv; p++)
+        d[p] = dg[p] > 0.0 ? r[p] / dg[p] / theta : 0.0;
+    double rho = 1.0 / sigma;
+    for (int j = 0; j < degree; j++) {
+        for (size_t p = 0; p < nv; p++)
+            x[p] += d[p];
+        if (j + 1 < degree) {
+            or_apply_raw(n, kx, ky, kz, d, t);
+            for (size_t p = 0; p < nv; p++)
+                r[p] -= t[p];
+            double rho_new = 1.0 / (2.0 * sigma - rho);
+            for (size_t p = 0; p < nv; p++)
+                d[p] = rho_new * rho * d[p] + (2.0 * rho_new / delta) * (dg[p] > 0.0 ? r[p] / dg[p] : 0.0);
+            rho = rho_new;
+        }
+    }
+    /* boundary entries stay zero */
+    for (int k = 0; k < n; k++)
+        for (int j = 0; j < n; j++)
+            for (int i = 0; i < n; i++)
+                if (!interior(n, i, j, k))
+                    x[vid(n, i, j, k)] = 0.0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dense assembly and Cholesky factorization of the coarsest operator.      */
+/* The coarsest level is solved exactly (Sec. 1 and Sec. 3.3.1 use LU; A   */
+/* is symmetric positive definite here, so Cholesky L L^T).                 */
+/* Unknown numbering: interior vertices in C order, x fastest.              */
+/* ------------------------------------------------------------------------ */
+static int unk(int n, int i, int j, int k) { return ((k - 1) * (n - 2) + (j - 1)) * (n - 2) + (i - 1); }
+
+void or_assemble_dense_raw(int n, const double *kx, const double *ky, const double *kz, double *A)
+{
+    int m = (n - 2) * (n - 2) * (n - 2);
+    double s = (double)(n - 1) * (double)(n - 1);
+    memset(A, 0, sizeof(double) * (size_t)m * m);
+    for (int k = 1; k <= n - 2; k++)
+        for (int j = 1; j <= n - 2; j++)
+            for (int i = 1; i <= n - 2; i++) {
+                int p = unk(n, i, j, k);
+                /* the six links of p: coefficient and neighbour */
+                double kf[6] = {kx[xid(n, i - 1, j, k)], kx[xid(n, i, j, k)], ky[yid(n, i, j - 1, k)],
+                                ky[yid(n, i, j, k)],     kz[zid(n, i, j, k - 1)], kz[zid(n, i, j, k)]};
+                int nb[6][3] = {{i - 1, j, k}, {i + 1, j, k}, {i, j - 1, k},
+                                {i, j + 1, k}, {i, j, k - 1}, {i, j, k + 1}};
+                for (int f = 0; f < 6; f++) {
+                    A[(size_t)p * m + p] += s * kf[f];
+                    if (interior(n, nb[f][0], nb[f][1], nb[f][2]))
+                        A[(size_t)p * m + unk(n, nb[f][0], nb[f][1], nb[f][2])] -= s * kf[f];
+                }
+            }
+}
+
+/* In-place Cholesky: on return the lower triangle of A holds L.  Returns 0, */
+/* or -1 when a pivot is not positive (A not SPD).                          */
+int or_cholesky_raw(int m, double *A)
+{
+    for (int j = 0; j < m; j++) {
+        double dsum = A[(size_t)j * m + j];
+        for (int c = 0; c < j; c++)
+            dsum -= A[(size_t)j * m + c] * A[(size_t)j * m + c];
+        if (!(dsum > 0.0))
+            return -1;
+        double ljj = sqrt(dsum);
+        A[(size_t)j * m + j] = ljj;
+        for (int r = j + 1; r < m; r++) {
+            double s = A[(size_t)r * m + j];
+            for (int c = 0; c < j; c++)
+                s -= A[(size_t)r * m + c] * A[(size_t)j * m + c];
+            A[(size_t)r * m + j] = s / ljj;
+        }
+    }
+    return 0;
+}
+
+/* Solve L L^T y = rhs with the factor from or_cholesky_raw (in place on y). */
+void or_chol_solve_raw(int m, const double *L, double *y)
+{
+    for (int r = 0; r < m; r++) { /* forward: L w = rhs */
+        double s = y[r];
+        for (int c = 0; c < r; c++)
+            s -= L[(size_t)r * m + c] * y[c];
+        y[r] = s / L[(size_t)r * m + r];
+    }
+    for (int r = m - 1; r >= 0; r--) { /* backward: L^T y = w */
+        double s = y[r];
+        for (int c = r + 1; c < m; c++)
+            s -= L[(size_t)c * m + r] * y[c];
+        y[r] = s / L[(size_t)r * m + r];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Hierarchy (Sec. 2.1.1: per level an operator, a smoother, R and P; an    */
+/* exact solver on the coarsest level).  Coarsening factor 2 (Sec. 1):      */
+/* N_{l+1} = (N_l - 1)/2 + 1, coarse vertex I sits on fine vertex 2I.       */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int n;
+    double *kx, *ky, *kz;
+    double *x, *b, *r, *work; /* work: 4 vectors for the smoother */
+} or_level;
+
+typedef struct {
+    int levels, degree, rule;
+    double lo, hi;
+    or_level lv[OR_MAX_LEVELS];
+    int m;       /* unknowns on the coarsest level */
+    double *chol; /* m x m, lower triangle = L */
+} or_hier;
+
+enum { OR_OK = 0, OR_ERR_ARG = 1, OR_ERR_DIMS = 2, OR_ERR_COEFF = 3, OR_ERR_NOMEM = 4,
+       OR_ERR_NOT_CONVERGED = 6, OR_ERR_BREAKDOWN = 7 };
+
+void or_destroy(void *hp)
+{
+    or_hier *H = (or_hier *)hp;
+    if (!H)
+        return;
+    for (int l = 0; l < H->levels; l++) {
+        free(H->lv[l].kx);
+        free(H->lv[l].ky);
+        free(H->lv[l].kz);
+        free(H->lv[l].x);
+        free(H->lv[l].b);
+        free(H->lv[l].r);
+        free(H->lv[l].work);
+    }
+    free(H->chol);
+    free(H);
+}
+
+int or_create(int n, int levels, int degree, double lo, double hi, int rule, const double *kx,
+              const double *ky, const double *kz, void **out)
+{
+    *out = NULL;
+    if (n < 3 || levels < 1 || levels > OR_MAX_LEVELS || degree < 1 || !(lo > 0.0) || !(hi > lo) ||
+        rule < 0 || rule > 1)
+        return OR_ERR_ARG;
+    if ((n - 1) % (1 << (levels - 1)) != 0)
+        return OR_ERR_DIMS;
+    int ncoarse = (n - 1) / (1 << (levels - 1)) + 1;
+    if (ncoarse < 3)
+        return OR_ERR_DIMS;
+    int m = (ncoarse - 2) * (ncoarse - 2) * (ncoarse - 2);
+    if (m > OR_MAX_COARSE)
+        return OR_ERR_DIMS;
+    /* coefficients must be positive and finite on every active link (a link
+     * is active when one of its end points is interior; the values on links
+     * between two boundary vertices are never read) */
+    for (int k = 1; k <= n - 2; k++)
+        for (int j = 1; j <= n - 2; j++)
+            for (int i = 0; i <= n - 2; i++) {
+                double a = kx[xid(n, i, j, k)], b = ky[yid(n, j, i, k)], c = kz[zid(n, j, k, i)];
+                if (!(a > 0.0) || !isfinite(a) || !(b > 0.0) || !isfinite(b) || !(c > 0.0) ||
+                    !isfinite(c))
+                    return OR_ERR_COEFF;
+            }
+    or_hier *H = (or_hier *)calloc(1, sizeof(or_hier));
+    if (!H)
+        return OR_ERR_NOMEM;
+    H->levels = levels;
+    H->degree = degree;
+    H->rule = rule;
+    H->lo = lo;
+    H->hi = hi;
+    int nl = n;
+    for (int l = 0; l < levels; l++) {
+        or_level *L = &H->lv[l];
+        L->n = nl;
+        size_t nv = nvert(nl), nfl = (size_t)nl * nl * (nl - 1);
+        L->kx = (double *)malloc(sizeof(double) * nfl);
+        L->ky = (double *)malloc(sizeof(double) * nfl);
+        L->kz = (double *)malloc(sizeof(double) * nfl);
+        L->x = (double *)calloc(nv, sizeof(double));
+        L->b = (double *)calloc(nv, sizeof(double));
+        L->r = (double *)calloc(nv, sizeof(double));
+        L->work = (double *)calloc(4 * nv, sizeof(double));
+        if (!L->kx || !L->ky || !L->kz || !L->x || !L->b || !L->r || !L->work) {
+            H->levels = l + 1;
+            or_destroy(H);
+            return OR_ERR_NOMEM;
+        }
+        if (l == 0) {
+            memcpy(L->kx, kx, sizeof(double) * nfl);
+            memcpy(L->ky, ky, sizeof(double) * nfl);
+            memcpy(L->kz, kz, sizeof(double) * nfl);
+        } else {
+            or_level *F = &H->lv[l - 1];
+            or_coarsen_k_raw(F->n, F->kx, F->ky, F->kz, nl, L->kx, L->ky, L->kz, rule);
+        }
+        nl = (nl - 1) / 2 + 1;
+    }
+    or_level *C = &H->lv[levels - 1];
+    H->m = m;
+    H->chol = (double *)malloc(sizeof(double) * (size_t)m * m);
+    if (!H->chol) {
+        or_destroy(H);
+        return OR_ERR_NOMEM;
+    }
+    or_assemble_dense_raw(C->n, C->kx, C->ky, C->kz, H->chol);
+    if (or_cholesky_raw(m, H->chol) != 0) {
+        or_destroy(H);
+        return OR_ERR_COEFF;
+    }
+    *out = H;
+    return OR_OK;
+}
+
+int or_level_n(void *hp, int l)
+{
+    or_hier *H = (or_hier *)hp;
+    return (l >= 0 && l < H->levels) ? H->lv[l].n : -1;
+}
+
+int or_get_k(void *hp, int l, double *kx, double *ky, double *kz)
+{
+    or_hier *H = (or_hier *)hp;
+    if (l < 0 || l >= H->levels)
+        return OR_ERR_ARG;
+    int n = H->lv[l].n;
+    size_t nf = (size_t)n * n * (n - 1);
+    memcpy(kx, H->lv[l].kx, sizeof(double) * nf);
+    memcpy(ky, H->lv[l].ky, sizeof(double) * nf);
+    memcpy(kz, H->lv[l].kz, sizeof(double) * nf);
+    return OR_OK;
+}
+
+/* exact coarsest solve: x = A_c^-1 b on the coarsest level */
+int or_coarse_solve(void *hp, const double *b, double *x)
+{
+    or_hier *H = (or_hier *)hp;
+    int n = H->lv[H->levels - 1].n;
+    double *y = (double *)malloc(sizeof(double) * (size_t)H->m);
+    if (!y)
+        return OR_ERR_NOMEM;
+    for (int k = 1; k <= n - 2; k++)
+        for (int j = 1; j <= n - 2; j++)
+            for (int i = 1; i <= n - 2; i++)
+                y[unk(n, i, j, k)] = b[vid(n, i, j, k)];
+    or_chol_solve_raw(H->m, H->chol, y);
+    memset(x, 0, sizeof(double) * nvert(n));
+    for (int k = 1; k <= n - 2; k++)
+        for (int j = 1; j <= n - 2; j++)
+            for (int i = 1; i <= n - 2; i++)
+                x[vid(n, i, j, k)] = y[unk(n, i, j, k)];
+    free(y);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* V-cycle: Alg. 1 (two-level multigrid) applied recursively, one cycle,   */
+/* zero initial guess, pre- and post-smoothing by one Chebyshev-Jacobi      */
+/* polynomial each, exact solve on the coarsest level.                      */
+/*   V(l, b): l = last -> A_l^-1 b.  Otherwise                               */
+/*     x = Cheb(b, x0 = 0); r = b - A_l x; e = V(l+1, R r);                  */
+/*     x += P e; x = Cheb(b, x0 = x).                                        */
+/* The result is written to H->lv[l].x; b is H->lv[l].b.                    */
+/* ------------------------------------------------------------------------ */
+static int vcycle_level(or_hier *H, int l)
+{
+    or_level *L = &H->lv[l];
+    if (l == H->levels - 1)
+        return or_coarse_solve(H, L->b, L->x);
+    or_level *C = &H->lv[l + 1];
+    or_cheb_raw(L->n, L->kx, L->ky, L->kz, H->degree, H->lo, H->hi, L->b, L->x, 1, L->work);
+    or_apply_raw(L->n, L->kx, L->ky, L->kz, L->x, L->r);
+    size_t nv = nvert(L->n);
+    for (size_t p = 0; p < nv; p++)
+        L->r[p] = L->b[p] - L->r[p];
+    or_restrict_raw(L->n, L->r, C->n, C->b);
+    int st = vcycle_level(H, l + 1);
+    if (st != OR_OK)
+        return st;
+    or_prolong_add_raw(C->n, C->x, L->n, L->x);
+    or_cheb_raw(L->n, L->kx, L->ky, L->kz, H->degree, H->lo, H->hi, L->b, L->x, 0, L->work);
+    return OR_OK;
+}
+
+/* z = B r, with B the V-cycle preconditioner on the finest level. */
+int or_vcycle(void *hp, const double *r, double *z)
+{
+    or_hier *H = (or_hier *)hp;
+    or_level *L = &H->lv[0];
+    size_t nv = nvert(L->n);
+    for (int k = 0; k < L->n; k++)
+        for (int j = 0; j < L->n; j++)
+            for (int i = 0; i < L->n; i++)
+                L->b[vid(L->n, i, j, k)] = val(L->n, r, i, j, k);
+    int st = vcycle_level(H, 0);
+    memcpy(z, L->x, sizeof(double) * nv);
+    return st;
+}
+
+/* Smoother on an arbitrary level (exposed for the kernel-level checks). */
+int or_smooth(void *hp, int l, const double *b, double *x, int x0_zero)
+{
+    or_hier *H = (or_hier *)hp;
+    if (l < 0 || l >= H->levels)
+        return OR_ERR_ARG;
+    or_level *L = &H->lv[l];
+    or_cheb_raw(L->n, L->kx, L->ky, L->kz, H->degree, H->lo, H->hi, b, x, x0_zero, L->work);
+    return OR_OK;
+}
+
+int or_apply(void *hp, int l, const double *u, double *out)
+{
+    or_hier *H = (or_hier *)hp;
+    if (l < 0 || l >= H->levels)
+        return OR_ERR_ARG;
+    or_level *L = &H->lv[l];
+    or_apply_raw(L->n, L->kx, L->ky, L->kz, u, out);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dot products over the interior, summed per z-plane and then in order.    */
+/* ------------------------------------------------------------------------ */
+static double dot_int(int n, const double *a, const double *b)
+{
+    double *plane = (double *)calloc((size_t)n, sizeof(double));
+#pragma omp parallel for schedule(static)
+    for (int k = 1; k <= n - 2; k++) {
+        double s = 0.0;
+        for (int j = 1; j <= n - 2; j++)
+            for (int i = 1; i <= n - 2; i++)
+                s += a[vid(n, i, j, k)] * b[vid(n, i, j, k)];
+        plane[k] = s;
+    }
+    double s = 0.0;
+    for (int k = 1; k <= n - 2; k++)
+        s += plane[k];
+    free(plane);
+    return s;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Preconditioned conjugate gradients (Sec. 2.1: CG as the Krylov method,   */
+/* the V-cycle as preconditioner).  Stop when ||r||_2 <= rtol ||b||_2 (the  */
+/* relative reduction of the initial residual used in Sec. 4.2 and 4.3,     */
+/* with x0 = 0).  its counts the updates of x.  On exit relres is the       */
+/* recursive residual ratio and relres_true = ||b - A x|| / ||b||.          */
+/* ------------------------------------------------------------------------ */
+int or_pcg(void *hp, const double *f, double *x, double rtol, int max_it, int *its,
+           double *relres, double *relres_true)
+{
+    or_hier *H = (or_hier *)hp;
+    or_level *L = &H->lv[0];
+    int n = L->n;
+    size_t nv = nvert(n);
+    double *b = (double *)calloc(nv, sizeof(double));
+    double *r = (double *)calloc(nv, sizeof(double));
+    double *z = (double *)calloc(nv, sizeof(double));
+    double *p = (double *)calloc(nv, sizeof(double));
+    double *q = (double *)calloc(nv, sizeof(double));
+    if (!b || !r || !z || !p || !q) {
+        free(b); free(r); free(z); free(p); free(q);
+        return OR_ERR_NOMEM;
+    }
+    int st = OR_OK;
+    for (int k = 0; k < n; k++)
+        for (int j = 0; j < n; j++)
+            for (int i = 0; i < n; i++)
+                b[vid(n, i, j, k)] = val(n, f, i, j, k);
+    memset(x, 0, sizeof(double) * nv);
+    memcpy(r, b, sizeof(double) * nv);
+    double bnorm = sqrt(dot_int(n, b, b));
+    *its = 0;
+    *relres = 0.0;
+    *relres_true = 0.0;
+    if (bnorm == 0.0)
+        goto done;
+    if (!isfinite(bnorm)) {
+        st = OR_ERR_ARG;
+        goto done;
+    }
+    or_vcycle(H, r, z);
+    memcpy(p, z, sizeof(double) * nv);
+    double rho = dot_int(n, r, z);
+    *relres = 1.0;
+    st = OR_ERR_NOT_CONVERGED;
+    for (int it = 0; it < max_it; it++) {
+        or_apply_raw(n, L->kx, L->ky, L->kz, p, q);
+        double pq = dot_int(n, p, q);
+        if (!(pq > 0.0) || !isfinite(pq)) {
+            st = OR_ERR_BREAKDOWN;
+            break;
+        }
+        double alpha = rho / pq;
+        for (size_t i = 0; i < nv; i++) {
+            x[i] += alpha * p[i];
+            r[i] -= alpha * q[i];
+        }
+        *its = it + 1;
+        double rnorm = sqrt(dot_int(n, r, r));
+        *relres = rnorm / bnorm;
+        if (!isfinite(rnorm)) {
+            st = OR_ERR_BREAKDOWN;
+            break;
+        }
+        if (rnorm <= rtol * bnorm) {
+            st = OR_OK;
+            break;
+        }
+        or_vcycle(H, r, z);
+        double rho_new = dot_int(n, r, z);
+        double beta = rho_new / rho;
+        rho = rho_new;
+        for (size_t i = 0; i < nv; i++)
+            p[i] = z[i] + beta * p[i];
+    }
+    /* true residual */
+    or_apply_raw(n, L->kx, L->ky, L->kz, x, q);
+    for (size_t i = 0; i < nv; i++)
+        q[i] = b[i] - q[i];
+    *relres_true = sqrt(dot_int(n, q, q)) / bnorm;
+done:
+    free(b); free(r); free(z); free(p); free(q);
+    return st;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Adjoint gradient.  With A(k) phi = f and a loss L(phi):                  */
+/*   A lambda = dL/dphi          (A is symmetric, so A^T = A)               */
+/*   dL/dk_f  = -h^-2 (lambda_p - lambda_q)(phi_p - phi_q)                   */
+/*   dL/dtheta_f = k_f dL/dk_f   with theta = ln k                          */
+/* for every link f = (p,q) with at least one interior end point; a         */
+/* boundary end point contributes zero values.  Links between two boundary  */
+/* vertices get 0.  lambda (may be NULL) receives the adjoint solution.     */
+/* The coarse hierarchy only preconditions the solve and is not             */
+/* differentiated.                                                          */
+/* ------------------------------------------------------------------------ */
+int or_adjoint_gradient(void *hp, const double *phi, const double *dl_dphi, double *gx, double *gy,
+                        double *gz, double *lambda, double rtol, int max_it, int *its)
+{
+    or_hier *H = (or_hier *)hp;
+    or_level *L = &H->lv[0];
+    int n = L->n;
+    double s = (double)(n - 1) * (double)(n - 1);
+    double *lam = (double *)calloc(nvert(n), sizeof(double));
+    if (!lam)
+        return OR_ERR_NOMEM;
+    double rr, rt;
+    int st = or_pcg(H, dl_dphi, lam, rtol, max_it, its, &rr, &rt);
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < n; k++)
+        for (int j = 0; j < n; j++)
+            for (int i = 0; i < n - 1; i++) {
+                double g = 0.0;
+                if (interior(n, i, j, k) || interior(n, i + 1, j, k))
+                    g = -s * (val(n, lam, i, j, k) - val(n, lam, i + 1, j, k)) *
+                        (val(n, phi, i, j, k) - val(n, phi, i + 1, j, k));
+                gx[xid(n, i, j, k)] = g != 0.0 ? L->kx[xid(n, i, j, k)] * g : 0.0;
+            }
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < n; k++)
+        for (int j = 0; j < n - 1; j++)
+            for (int i = 0; i < n; i++) {
+                double g = 0.0;
+                if (interior(n, i, j, k) || interior(n, i, j + 1, k))
+                    g = -s * (val(n, lam, i, j, k) - val(n, lam, i, j + 1, k)) *
+                        (val(n, phi, i, j, k) - val(n, phi, i, j + 1, k));
+                gy[yid(n, i, j, k)] = g != 0.0 ? L->ky[yid(n, i, j, k)] * g : 0.0;
+            }
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < n - 1; k++)
+        for (int j = 0; j < n; j++)
+            for (int i = 0; i < n; i++) {
+                double g = 0.0;
+                if (interior(n, i, j, k) || interior(n, i, j, k + 1))
+                    g = -s * (val(n, lam, i, j, k) - val(n, lam, i, j, k + 1)) *
+                        (val(n, phi, i, j, k) - val(n, phi, i, j, k + 1));
+                gz[zid(n, i, j, k)] = g != 0.0 ? L->kz[zid(n, i, j, k)] * g : 0.0;
+            }
+    if (lambda)
+        memcpy(lambda, lam, sizeof(double) * nvert(n));
+    free(lam);
+    return st;
+}

@@ -1,0 +1,159 @@
+/*
+ * gmg.h -- C ABI of the MI355X (gfx950) geometric-multigrid-preconditioned
+ * conjugate-gradient solver for the variable-coefficient diffusion problem
+ *
+ *        -div(k grad phi) = f        on the unit cube, phi = 0 on the boundary
+ *
+ * (Eq. 2 of Sec. 1, discretized by the 7-point finite-difference stencil of
+ * the structured-grid Laplace workload of Sec. 4.1).  The preconditioner is one
+ * multigrid V-cycle (Alg. 1 of Sec. 2.1.1 applied recursively, factor-2
+ * coarsening as in Sec. 1) with Chebyshev-Jacobi smoothing and re-discretized
+ * coarse operators; the coarsest level is solved exactly (Sec. 1, Sec. 3.3.1).
+ * Coarse levels at or below a size threshold are agglomerated onto one
+ * workgroup of a persistent kernel: the in-device counterpart of moving coarse
+ * levels onto a smaller communicator (Sec. 3.1, Fig. 1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  * N vertices per side, h = 1/(N-1).  Arrays are C order (z, y, x), x fastest:
+ *      vertex vectors  (N, N, N)      -- boundary entries are ignored on input
+ *                                        and written as 0 on output
+ *      kx              (N, N, N-1)    link (i,j,k)-(i+1,j,k)
+ *      ky              (N, N-1, N)    link (i,j,k)-(i,j+1,k)
+ *      kz              (N-1, N, N)    link (i,j,k)-(i,j,k+1)
+ *    A link is active when one of its end points is interior; values on the
+ *    other links are never read.
+ *  * The operator is (A u)_p = h^-2 sum_{links f of p} k_f (u_p - u_q(f)).
+ *  * Every array pointer is a DEVICE pointer (e.g. a torch tensor's data_ptr()),
+ *    FP64, contiguous, owned by the caller.  The library copies what it keeps.
+ *  * All work is enqueued on the handle's HIP stream (hipStream_t passed as
+ *    void*; NULL = the default stream).  Calls return after their results are
+ *    complete on that stream unless stated otherwise.
+ *  * Nothing aborts and no exception crosses the ABI: every call returns a
+ *    gmg_status; gmg_last_error() gives a per-handle message.
+ *  * A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef GMG_H
+#define GMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gmg_handle gmg_handle;
+
+typedef enum {
+    GMG_OK = 0,
+    GMG_ERR_ARG = 1,           /* null pointer, bad option value, bad level index */
+    GMG_ERR_DIMS = 2,          /* N / levels inconsistent, coarsest level too large */
+    GMG_ERR_COEFF = 3,         /* a k on an active link is <= 0, NaN or Inf */
+    GMG_ERR_NOMEM = 4,         /* device allocation failed */
+    GMG_ERR_HIP = 5,           /* a HIP runtime call or kernel launch failed */
+    GMG_ERR_NOT_CONVERGED = 6, /* max_it reached; x holds the last iterate */
+    GMG_ERR_BREAKDOWN = 7      /* p.Ap <= 0 or a non-finite residual; x holds the last iterate */
+} gmg_status;
+
+typedef enum { GMG_FP64 = 0, GMG_MIXED = 1 } gmg_precision;
+
+/* Rule for the coarse link coefficients of the re-discretized coarse operators
+ * (the paper uses re-discretized coarse operators, Sec. 4.3, without giving
+ * the averaging).  A coarse link spans two fine links in series; the 3x3 lines
+ * around it are weighted by (1/4,1/2,1/4) x (1/4,1/2,1/4).  Along the link the
+ * two fine values p, q combine as (p+q)/2 (ARITHMETIC) or 2pq/(p+q) (HARMONIC). */
+typedef enum { GMG_COARSE_ARITHMETIC = 0, GMG_COARSE_HARMONIC = 1 } gmg_coarse_rule;
+
+typedef struct {
+    int32_t n;              /* vertices per side; n >= 3 and (n-1) % 2^(levels-1) == 0 */
+    int32_t levels;         /* >= 1; coarsest level has at most 4096 interior unknowns */
+    int32_t cheb_degree;    /* Chebyshev steps per smoothing (pre and post), 1..8; default 2 */
+    double cheb_lo;         /* Chebyshev interval of D^-1 A, default [0.25, 2.0] */
+    double cheb_hi;
+    int32_t switch_n;       /* 0: grid launches on every level.  Else levels with
+                               N_l <= switch_n run inside one persistent kernel */
+    int32_t persistent_wgs; /* workgroups of the persistent kernel (1) */
+    int32_t precision;      /* gmg_precision.  MIXED: V-cycle in FP32 with BF16 link
+                               coefficients (round-to-nearest-even from FP64), outer
+                               PCG, dot products and coarsest Cholesky in FP64 */
+    int32_t coarse_rule;    /* gmg_coarse_rule, default ARITHMETIC */
+    int32_t coeff_is_log;   /* 1: kx/ky/kz hold ln k (natural log) instead of k */
+    int32_t check_every;    /* host reads the convergence flag every this many PCG
+                               iterations (0 = automatic by grid size) */
+} gmg_options;
+
+typedef struct {
+    int32_t iterations;   /* PCG iterations (updates of x) */
+    int32_t restarts;     /* MIXED: restarts from the true residual */
+    double rel_res;       /* recursive ||r|| / ||f|| at exit */
+    double rel_res_true;  /* ||f - A x|| / ||f|| at exit, FP64 */
+    double setup_ms;      /* gmg_create / gmg_set_coefficients wall time */
+    double solve_ms;      /* device time of the solve (HIP events on the stream) */
+} gmg_info;
+
+/* Fill *opt with the defaults above for n vertices per side and
+ * levels = log2(n-1) (coarsest 3^3), FP64, no persistent switch. */
+void gmg_default_options(gmg_options *opt, int32_t n);
+
+/* Build the hierarchy: copy k (device, FP64, face shapes) into the library's
+ * padded layout, derive the coarse coefficients level by level, the BF16
+ * copies (MIXED), and the Cholesky factor of the dense coarsest operator.
+ * Allocates every device buffer the solver needs (no allocation happens in
+ * gmg_solve).  On success *out owns them until gmg_destroy. */
+gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky, const double *kz,
+                      void *stream, gmg_handle **out);
+
+/* Replace the coefficients (same N, levels, options); rebuilds every derived
+ * level and the coarsest factor without reallocating. */
+gmg_status gmg_set_coefficients(gmg_handle *h, const double *kx, const double *ky, const double *kz);
+
+/* Change the stream used by later calls. */
+gmg_status gmg_set_stream(gmg_handle *h, void *stream);
+
+/* PCG solve of A x = f (Sec. 2.1, CG preconditioned by one V-cycle).  Stops
+ * when ||r||_2 <= rtol ||f||_2 (recursive residual; FP64 mode) or when the
+ * FP64 true residual also passes (MIXED: otherwise r is replaced by f - A x
+ * and CG restarts).  x0 may be NULL (zero initial guess).  f, x, x0: (N,N,N).
+ * Returns GMG_OK, GMG_ERR_NOT_CONVERGED or GMG_ERR_BREAKDOWN with x written
+ * in every case; info may be NULL. */
+gmg_status gmg_solve(gmg_handle *h, const double *f, double *x, const double *x0, double rtol,
+                     int32_t max_it, gmg_info *info);
+
+/* Adjoint gradient.  Solves A lambda = dl_dphi with the same PCG (A is
+ * symmetric), then for every active link f = (p,q)
+ *     g_f = dL/d(ln k_f) = -h^-2 k_f (lambda_p - lambda_q)(phi_p - phi_q)
+ * (boundary values are 0); links between two boundary vertices get 0.
+ * phi, dl_dphi, lambda: (N,N,N); g_x, g_y, g_z: face shapes.  lambda may be
+ * NULL.  Status as gmg_solve. */
+gmg_status gmg_adjoint_gradient(gmg_handle *h, const double *phi, const double *dl_dphi, double *g_x,
+                                double *g_y, double *g_z, double *lambda, double rtol, int32_t max_it,
+                                gmg_info *info);
+
+/* ---- test hooks: each runs one step of the path on level `level`, in the
+ * handle's V-cycle precision (FP32/BF16 in MIXED mode, with FP64 in and out).
+ * Vectors are (N_l, N_l, N_l) device arrays. */
+int32_t gmg_level_n(const gmg_handle *h, int32_t level);   /* N_l, or -1 */
+/* y = A_l x (level 0 with use_fp64 = 1 is the outer FP64 operator). */
+gmg_status gmg_apply_operator(gmg_handle *h, int32_t level, int32_t use_fp64, const double *x, double *y);
+/* x <- Chebyshev-Jacobi smoothing of A_l x = b from x (x0_zero: from 0). */
+gmg_status gmg_debug_smooth(gmg_handle *h, int32_t level, const double *b, double *x, int32_t x0_zero);
+/* b_c = R (b - A_l x) on level+1 (full weighting). */
+gmg_status gmg_debug_residual_restrict(gmg_handle *h, int32_t level, const double *b, const double *x,
+                                       double *b_coarse);
+/* x += P e, e on level+1 (trilinear). */
+gmg_status gmg_debug_prolong(gmg_handle *h, int32_t level, const double *e_coarse, double *x);
+/* x = A_c^-1 b on the coarsest level (FP64 Cholesky). */
+gmg_status gmg_debug_coarse_solve(gmg_handle *h, const double *b, double *x);
+/* z = B r, one V-cycle on level 0 (uses the handle's switch level). */
+gmg_status gmg_debug_vcycle(gmg_handle *h, const double *r, double *z);
+/* Copy level coefficients out in face shapes (MIXED: the BF16 values). */
+gmg_status gmg_get_level_coefficients(gmg_handle *h, int32_t level, double *kx, double *ky, double *kz);
+
+void gmg_destroy(gmg_handle *h);
+const char *gmg_status_string(gmg_status s);
+const char *gmg_last_error(const gmg_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GMG_H */

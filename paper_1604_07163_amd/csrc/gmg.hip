@@ -1,0 +1,972 @@
+// gmg.hip -- host side of the C ABI declared in include/gmg.h.
+//
+// Owns the multigrid hierarchy in HBM, schedules the V-cycle (grid-wide
+// launches on fine levels, one persistent workgroup below the switch size) and
+// drives preconditioned CG with every scalar (alpha, beta, norms, the stop
+// flag) kept on the device.  The host only reads the stop flag every
+// `check_every` iterations; kernels enqueued past convergence return at once.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "gmg.h"
+#include "kernels.hpp"
+
+using gmg::bf16;
+using gmg::ChebCoef;
+using gmg::Lev;
+using gmg::LevBuf;
+using gmg::PcgState;
+using gmg::Tiling;
+
+namespace {
+
+struct LevelHost {
+    int n = 0, pitch = 0;
+    long long plane = 0, nel = 0;  // nel = n * plane elements per array
+    double s = 0;                  // h^-2
+    double *kx64 = nullptr, *ky64 = nullptr, *kz64 = nullptr;
+    bf16 *kx16 = nullptr, *ky16 = nullptr, *kz16 = nullptr;
+    void *b = nullptr, *x = nullptr, *t1 = nullptr;
+    Tiling til{};
+};
+
+}  // namespace
+
+struct gmg_handle {
+    gmg_options opt{};
+    hipStream_t stream = nullptr;
+    int L = 0;
+    LevelHost lv[gmg::MAX_LEVELS];
+    double *F = nullptr, *X = nullptr, *R = nullptr, *P = nullptr, *Q = nullptr;
+    double *partial = nullptr;
+    int npartial = 0;
+    PcgState *st = nullptr;       // device
+    PcgState *st_in = nullptr;    // pinned host (uploads)
+    PcgState *st_out = nullptr;   // pinned host (read-back)
+    double *chol = nullptr;       // coarsest factor, device
+    int m = 0;
+    void *dev_levels = nullptr;   // LevBuf<V,K>[L] on the device
+    int s_persist = 0;            // first level run by the persistent kernel (L-1 if none)
+    bool persist = false;
+    ChebCoef<double> cheb64{};
+    ChebCoef<float> cheb32{};
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::vector<void *> allocs;
+    std::string err;
+    double setup_ms = 0;
+};
+
+namespace {
+
+gmg_status fail(gmg_handle *h, gmg_status s, const std::string &msg) {
+    if (h) h->err = msg;
+    return s;
+}
+
+#define HIPCHK(call)                                                                           \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(h, GMG_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+#define LAUNCHCHK()                                                                            \
+    do {                                                                                       \
+        hipError_t e_ = hipGetLastError();                                                     \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(h, GMG_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e_)); \
+    } while (0)
+#define STCHK(expr)                   \
+    do {                              \
+        gmg_status s_ = (expr);       \
+        if (s_ != GMG_OK) return s_;  \
+    } while (0)
+
+int round_up(int a, int b) { return (a + b - 1) / b * b; }
+unsigned blocks_for(long long n, int nt) { return (unsigned)((n + nt - 1) / nt); }
+
+int target_wgs() {
+    const char *e = getenv("GMG_TARGET_WGS");
+    int v = e ? atoi(e) : 0;
+    return v > 0 ? v : 8192;
+}
+
+Tiling make_tiling(int n) {
+    Tiling t;
+    t.tiles_x = (n - 2) / gmg::TX + 1;  // covers i = 0 .. n-2
+    t.tiles_y = (n - 2 + gmg::TY - 1) / gmg::TY;
+    const int planes = n - 2;
+    int nch = (target_wgs() + t.tiles_x * t.tiles_y - 1) / (t.tiles_x * t.tiles_y);
+    if (nch < 1) nch = 1;
+    if (nch > planes) nch = planes;
+    t.zchunk = (planes + nch - 1) / nch;
+    nch = (planes + t.zchunk - 1) / t.zchunk;
+    t.nblocks = t.tiles_x * t.tiles_y * nch;
+    return t;
+}
+
+template <typename T>
+gmg_status dalloc(gmg_handle *h, T **p, long long count) {
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, (size_t)count * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(h, GMG_ERR_NOMEM, "hipMalloc of " + std::to_string((size_t)count * sizeof(T)) + " bytes failed");
+    }
+    h->allocs.push_back(q);
+    e = hipMemsetAsync(q, 0, (size_t)count * sizeof(T), h->stream);
+    if (e != hipSuccess) return fail(h, GMG_ERR_HIP, "hipMemsetAsync failed");
+    *p = (T *)q;
+    return GMG_OK;
+}
+
+bool mixed(const gmg_handle *h) { return h->opt.precision == GMG_MIXED; }
+
+template <typename K>
+struct KSel;
+template <>
+struct KSel<double> {
+    static const double *x(const LevelHost &l) { return l.kx64; }
+    static const double *y(const LevelHost &l) { return l.ky64; }
+    static const double *z(const LevelHost &l) { return l.kz64; }
+};
+template <>
+struct KSel<bf16> {
+    static const bf16 *x(const LevelHost &l) { return l.kx16; }
+    static const bf16 *y(const LevelHost &l) { return l.ky16; }
+    static const bf16 *z(const LevelHost &l) { return l.kz16; }
+};
+
+template <typename V, typename K>
+Lev<V, K> view(const LevelHost &l) {
+    Lev<V, K> v;
+    v.n = l.n;
+    v.pitch = l.pitch;
+    v.plane = l.plane;
+    v.s = (V)l.s;
+    v.kx = KSel<K>::x(l);
+    v.ky = KSel<K>::y(l);
+    v.kz = KSel<K>::z(l);
+    return v;
+}
+
+template <typename V>
+const ChebCoef<V> &cheb(const gmg_handle *h);
+template <>
+const ChebCoef<double> &cheb<double>(const gmg_handle *h) { return h->cheb64; }
+template <>
+const ChebCoef<float> &cheb<float>(const gmg_handle *h) { return h->cheb32; }
+
+// ------------------------------------------------------------------ smoothing
+// Chebyshev-Jacobi smoothing of A_l x = b_l on the grid path.  The iterate
+// alternates between x and t1 (x_{j+1} overwrites the buffer of x_{j-1});
+// odd degrees end with a copy into x.  `dot_r64` (finest level, post-smoothing
+// only) fuses the partial sums of r.z into the last sweep; returns the number
+// of partials written (0 if none).
+template <typename V, typename K>
+gmg_status smooth_grid(gmg_handle *h, int l, bool from_zero, const double *r64_cvt, const double *dot_r64,
+                       const int *skip, int *nparts) {
+    LevelHost &lh = h->lv[l];
+    const Lev<V, K> L = view<V, K>(lh);
+    const ChebCoef<V> &cc = cheb<V>(h);
+    V *bufs[2] = {(V *)lh.x, (V *)lh.t1};
+    V *b = (V *)lh.b;
+    const dim3 grid(lh.til.nblocks), blk(gmg::NT);
+    int cur, prev;
+    if (nparts) *nparts = 0;
+    if (from_zero) {
+        V *dst = cc.m == 1 ? bufs[0] : bufs[1];
+        if (r64_cvt)
+            gmg::k_cheb_first<V, K, true><<<grid, blk, 0, h->stream>>>(L, lh.til, nullptr, r64_cvt, b, dst, cc.cfirst,
+                                                                        skip);
+        else
+            gmg::k_cheb_first<V, K, false><<<grid, blk, 0, h->stream>>>(L, lh.til, b, nullptr, nullptr, dst, cc.cfirst,
+                                                                         skip);
+        LAUNCHCHK();
+        if (cc.m == 1) return GMG_OK;
+        cur = 1;
+        prev = -1;
+    } else {
+        gmg::k_cheb_step<V, K, 0, false><<<grid, blk, 0, h->stream>>>(L, lh.til, b, bufs[0], nullptr, bufs[1], V(0),
+                                                                        cc.cfirst, nullptr, nullptr, skip);
+        LAUNCHCHK();
+        cur = 1;
+        prev = 0;
+    }
+    for (int j = 1; j < cc.m; ++j) {
+        const int dst = 1 - cur;
+        const bool fuse = dot_r64 && (j == cc.m - 1) && dst == 0;
+        if (prev < 0) {
+            gmg::k_cheb_step<V, K, 1, false><<<grid, blk, 0, h->stream>>>(L, lh.til, b, bufs[cur], nullptr, bufs[dst],
+                                                                            cc.c1[j], cc.c2[j], nullptr, nullptr, skip);
+        } else if (fuse) {
+            gmg::k_cheb_step<V, K, 2, true><<<grid, blk, 0, h->stream>>>(L, lh.til, b, bufs[cur], bufs[prev], bufs[dst],
+                                                                           cc.c1[j], cc.c2[j], dot_r64, h->partial, skip);
+            if (nparts) *nparts = lh.til.nblocks;
+        } else {
+            gmg::k_cheb_step<V, K, 2, false><<<grid, blk, 0, h->stream>>>(L, lh.til, b, bufs[cur], bufs[prev], bufs[dst],
+                                                                            cc.c1[j], cc.c2[j], nullptr, nullptr, skip);
+        }
+        LAUNCHCHK();
+        prev = cur;
+        cur = dst;
+    }
+    if (cur != 0) {
+        gmg::k_cast<V, V><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(lh.nel, bufs[1], bufs[0], skip);
+        LAUNCHCHK();
+    }
+    if (dot_r64 && nparts && *nparts == 0) {
+        gmg::k_dot<V><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(lh.nel, dot_r64, bufs[0], h->partial, skip);
+        LAUNCHCHK();
+        *nparts = gmg::NB_FLAT;
+    }
+    return GMG_OK;
+}
+
+template <typename V, typename K>
+gmg_status coarse_part(gmg_handle *h, const int *skip) {
+    const int last = h->L - 1;
+    if (h->persist) {
+        gmg::k_persistent<V, K><<<1, gmg::NT_PERSIST, 0, h->stream>>>(
+            (const LevBuf<V, K> *)h->dev_levels, h->s_persist, last, cheb<V>(h), h->chol, h->m, skip);
+    } else {
+        const LevelHost &c = h->lv[last];
+        gmg::k_coarse_solve<V><<<1, 256, 0, h->stream>>>(c.n, c.pitch, c.plane, h->m, h->chol, (const V *)c.b,
+                                                          (V *)c.x, skip);
+    }
+    LAUNCHCHK();
+    return GMG_OK;
+}
+
+// z = B r: one V-cycle on the FP64 residual r (= h->R).  The result is in
+// lv[0].x (FP64 or FP32).  With want_dot, partial sums of r.z are left in
+// h->partial and their count in *nparts.
+template <typename V, typename K>
+gmg_status vcycle(gmg_handle *h, const int *skip, bool want_dot, int *nparts) {
+    const int last = h->L - 1;
+    const bool mx = mixed(h);
+    if (nparts) *nparts = 0;
+    if (last == 0) {  // the finest level is the coarsest: exact solve
+        LevelHost &l0 = h->lv[0];
+        if (mx) {
+            gmg::k_cast<double, V><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(l0.nel, h->R, (V *)l0.b, skip);
+            LAUNCHCHK();
+        }
+        STCHK((coarse_part<V, K>(h, skip)));
+        if (want_dot) {
+            gmg::k_dot<V><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(l0.nel, h->R, (const V *)l0.x, h->partial, skip);
+            LAUNCHCHK();
+            *nparts = gmg::NB_FLAT;
+        }
+        return GMG_OK;
+    }
+    const int s = h->s_persist;  // levels 0..s-1 on the grid path
+    for (int l = 0; l < s; ++l) {
+        STCHK((smooth_grid<V, K>(h, l, true, (l == 0 && mx) ? h->R : nullptr, nullptr, skip, nullptr)));
+        LevelHost &f = h->lv[l], &c = h->lv[l + 1];
+        const long long mc = (long long)(c.n - 2) * (c.n - 2) * (c.n - 2);
+        gmg::k_resid_restrict<V, K><<<blocks_for(mc, 256), 256, 0, h->stream>>>(
+            view<V, K>(f), (const V *)f.b, (const V *)f.x, c.n, c.pitch, c.plane, (V *)c.b, skip);
+        LAUNCHCHK();
+    }
+    STCHK((coarse_part<V, K>(h, skip)));
+    for (int l = s - 1; l >= 0; --l) {
+        LevelHost &f = h->lv[l], &c = h->lv[l + 1];
+        const long long mf = (long long)(f.n - 2) * (f.n - 2) * (f.n - 2);
+        gmg::k_prolong_add<V><<<blocks_for(mf, 256), 256, 0, h->stream>>>(f.n, f.pitch, f.plane, (const V *)c.x,
+                                                                          c.pitch, c.plane, (V *)f.x, skip);
+        LAUNCHCHK();
+        STCHK((smooth_grid<V, K>(h, l, false, nullptr, (l == 0 && want_dot) ? h->R : nullptr, skip,
+                                 l == 0 ? nparts : nullptr)));
+    }
+    return GMG_OK;
+}
+
+gmg_status vcycle_any(gmg_handle *h, const int *skip, bool want_dot, int *nparts) {
+    return mixed(h) ? vcycle<float, bf16>(h, skip, want_dot, nparts) : vcycle<double, double>(h, skip, want_dot, nparts);
+}
+
+gmg_status finalize(gmg_handle *h, int count, int stage) {
+    gmg::k_finalize<<<1, 256, 0, h->stream>>>(h->partial, count, stage, h->st);
+    LAUNCHCHK();
+    return GMG_OK;
+}
+
+gmg_status dot64(gmg_handle *h, const double *a, const double *b, int stage, const int *skip) {
+    gmg::k_dot<double><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(h->lv[0].nel, a, b, h->partial, skip);
+    LAUNCHCHK();
+    return finalize(h, gmg::NB_FLAT, stage);
+}
+
+gmg_status read_state(gmg_handle *h) {
+    HIPCHK(hipMemcpyAsync(h->st_out, h->st, sizeof(PcgState), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return GMG_OK;
+}
+
+// z = B r ; rho = r.z ; p = z   (start, or restart, of the CG recurrence)
+gmg_status pcg_start(gmg_handle *h) {
+    int np = 0;
+    const int *skip = &h->st->done;
+    STCHK(vcycle_any(h, skip, true, &np));
+    STCHK(finalize(h, np, gmg::ST_RHO0));
+    if (mixed(h))
+        gmg::k_update_p<float><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(h->lv[0].nel, h->P,
+                                                                              (const float *)h->lv[0].x, h->st);
+    else
+        gmg::k_update_p<double><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(h->lv[0].nel, h->P,
+                                                                               (const double *)h->lv[0].x, h->st);
+    LAUNCHCHK();
+    gmg::k_clear_restart<<<1, 64, 0, h->stream>>>(h->st);
+    LAUNCHCHK();
+    return GMG_OK;
+}
+
+gmg_status pcg_iteration(gmg_handle *h) {
+    LevelHost &l0 = h->lv[0];
+    const int *skip = &h->st->done;
+    gmg::k_apply<double, double, true><<<l0.til.nblocks, gmg::NT, 0, h->stream>>>(view<double, double>(l0), l0.til,
+                                                                                  h->P, h->Q, h->partial, skip);
+    LAUNCHCHK();
+    STCHK(finalize(h, l0.til.nblocks, gmg::ST_ALPHA));
+    gmg::k_update_xr<<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(l0.nel, h->X, h->R, h->P, h->Q, h->st, h->partial);
+    LAUNCHCHK();
+    STCHK(finalize(h, gmg::NB_FLAT, gmg::ST_RR));
+    int np = 0;
+    STCHK(vcycle_any(h, skip, true, &np));
+    STCHK(finalize(h, np, gmg::ST_BETA));
+    if (mixed(h))
+        gmg::k_update_p<float><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(l0.nel, h->P, (const float *)l0.x, h->st);
+    else
+        gmg::k_update_p<double><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(l0.nel, h->P, (const double *)l0.x,
+                                                                               h->st);
+    LAUNCHCHK();
+    return GMG_OK;
+}
+
+int check_period(const gmg_handle *h) {
+    if (h->opt.check_every > 0) return h->opt.check_every;
+    const int n = h->opt.n;
+    return n >= 257 ? 1 : n >= 65 ? 2 : 4;
+}
+
+// The CG loop until the device sets `done`.
+gmg_status pcg_loop(gmg_handle *h) {
+    const int per = check_period(h);
+    for (;;) {
+        for (int b = 0; b < per; ++b) STCHK(pcg_iteration(h));
+        STCHK(read_state(h));
+        if (h->st_out->done) return GMG_OK;
+    }
+}
+
+// Solve A X = F with the result left in h->X (padded).  f, x0: caller arrays.
+gmg_status solve_core(gmg_handle *h, const double *f, const double *x0, double rtol, int max_it, gmg_info *info) {
+    LevelHost &l0 = h->lv[0];
+    const long long nv = (long long)l0.n * l0.n * l0.n;
+    HIPCHK(hipEventRecord(h->ev0, h->stream));
+    gmg::k_to_padded<double><<<blocks_for(nv, 256), 256, 0, h->stream>>>(l0.n, l0.pitch, f, h->F);
+    LAUNCHCHK();
+    PcgState s0{};
+    s0.rtol2 = rtol * rtol;
+    s0.max_it = max_it;
+    *h->st_in = s0;
+    HIPCHK(hipMemcpyAsync(h->st, h->st_in, sizeof(PcgState), hipMemcpyHostToDevice, h->stream));
+    if (x0) {
+        gmg::k_to_padded<double><<<blocks_for(nv, 256), 256, 0, h->stream>>>(l0.n, l0.pitch, x0, h->X);
+        LAUNCHCHK();
+        gmg::k_residual<double, double><<<l0.til.nblocks, gmg::NT, 0, h->stream>>>(view<double, double>(l0), l0.til,
+                                                                                   h->F, h->X, h->R);
+        LAUNCHCHK();
+    } else {
+        HIPCHK(hipMemsetAsync(h->X, 0, l0.nel * sizeof(double), h->stream));
+        HIPCHK(hipMemcpyAsync(h->R, h->F, l0.nel * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    }
+    STCHK(dot64(h, h->F, h->F, gmg::ST_BB, nullptr));
+    STCHK(dot64(h, h->R, h->R, gmg::ST_RR0, nullptr));
+    STCHK(read_state(h));
+    const double bb = h->st_out->bb;
+    int restarts = 0;
+    gmg_status status = GMG_OK;
+    if (!(bb == bb) || bb > 1.7e308) return fail(h, GMG_ERR_ARG, "right-hand side is not finite");
+    if (bb == 0.0) {  // f = 0: x = 0
+        HIPCHK(hipMemsetAsync(h->X, 0, l0.nel * sizeof(double), h->stream));
+        h->st_out->rr = h->st_out->tt = 0;
+        h->st_out->its = 0;
+    } else {
+        if (!h->st_out->done) {
+            STCHK(pcg_start(h));
+            STCHK(pcg_loop(h));
+        }
+        for (;;) {
+            // FP64 true residual
+            gmg::k_residual<double, double><<<l0.til.nblocks, gmg::NT, 0, h->stream>>>(view<double, double>(l0),
+                                                                                       l0.til, h->F, h->X, h->Q);
+            LAUNCHCHK();
+            STCHK(dot64(h, h->Q, h->Q, gmg::ST_TT, nullptr));
+            STCHK(read_state(h));
+            const PcgState &so = *h->st_out;
+            const bool true_ok = so.tt <= so.rtol2 * so.bb;
+            if (so.status != 0 || true_ok || !mixed(h) || restarts >= 20 || so.its >= so.max_it) break;
+            // MIXED: the recursive residual passed but the FP64 true residual did
+            // not; continue from r = f - A x with a fresh search direction.
+            ++restarts;
+            HIPCHK(hipMemcpyAsync(h->R, h->Q, l0.nel * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+            PcgState s1 = so;
+            s1.done = 0;
+            *h->st_in = s1;
+            HIPCHK(hipMemcpyAsync(h->st, h->st_in, sizeof(PcgState), hipMemcpyHostToDevice, h->stream));
+            STCHK(pcg_start(h));
+            STCHK(pcg_loop(h));
+        }
+        status = h->st_out->status == 7 ? GMG_ERR_BREAKDOWN
+                 : h->st_out->status == 6 ? GMG_ERR_NOT_CONVERGED
+                                          : GMG_OK;
+        if (status == GMG_OK && !(h->st_out->tt <= h->st_out->rtol2 * h->st_out->bb) && mixed(h))
+            status = GMG_ERR_NOT_CONVERGED;
+    }
+    HIPCHK(hipEventRecord(h->ev1, h->stream));
+    HIPCHK(hipEventSynchronize(h->ev1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+    if (info) {
+        const PcgState &so = *h->st_out;
+        info->iterations = so.its;
+        info->restarts = restarts;
+        info->rel_res = bb > 0 ? std::sqrt(so.rr / bb) : 0.0;
+        info->rel_res_true = bb > 0 ? std::sqrt(so.tt / bb) : 0.0;
+        info->setup_ms = h->setup_ms;
+        info->solve_ms = ms;
+    }
+    if (status == GMG_ERR_BREAKDOWN) h->err = "breakdown: p.Ap <= 0 or non-finite residual";
+    if (status == GMG_ERR_NOT_CONVERGED) h->err = "not converged within max_it";
+    return status;
+}
+
+// ------------------------------------------------------------------ setup
+// Dense Cholesky (right-looking, outer-product form) of the coarsest operator,
+// assembled from its padded link coefficients.  Host-side, FP64.
+gmg_status factor_coarsest(gmg_handle *h) {
+    LevelHost &c = h->lv[h->L - 1];
+    const int n = c.n, nn = n - 2, m = nn * nn * nn;
+    std::vector<double> kx(c.nel), ky(c.nel), kz(c.nel);
+    HIPCHK(hipMemcpyAsync(kx.data(), c.kx64, c.nel * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(ky.data(), c.ky64, c.nel * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(kz.data(), c.kz64, c.nel * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    std::vector<double> A((size_t)m * m, 0.0);
+    auto off = [&](int i, int j, int k) { return (long long)k * c.plane + (long long)j * c.pitch + i; };
+    auto unk = [&](int i, int j, int k) { return ((k - 1) * nn + (j - 1)) * nn + (i - 1); };
+    auto in = [&](int i, int j, int k) { return i >= 1 && j >= 1 && k >= 1 && i <= n - 2 && j <= n - 2 && k <= n - 2; };
+    for (int k = 1; k <= n - 2; ++k)
+        for (int j = 1; j <= n - 2; ++j)
+            for (int i = 1; i <= n - 2; ++i) {
+                const int p = unk(i, j, k);
+                const long long o = off(i, j, k);
+                const double lk[6] = {kx[o - 1], kx[o], ky[o - c.pitch], ky[o], kz[o - c.plane], kz[o]};
+                const int nb[6][3] = {{i - 1, j, k}, {i + 1, j, k}, {i, j - 1, k}, {i, j + 1, k}, {i, j, k - 1}, {i, j, k + 1}};
+                for (int f = 0; f < 6; ++f) {
+                    A[(size_t)p * m + p] += c.s * lk[f];
+                    if (in(nb[f][0], nb[f][1], nb[f][2])) A[(size_t)p * m + unk(nb[f][0], nb[f][1], nb[f][2])] -= c.s * lk[f];
+                }
+            }
+    // right-looking: for each column, scale it, then update the trailing block
+    for (int col = 0; col < m; ++col) {
+        double piv = A[(size_t)col * m + col];
+        if (!(piv > 0.0)) return fail(h, GMG_ERR_COEFF, "coarsest operator is not positive definite");
+        piv = std::sqrt(piv);
+        A[(size_t)col * m + col] = piv;
+        for (int r = col + 1; r < m; ++r) A[(size_t)r * m + col] /= piv;
+        for (int cc = col + 1; cc < m; ++cc) {
+            const double lc = A[(size_t)cc * m + col];
+            if (lc == 0.0) continue;
+            for (int r = cc; r < m; ++r) A[(size_t)r * m + cc] -= A[(size_t)r * m + col] * lc;
+        }
+    }
+    for (int r = 0; r < m; ++r)
+        for (int cc = r + 1; cc < m; ++cc) A[(size_t)r * m + cc] = 0.0;
+    HIPCHK(hipMemcpyAsync(h->chol, A.data(), (size_t)m * m * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return GMG_OK;
+}
+
+template <typename V, typename K>
+gmg_status upload_levels(gmg_handle *h) {
+    std::vector<LevBuf<V, K>> lb(h->L);
+    for (int l = 0; l < h->L; ++l) {
+        lb[l].L = view<V, K>(h->lv[l]);
+        lb[l].b = (V *)h->lv[l].b;
+        lb[l].x = (V *)h->lv[l].x;
+        lb[l].t1 = (V *)h->lv[l].t1;
+        lb[l].t2 = nullptr;
+    }
+    HIPCHK(hipMemcpyAsync(h->dev_levels, lb.data(), sizeof(LevBuf<V, K>) * h->L, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return GMG_OK;
+}
+
+gmg_status load_coefficients(gmg_handle *h, const double *kx, const double *ky, const double *kz) {
+    const double t0 = 0;
+    (void)t0;
+    LevelHost &l0 = h->lv[0];
+    // level 0 (+ validation)
+    gmg::k_faces_in<<<blocks_for((long long)l0.n * l0.n * l0.n, 256), 256, 0, h->stream>>>(
+        l0.n, l0.pitch, kx, ky, kz, h->opt.coeff_is_log, l0.kx64, l0.ky64, l0.kz64, h->partial);
+    LAUNCHCHK();
+    STCHK(finalize(h, (int)blocks_for((long long)l0.n * l0.n * l0.n, 256), gmg::ST_TT));
+    STCHK(read_state(h));
+    if (h->st_out->tt != 0.0)
+        return fail(h, GMG_ERR_COEFF, std::to_string((long long)h->st_out->tt) +
+                                          " active link coefficients are not positive and finite");
+    for (int l = 1; l < h->L; ++l) {
+        LevelHost &f = h->lv[l - 1], &c = h->lv[l];
+        gmg::k_coarsen<<<blocks_for((long long)c.n * c.n * c.n, 256), 256, 0, h->stream>>>(
+            f.n, f.pitch, f.plane, f.kx64, f.ky64, f.kz64, c.n, c.pitch, c.plane, c.kx64, c.ky64, c.kz64,
+            h->opt.coarse_rule);
+        LAUNCHCHK();
+    }
+    if (mixed(h)) {
+        for (int l = 0; l < h->L; ++l) {
+            LevelHost &c = h->lv[l];
+            gmg::k_to_bf16<<<gmg::NB_FLAT, 256, 0, h->stream>>>(c.nel, c.kx64, c.kx16);
+            gmg::k_to_bf16<<<gmg::NB_FLAT, 256, 0, h->stream>>>(c.nel, c.ky64, c.ky16);
+            gmg::k_to_bf16<<<gmg::NB_FLAT, 256, 0, h->stream>>>(c.nel, c.kz64, c.kz16);
+            LAUNCHCHK();
+        }
+    }
+    STCHK(factor_coarsest(h));
+    return GMG_OK;
+}
+
+gmg_status check_level(gmg_handle *h, int level) {
+    if (!h) return GMG_ERR_ARG;
+    if (level < 0 || level >= h->L) return fail(h, GMG_ERR_ARG, "level out of range");
+    return GMG_OK;
+}
+
+}  // namespace
+
+// ==================================================================== C ABI
+extern "C" {
+
+void gmg_default_options(gmg_options *o, int32_t n) {
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->n = n;
+    int lv = 0;
+    for (int t = n - 1; t > 1 && (t % 2) == 0; t /= 2) ++lv;
+    o->levels = lv > 0 ? lv : 1;
+    o->cheb_degree = 2;
+    o->cheb_lo = 0.25;
+    o->cheb_hi = 2.0;
+    o->switch_n = 0;
+    o->persistent_wgs = 1;
+    o->precision = GMG_FP64;
+    o->coarse_rule = GMG_COARSE_ARITHMETIC;
+    o->coeff_is_log = 0;
+    o->check_every = 0;
+}
+
+const char *gmg_status_string(gmg_status s) {
+    switch (s) {
+    case GMG_OK: return "GMG_OK";
+    case GMG_ERR_ARG: return "GMG_ERR_ARG";
+    case GMG_ERR_DIMS: return "GMG_ERR_DIMS";
+    case GMG_ERR_COEFF: return "GMG_ERR_COEFF";
+    case GMG_ERR_NOMEM: return "GMG_ERR_NOMEM";
+    case GMG_ERR_HIP: return "GMG_ERR_HIP";
+    case GMG_ERR_NOT_CONVERGED: return "GMG_ERR_NOT_CONVERGED";
+    case GMG_ERR_BREAKDOWN: return "GMG_ERR_BREAKDOWN";
+    }
+    return "GMG_ERR_UNKNOWN";
+}
+
+const char *gmg_last_error(const gmg_handle *h) { return h ? h->err.c_str() : "null handle"; }
+
+void gmg_destroy(gmg_handle *h) {
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    for (void *p : h->allocs) (void)hipFree(p);
+    if (h->st_in) (void)hipHostFree(h->st_in);
+    if (h->st_out) (void)hipHostFree(h->st_out);
+    if (h->ev0) (void)hipEventDestroy(h->ev0);
+    if (h->ev1) (void)hipEventDestroy(h->ev1);
+    delete h;
+}
+
+gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky, const double *kz, void *stream,
+                      gmg_handle **out) {
+    if (!out) return GMG_ERR_ARG;
+    *out = nullptr;
+    if (!opt || !kx || !ky || !kz) return GMG_ERR_ARG;
+    const gmg_options o = *opt;
+    if (o.n < 3 || o.levels < 1 || o.levels > gmg::MAX_LEVELS) return GMG_ERR_DIMS;
+    if (o.cheb_degree < 1 || o.cheb_degree > gmg::MAX_DEGREE || !(o.cheb_lo > 0.0) || !(o.cheb_hi > o.cheb_lo) ||
+        (o.precision != GMG_FP64 && o.precision != GMG_MIXED) ||
+        (o.coarse_rule != GMG_COARSE_ARITHMETIC && o.coarse_rule != GMG_COARSE_HARMONIC) || o.switch_n < 0 ||
+        o.persistent_wgs != 1 || o.check_every < 0 || (o.coeff_is_log != 0 && o.coeff_is_log != 1))
+        return GMG_ERR_ARG;
+    if ((o.n - 1) % (1 << (o.levels - 1)) != 0) return GMG_ERR_DIMS;
+    const int nc = (o.n - 1) / (1 << (o.levels - 1)) + 1;
+    if (nc < 3 || (nc - 2) * (nc - 2) * (nc - 2) > gmg::MAX_COARSE) return GMG_ERR_DIMS;
+
+    gmg_handle *h = new gmg_handle();
+    h->opt = o;
+    h->stream = (hipStream_t)stream;
+    h->L = o.levels;
+    auto bail = [&](gmg_status s) {
+        std::string e = h->err;
+        gmg_destroy(h);
+        (void)e;
+        return s;
+    };
+    hipEvent_t t0, t1;
+    if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess ||
+        hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess)
+        return bail(GMG_ERR_HIP);
+    (void)hipEventRecord(t0, h->stream);
+    if (hipHostMalloc((void **)&h->st_in, sizeof(PcgState)) != hipSuccess ||
+        hipHostMalloc((void **)&h->st_out, sizeof(PcgState)) != hipSuccess)
+        return bail(GMG_ERR_NOMEM);
+    const bool mx = o.precision == GMG_MIXED;
+    // level geometry
+    int n = o.n;
+    for (int l = 0; l < h->L; ++l) {
+        LevelHost &lh = h->lv[l];
+        lh.n = n;
+        lh.pitch = round_up(n, 64);
+        lh.plane = (long long)n * lh.pitch;
+        lh.nel = (long long)n * lh.plane;
+        lh.s = (double)(n - 1) * (double)(n - 1);
+        lh.til = make_tiling(n);
+        n = (n - 1) / 2 + 1;
+    }
+    // persistent switch: first level l >= 1 with N_l <= switch_n
+    h->s_persist = h->L - 1;
+    h->persist = false;
+    if (o.switch_n > 0 && h->L > 1) {
+        for (int l = 1; l < h->L; ++l)
+            if (h->lv[l].n <= o.switch_n) {
+                h->s_persist = l;
+                h->persist = true;
+                break;
+            }
+    }
+    // allocations
+    gmg_status s;
+    LevelHost &l0 = h->lv[0];
+#define ALLOC(ptr, cnt)                                   \
+    do {                                                  \
+        if ((s = dalloc(h, &(ptr), (cnt))) != GMG_OK) return bail(s); \
+    } while (0)
+    ALLOC(h->F, l0.nel);
+    ALLOC(h->X, l0.nel);
+    ALLOC(h->R, l0.nel);
+    ALLOC(h->P, l0.nel);
+    ALLOC(h->Q, l0.nel);
+    h->npartial = std::max(l0.til.nblocks, gmg::NB_FLAT);
+    {
+        const long long nfaces_blocks = blocks_for((long long)l0.n * l0.n * l0.n, 256);
+        if (nfaces_blocks > h->npartial) h->npartial = (int)nfaces_blocks;
+    }
+    ALLOC(h->partial, (long long)h->npartial);
+    ALLOC(h->st, 1LL);
+    for (int l = 0; l < h->L; ++l) {
+        LevelHost &lh = h->lv[l];
+        ALLOC(lh.kx64, lh.nel);
+        ALLOC(lh.ky64, lh.nel);
+        ALLOC(lh.kz64, lh.nel);
+        if (mx) {
+            ALLOC(lh.kx16, lh.nel);
+            ALLOC(lh.ky16, lh.nel);
+            ALLOC(lh.kz16, lh.nel);
+            float *b, *x, *t1;
+            ALLOC(b, lh.nel);
+            ALLOC(x, lh.nel);
+            ALLOC(t1, lh.nel);
+            lh.b = b;
+            lh.x = x;
+            lh.t1 = t1;
+        } else {
+            double *b = nullptr, *x, *t1;
+            if (l > 0) ALLOC(b, lh.nel);
+            ALLOC(x, lh.nel);
+            ALLOC(t1, lh.nel);
+            lh.b = l == 0 ? (void *)h->R : (void *)b;  // FP64: the finest V-cycle input is r itself
+            lh.x = x;
+            lh.t1 = t1;
+        }
+    }
+    {
+        const int nn = h->lv[h->L - 1].n - 2;
+        h->m = nn * nn * nn;
+        ALLOC(h->chol, (long long)h->m * h->m);
+    }
+    {
+        char *dl;
+        const size_t sz = mx ? sizeof(LevBuf<float, bf16>) : sizeof(LevBuf<double, double>);
+        ALLOC(dl, (long long)(sz * h->L));
+        h->dev_levels = dl;
+    }
+#undef ALLOC
+    // Chebyshev coefficients
+    {
+        const double theta = 0.5 * (o.cheb_hi + o.cheb_lo), delta = 0.5 * (o.cheb_hi - o.cheb_lo);
+        const double sigma = theta / delta;
+        ChebCoef<double> c{};
+        c.m = o.cheb_degree;
+        c.cfirst = 1.0 / theta;
+        double rho = 1.0 / sigma;
+        for (int j = 1; j < c.m; ++j) {
+            const double rn = 1.0 / (2.0 * sigma - rho);
+            c.c1[j] = rn * rho;
+            c.c2[j] = 2.0 * rn / delta;
+            rho = rn;
+        }
+        h->cheb64 = c;
+        h->cheb32.m = c.m;
+        h->cheb32.cfirst = (float)c.cfirst;
+        for (int j = 0; j < gmg::MAX_DEGREE; ++j) {
+            h->cheb32.c1[j] = (float)c.c1[j];
+            h->cheb32.c2[j] = (float)c.c2[j];
+        }
+    }
+    if ((s = load_coefficients(h, kx, ky, kz)) != GMG_OK) return bail(s);
+    if ((s = (mx ? upload_levels<float, bf16>(h) : upload_levels<double, double>(h))) != GMG_OK) return bail(s);
+    (void)hipEventRecord(t1, h->stream);
+    (void)hipEventSynchronize(t1);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, t0, t1);
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    h->setup_ms = ms;
+    *out = h;
+    return GMG_OK;
+}
+
+gmg_status gmg_set_coefficients(gmg_handle *h, const double *kx, const double *ky, const double *kz) {
+    if (!h || !kx || !ky || !kz) return GMG_ERR_ARG;
+    hipEvent_t t0, t1;
+    HIPCHK(hipEventCreate(&t0));
+    HIPCHK(hipEventCreate(&t1));
+    HIPCHK(hipEventRecord(t0, h->stream));
+    gmg_status s = load_coefficients(h, kx, ky, kz);
+    (void)hipEventRecord(t1, h->stream);
+    (void)hipEventSynchronize(t1);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, t0, t1);
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    h->setup_ms = ms;
+    return s;
+}
+
+gmg_status gmg_set_stream(gmg_handle *h, void *stream) {
+    if (!h) return GMG_ERR_ARG;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    h->stream = (hipStream_t)stream;
+    return GMG_OK;
+}
+
+gmg_status gmg_solve(gmg_handle *h, const double *f, double *x, const double *x0, double rtol, int32_t max_it,
+                     gmg_info *info) {
+    if (!h || !f || !x) return h ? fail(h, GMG_ERR_ARG, "null vector") : GMG_ERR_ARG;
+    if (!(rtol >= 0.0) || max_it < 1) return fail(h, GMG_ERR_ARG, "rtol must be >= 0 and max_it >= 1");
+    gmg_status st = solve_core(h, f, x0, rtol, max_it, info);
+    if (st != GMG_OK && st != GMG_ERR_NOT_CONVERGED && st != GMG_ERR_BREAKDOWN) return st;
+    LevelHost &l0 = h->lv[0];
+    gmg::k_to_natural<double><<<blocks_for((long long)l0.n * l0.n * l0.n, 256), 256, 0, h->stream>>>(l0.n, l0.pitch,
+                                                                                                     h->X, x);
+    LAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return st;
+}
+
+gmg_status gmg_adjoint_gradient(gmg_handle *h, const double *phi, const double *dl_dphi, double *g_x, double *g_y,
+                                double *g_z, double *lambda, double rtol, int32_t max_it, gmg_info *info) {
+    if (!h || !phi || !dl_dphi || !g_x || !g_y || !g_z) return h ? fail(h, GMG_ERR_ARG, "null array") : GMG_ERR_ARG;
+    if (!(rtol >= 0.0) || max_it < 1) return fail(h, GMG_ERR_ARG, "rtol must be >= 0 and max_it >= 1");
+    gmg_status st = solve_core(h, dl_dphi, nullptr, rtol, max_it, info);
+    if (st != GMG_OK && st != GMG_ERR_NOT_CONVERGED && st != GMG_ERR_BREAKDOWN) return st;
+    LevelHost &l0 = h->lv[0];
+    const long long nv = (long long)l0.n * l0.n * l0.n;
+    gmg::k_face_gradient<<<blocks_for(nv, 256), 256, 0, h->stream>>>(l0.n, l0.pitch, l0.s, h->X, phi, l0.kx64,
+                                                                     l0.ky64, l0.kz64, g_x, g_y, g_z);
+    LAUNCHCHK();
+    if (lambda) {
+        gmg::k_to_natural<double><<<blocks_for(nv, 256), 256, 0, h->stream>>>(l0.n, l0.pitch, h->X, lambda);
+        LAUNCHCHK();
+    }
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return st;
+}
+
+int32_t gmg_level_n(const gmg_handle *h, int32_t level) {
+    if (!h || level < 0 || level >= h->L) return -1;
+    return h->lv[level].n;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ test hooks
+namespace {
+
+template <typename V>
+gmg_status in_vec(gmg_handle *h, const LevelHost &lh, const double *src, V *dst) {
+    const long long nv = (long long)lh.n * lh.n * lh.n;
+    gmg::k_to_padded<V><<<blocks_for(nv, 256), 256, 0, h->stream>>>(lh.n, lh.pitch, src, dst);
+    LAUNCHCHK();
+    return GMG_OK;
+}
+template <typename V>
+gmg_status out_vec(gmg_handle *h, const LevelHost &lh, const V *src, double *dst) {
+    const long long nv = (long long)lh.n * lh.n * lh.n;
+    gmg::k_to_natural<V><<<blocks_for(nv, 256), 256, 0, h->stream>>>(lh.n, lh.pitch, src, dst);
+    LAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return GMG_OK;
+}
+
+template <typename V, typename K>
+gmg_status hook_apply(gmg_handle *h, int level, const double *x, double *y) {
+    LevelHost &lh = h->lv[level];
+    STCHK(in_vec<V>(h, lh, x, (V *)lh.t1));
+    gmg::k_apply<V, K, false><<<lh.til.nblocks, gmg::NT, 0, h->stream>>>(view<V, K>(lh), lh.til, (const V *)lh.t1,
+                                                                        (V *)lh.x, nullptr, nullptr);
+    LAUNCHCHK();
+    return out_vec<V>(h, lh, (const V *)lh.x, y);
+}
+
+template <typename V, typename K>
+gmg_status hook_smooth(gmg_handle *h, int level, const double *b, double *x, int x0_zero) {
+    LevelHost &lh = h->lv[level];
+    STCHK(in_vec<V>(h, lh, b, (V *)lh.b));
+    if (!x0_zero) STCHK(in_vec<V>(h, lh, x, (V *)lh.x));
+    STCHK((smooth_grid<V, K>(h, level, x0_zero != 0, nullptr, nullptr, nullptr, nullptr)));
+    return out_vec<V>(h, lh, (const V *)lh.x, x);
+}
+
+template <typename V, typename K>
+gmg_status hook_restrict(gmg_handle *h, int level, const double *b, const double *x, double *bc) {
+    LevelHost &f = h->lv[level], &c = h->lv[level + 1];
+    STCHK(in_vec<V>(h, f, b, (V *)f.b));
+    STCHK(in_vec<V>(h, f, x, (V *)f.x));
+    const long long mc = (long long)(c.n - 2) * (c.n - 2) * (c.n - 2);
+    gmg::k_resid_restrict<V, K><<<blocks_for(mc, 256), 256, 0, h->stream>>>(view<V, K>(f), (const V *)f.b,
+                                                                             (const V *)f.x, c.n, c.pitch, c.plane,
+                                                                             (V *)c.b, nullptr);
+    LAUNCHCHK();
+    return out_vec<V>(h, c, (const V *)c.b, bc);
+}
+
+template <typename V, typename K>
+gmg_status hook_prolong(gmg_handle *h, int level, const double *e, double *x) {
+    LevelHost &f = h->lv[level], &c = h->lv[level + 1];
+    STCHK(in_vec<V>(h, c, e, (V *)c.x));
+    STCHK(in_vec<V>(h, f, x, (V *)f.x));
+    const long long mf = (long long)(f.n - 2) * (f.n - 2) * (f.n - 2);
+    gmg::k_prolong_add<V><<<blocks_for(mf, 256), 256, 0, h->stream>>>(f.n, f.pitch, f.plane, (const V *)c.x, c.pitch,
+                                                                      c.plane, (V *)f.x, nullptr);
+    LAUNCHCHK();
+    return out_vec<V>(h, f, (const V *)f.x, x);
+}
+
+template <typename V, typename K>
+gmg_status hook_coarse(gmg_handle *h, const double *b, double *x) {
+    LevelHost &c = h->lv[h->L - 1];
+    STCHK(in_vec<V>(h, c, b, (V *)c.b));
+    gmg::k_coarse_solve<V><<<1, 256, 0, h->stream>>>(c.n, c.pitch, c.plane, h->m, h->chol, (const V *)c.b, (V *)c.x,
+                                                      nullptr);
+    LAUNCHCHK();
+    return out_vec<V>(h, c, (const V *)c.x, x);
+}
+
+template <typename V, typename K>
+gmg_status hook_vcycle(gmg_handle *h, const double *r, double *z) {
+    LevelHost &l0 = h->lv[0];
+    STCHK(in_vec<double>(h, l0, r, h->R));
+    STCHK((vcycle<V, K>(h, nullptr, false, nullptr)));
+    return out_vec<V>(h, l0, (const V *)l0.x, z);
+}
+
+}  // namespace
+
+extern "C" {
+
+gmg_status gmg_apply_operator(gmg_handle *h, int32_t level, int32_t use_fp64, const double *x, double *y) {
+    STCHK(check_level(h, level));
+    if (!x || !y) return fail(h, GMG_ERR_ARG, "null vector");
+    if (use_fp64) {
+        if (level != 0) return fail(h, GMG_ERR_ARG, "the FP64 outer operator exists on level 0 only");
+        LevelHost &l0 = h->lv[0];
+        STCHK(in_vec<double>(h, l0, x, h->P));
+        gmg::k_apply<double, double, false><<<l0.til.nblocks, gmg::NT, 0, h->stream>>>(view<double, double>(l0), l0.til,
+                                                                                       h->P, h->Q, nullptr, nullptr);
+        LAUNCHCHK();
+        return out_vec<double>(h, l0, h->Q, y);
+    }
+    return mixed(h) ? hook_apply<float, bf16>(h, level, x, y) : hook_apply<double, double>(h, level, x, y);
+}
+
+gmg_status gmg_debug_smooth(gmg_handle *h, int32_t level, const double *b, double *x, int32_t x0_zero) {
+    STCHK(check_level(h, level));
+    if (!b || !x) return fail(h, GMG_ERR_ARG, "null vector");
+    if (mixed(h) && level == 0) {
+        // the finest FP32 level has its own b buffer; FP64 mode aliases b to r
+    }
+    return mixed(h) ? hook_smooth<float, bf16>(h, level, b, x, x0_zero)
+                    : hook_smooth<double, double>(h, level, b, x, x0_zero);
+}
+
+gmg_status gmg_debug_residual_restrict(gmg_handle *h, int32_t level, const double *b, const double *x,
+                                       double *b_coarse) {
+    STCHK(check_level(h, level));
+    if (level + 1 >= h->L) return fail(h, GMG_ERR_ARG, "no coarser level");
+    if (!b || !x || !b_coarse) return fail(h, GMG_ERR_ARG, "null vector");
+    return mixed(h) ? hook_restrict<float, bf16>(h, level, b, x, b_coarse)
+                    : hook_restrict<double, double>(h, level, b, x, b_coarse);
+}
+
+gmg_status gmg_debug_prolong(gmg_handle *h, int32_t level, const double *e_coarse, double *x) {
+    STCHK(check_level(h, level));
+    if (level + 1 >= h->L) return fail(h, GMG_ERR_ARG, "no coarser level");
+    if (!e_coarse || !x) return fail(h, GMG_ERR_ARG, "null vector");
+    return mixed(h) ? hook_prolong<float, bf16>(h, level, e_coarse, x)
+                    : hook_prolong<double, double>(h, level, e_coarse, x);
+}
+
+gmg_status gmg_debug_coarse_solve(gmg_handle *h, const double *b, double *x) {
+    if (!h) return GMG_ERR_ARG;
+    if (!b || !x) return fail(h, GMG_ERR_ARG, "null vector");
+    return mixed(h) ? hook_coarse<float, bf16>(h, b, x) : hook_coarse<double, double>(h, b, x);
+}
+
+gmg_status gmg_debug_vcycle(gmg_handle *h, const double *r, double *z) {
+    if (!h) return GMG_ERR_ARG;
+    if (!r || !z) return fail(h, GMG_ERR_ARG, "null vector");
+    return mixed(h) ? hook_vcycle<float, bf16>(h, r, z) : hook_vcycle<double, double>(h, r, z);
+}
+
+gmg_status gmg_get_level_coefficients(gmg_handle *h, int32_t level, double *kx, double *ky, double *kz) {
+    STCHK(check_level(h, level));
+    if (!kx || !ky || !kz) return fail(h, GMG_ERR_ARG, "null array");
+    LevelHost &lh = h->lv[level];
+    const long long nv = (long long)lh.n * lh.n * lh.n;
+    if (mixed(h))
+        gmg::k_faces_out<bf16><<<blocks_for(nv, 256), 256, 0, h->stream>>>(lh.n, lh.pitch, lh.kx16, lh.ky16, lh.kz16,
+                                                                           kx, ky, kz);
+    else
+        gmg::k_faces_out<double><<<blocks_for(nv, 256), 256, 0, h->stream>>>(lh.n, lh.pitch, lh.kx64, lh.ky64,
+                                                                             lh.kz64, kx, ky, kz);
+    LAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return GMG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,915 @@
+// kernels.hpp -- HIP device code (gfx950) for the multigrid-preconditioned CG
+// solve of -div(k grad phi) = f on a structured 3D vertex grid.
+//
+// Storage used by every kernel (one "level"):
+//   * vertex (i,j,k) of an N^3 grid lives at element  k*plane + j*pitch + i,
+//     pitch = N rounded up to a multiple of 64 elements, plane = N*pitch, so
+//     every row starts on a 128-byte boundary for FP64, FP32 and BF16 alike;
+//   * kx[o] is the coefficient of the link (i,j,k)-(i+1,j,k) stored at the
+//     offset o of its lower end point (ky, kz likewise along y, z);
+//   * boundary vertices and padding hold 0 in every vector and are never
+//     written, so flat (1D) vector kernels may sweep whole arrays.
+//
+// Two precisions share the code through templates: V is the arithmetic /
+// vector type (double or float) and K the stored coefficient type (double or
+// bfloat16 bits).  Arithmetic is written with explicit fused multiply-adds and
+// the file is compiled with -ffp-contract=off, so every code path that calls the
+// same value function (grid kernels, the persistent coarse kernel) rounds
+// identically.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gmg {
+
+typedef uint16_t bf16;
+
+constexpr int TX = 64;          // threads along x in a stencil tile (one wave64 row)
+constexpr int TY = 4;           // rows per tile
+constexpr int NT = TX * TY;     // threads per stencil workgroup
+constexpr int NT_FLAT = 256;    // threads per workgroup of the flat vector kernels
+constexpr int NB_FLAT = 2048;   // workgroups of the flat vector kernels (fixed => deterministic sums)
+constexpr int NT_PERSIST = 1024;
+constexpr int MAX_LEVELS = 16;
+constexpr int MAX_DEGREE = 8;
+constexpr int MAX_COARSE = 4096;  // interior unknowns of the coarsest level (dense Cholesky)
+
+// ---------------------------------------------------------------- scalars
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __fma_rn(a, b, c); }
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __fmaf_rn(a, b, c); }
+__device__ __forceinline__ double kval(double v) { return v; }
+__device__ __forceinline__ float kval(bf16 v) { return __uint_as_float(((uint32_t)v) << 16); }
+
+// FP64 -> BF16, round to nearest even, directly from the double (no double
+// rounding through FP32).  Inputs are positive normal numbers well inside the
+// BF16 range; the exponent carry of the rounding increment is handled by the
+// integer add.
+__device__ __forceinline__ bf16 f64_to_bf16_rne(double x) {
+    uint64_t u = (uint64_t)__double_as_longlong(x);
+    uint64_t sign = u >> 63;
+    int64_t e = (int64_t)((u >> 52) & 0x7ff);
+    uint64_t mant = u & 0xfffffffffffffull;
+    // 8 significant bits: keep the top 7 mantissa bits, round the other 45
+    uint64_t keep = mant >> 45;
+    uint64_t rest = mant & ((1ull << 45) - 1);
+    uint64_t half = 1ull << 44;
+    if (rest > half || (rest == half && (keep & 1))) {
+        keep += 1;
+        if (keep == 128) {
+            keep = 0;
+            e += 1;
+        }
+    }
+    int64_t eb = e - 1023 + 127;
+    if (e == 0 || eb <= 0) return (bf16)(sign << 15);           // zero / underflow -> signed zero
+    if (eb >= 255) return (bf16)((sign << 15) | (0xffu << 7));  // overflow -> inf
+    return (bf16)((sign << 15) | ((uint64_t)eb << 7) | keep);
+}
+
+// ---------------------------------------------------------------- level views
+template <typename V, typename K>
+struct Lev {
+    int n;           // vertices per side
+    int pitch;       // elements per row
+    long long plane; // n * pitch
+    V s;             // h^-2
+    const K *kx, *ky, *kz;
+};
+
+// Per-level buffers the V-cycle uses (device-resident array of these).
+template <typename V, typename K>
+struct LevBuf {
+    Lev<V, K> L;
+    V *b, *x, *t1, *t2;
+};
+
+struct Tiling {
+    int tiles_x, tiles_y, zchunk, nblocks;
+};
+
+template <typename V>
+struct ChebCoef {
+    int m;          // steps per smoothing
+    V cfirst;       // 1/theta
+    V c1[MAX_DEGREE], c2[MAX_DEGREE];  // step j >= 1: rho_j rho_{j-1}, 2 rho_j / delta
+};
+
+// ---------------------------------------------------------------- value functions
+// (A u)_p for one vertex from its 7 values and 6 link coefficients.
+template <typename T>
+__device__ __forceinline__ T apply7(T up, T uw, T ue, T us, T un, T ub, T ut, T kw, T ke, T ks, T kn,
+                                    T kb, T kt, T s) {
+    T acc = kw * (up - uw);
+    acc = fmaT(ke, up - ue, acc);
+    acc = fmaT(ks, up - us, acc);
+    acc = fmaT(kn, up - un, acc);
+    acc = fmaT(kb, up - ub, acc);
+    acc = fmaT(kt, up - ut, acc);
+    return s * acc;
+}
+template <typename T>
+__device__ __forceinline__ T diag7(T kw, T ke, T ks, T kn, T kb, T kt, T s) {
+    return s * (((kw + ke) + (ks + kn)) + (kb + kt));
+}
+// first Chebyshev step from x0 = 0:  x1 = (1/theta) D^-1 b
+template <typename T>
+__device__ __forceinline__ T cheb_first_val(T bv, T d, T c) { return c * (bv / d); }
+// Chebyshev step: x_{j+1} = x_j + c1 (x_j - x_{j-1}) + c2 D^-1 (b - A x_j)
+template <typename T>
+__device__ __forceinline__ T cheb_step_val(T xc, T diff, T bv, T ax, T d, T c1, T c2) {
+    return fmaT(c2, (bv - ax) / d, fmaT(c1, diff, xc));
+}
+
+// The 7 vertex values and 6 link coefficients around offset o, read from memory.
+template <typename V, typename K>
+struct Nbr {
+    V up, uw, ue, us, un, ub, ut;
+    V kw, ke, ks, kn, kb, kt;
+};
+template <typename V, typename K>
+__device__ __forceinline__ void load_k(const Lev<V, K> &L, long long o, Nbr<V, K> &q) {
+    q.kw = kval(L.kx[o - 1]);
+    q.ke = kval(L.kx[o]);
+    q.ks = kval(L.ky[o - L.pitch]);
+    q.kn = kval(L.ky[o]);
+    q.kb = kval(L.kz[o - L.plane]);
+    q.kt = kval(L.kz[o]);
+}
+template <typename V, typename K>
+__device__ __forceinline__ void load_u(const Lev<V, K> &L, const V *u, long long o, Nbr<V, K> &q) {
+    q.up = u[o];
+    q.uw = u[o - 1];
+    q.ue = u[o + 1];
+    q.us = u[o - L.pitch];
+    q.un = u[o + L.pitch];
+    q.ub = u[o - L.plane];
+    q.ut = u[o + L.plane];
+}
+template <typename V, typename K>
+__device__ __forceinline__ V apply_at(const Lev<V, K> &L, const V *u, long long o) {
+    Nbr<V, K> q;
+    load_k(L, o, q);
+    load_u(L, u, o, q);
+    return apply7(q.up, q.uw, q.ue, q.us, q.un, q.ub, q.ut, q.kw, q.ke, q.ks, q.kn, q.kb, q.kt, L.s);
+}
+
+// ---------------------------------------------------------------- reductions
+// Deterministic workgroup sum: wave64 butterfly, then the per-wave values in
+// wave order.  Result valid in thread 0.
+template <int NTH>
+__device__ __forceinline__ double block_sum(double v) {
+    __shared__ double red[NTH / 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int w = 0; w < NTH / 64; ++w) s += red[w];
+    }
+    return s;
+}
+
+// ---------------------------------------------------------------- tiling
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b on XCD
+// b % 8).  Give every XCD a contiguous range of tiles so that neighbouring
+// tiles, which share halo rows, share that XCD's L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+    const int per = nb >> 3;
+    if (b < (per << 3)) return (b & 7) * per + (b >> 3);
+    return b;
+}
+
+struct Column {
+    int i, j, k0, k1;
+    bool active;
+};
+// tile -> (x tile, y tile, z chunk), x fastest; a thread owns the column
+// (i, j) for planes k0..k1-1.  x tiles start at i = 0 so rows stay aligned.
+__device__ __forceinline__ Column tile_column(int n, const Tiling &t) {
+    int b = xcd_tile(blockIdx.x, t.nblocks);
+    const int tx = b % t.tiles_x;
+    b /= t.tiles_x;
+    const int ty = b % t.tiles_y;
+    const int cz = b / t.tiles_y;
+    Column c;
+    c.i = tx * TX + (threadIdx.x & (TX - 1));
+    c.j = 1 + ty * TY + (threadIdx.x >> 6);
+    c.k0 = 1 + cz * t.zchunk;
+    c.k1 = min(c.k0 + t.zchunk, n - 1);
+    c.active = c.i >= 1 && c.i <= n - 2 && c.j <= n - 2 && c.k0 < c.k1;
+    return c;
+}
+
+// ================================================================ stencil kernels
+// Each thread marches its column in z, keeping u(k-1), u(k) and the lower
+// z-link in registers; x/y neighbours come through the L1/L2 caches.
+
+// y = A u ;  DOT: partial[wg] = sum u . (A u)   (PCG p.Ap)
+template <typename V, typename K, bool DOT>
+__global__ __launch_bounds__(NT) void k_apply(Lev<V, K> L, Tiling t, const V *__restrict__ u,
+                                              V *__restrict__ y, double *__restrict__ partial,
+                                              const int *__restrict__ skip) {
+    if (skip && *skip) return;
+    const Column c = tile_column(L.n, t);
+    double dot = 0.0;
+    if (c.active) {
+        const int pitch = L.pitch;
+        const long long plane = L.plane;
+        long long o = (long long)c.k0 * plane + (long long)c.j * pitch + c.i;
+        V ub = u[o - plane], up = u[o];
+        V kb = kval(L.kz[o - plane]);
+        for (int k = c.k0; k < c.k1; ++k, o += plane) {
+            const V ut = u[o + plane];
+            const V uw = u[o - 1], ue = u[o + 1], us = u[o - pitch], un = u[o + pitch];
+            const V kw = kval(L.kx[o - 1]), ke = kval(L.kx[o]), ks = kval(L.ky[o - pitch]),
+                    kn = kval(L.ky[o]), kt = kval(L.kz[o]);
+            const V r = apply7(up, uw, ue, us, un, ub, ut, kw, ke, ks, kn, kb, kt, L.s);
+            y[o] = r;
+            if (DOT) dot = fmaT((double)up, (double)r, dot);
+            ub = up;
+            up = ut;
+            kb = kt;
+        }
+    }
+    if (DOT) {
+        const double s = block_sum<NT>(dot);
+        if (threadIdx.x == 0) partial[blockIdx.x] = s;
+    }
+}
+
+// r = b - A u   (FP64 true residual and the x0 != 0 start)
+template <typename V, typename K>
+__global__ __launch_bounds__(NT) void k_residual(Lev<V, K> L, Tiling t, const V *__restrict__ b,
+                                                 const V *__restrict__ u, V *__restrict__ r) {
+    const Column c = tile_column(L.n, t);
+    if (!c.active) return;
+    const int pitch = L.pitch;
+    const long long plane = L.plane;
+    long long o = (long long)c.k0 * plane + (long long)c.j * pitch + c.i;
+    V ub = u[o - plane], up = u[o];
+    V kb = kval(L.kz[o - plane]);
+    for (int k = c.k0; k < c.k1; ++k, o += plane) {
+        const V ut = u[o + plane];
+        const V uw = u[o - 1], ue = u[o + 1], us = u[o - pitch], un = u[o + pitch];
+        const V kw = kval(L.kx[o - 1]), ke = kval(L.kx[o]), ks = kval(L.ky[o - pitch]),
+                kn = kval(L.ky[o]), kt = kval(L.kz[o]);
+        r[o] = b[o] - apply7(up, uw, ue, us, un, ub, ut, kw, ke, ks, kn, kb, kt, L.s);
+        ub = up;
+        up = ut;
+        kb = kt;
+    }
+}
+
+// First Chebyshev step from zero: x1 = c D^-1 b.
+// CVT (finest level, mixed precision): b is converted from the FP64 residual
+// r64 and also stored (b_out) for the later sweeps of the cycle.
+template <typename V, typename K, bool CVT>
+__global__ __launch_bounds__(NT) void k_cheb_first(Lev<V, K> L, Tiling t, const V *__restrict__ b,
+                                                   const double *__restrict__ r64, V *__restrict__ b_out,
+                                                   V *__restrict__ x_out, V c, const int *__restrict__ skip) {
+    if (skip && *skip) return;
+    const Column col = tile_column(L.n, t);
+    if (!col.active) return;
+    const int pitch = L.pitch;
+    const long long plane = L.plane;
+    long long o = (long long)col.k0 * plane + (long long)col.j * pitch + col.i;
+    V kb = kval(L.kz[o - plane]);
+    for (int k = col.k0; k < col.k1; ++k, o += plane) {
+        const V kw = kval(L.kx[o - 1]), ke = kval(L.kx[o]), ks = kval(L.ky[o - pitch]),
+                kn = kval(L.ky[o]), kt = kval(L.kz[o]);
+        V bv;
+        if (CVT) {
+            bv = (V)r64[o];
+            b_out[o] = bv;
+        } else {
+            bv = b[o];
+        }
+        x_out[o] = cheb_first_val(bv, diag7(kw, ke, ks, kn, kb, kt, L.s), c);
+        kb = kt;
+    }
+}
+
+// Chebyshev step  out = x + c1 (x - x_prev) + c2 D^-1 (b - A x).
+// PM = 0: no previous iterate (c1 term vanishes); PM = 1: previous iterate is
+// zero (diff = x); PM = 2: previous iterate in xp.  out may alias xp (read only
+// at the thread's own vertex before the write), never x.
+// DOTR: last sweep of the cycle on the finest level; partial[wg] = sum r64 . out.
+template <typename V, typename K, int PM, bool DOTR>
+__global__ __launch_bounds__(NT) void k_cheb_step(Lev<V, K> L, Tiling t, const V *__restrict__ b,
+                                                  const V *__restrict__ x, const V *xp, V *out, V c1, V c2,
+                                                  const double *__restrict__ r64, double *__restrict__ partial,
+                                                  const int *__restrict__ skip) {
+    if (skip && *skip) return;
+    const Column col = tile_column(L.n, t);
+    double dot = 0.0;
+    if (col.active) {
+        const int pitch = L.pitch;
+        const long long plane = L.plane;
+        long long o = (long long)col.k0 * plane + (long long)col.j * pitch + col.i;
+        V ub = x[o - plane], up = x[o];
+        V kb = kval(L.kz[o - plane]);
+        for (int k = col.k0; k < col.k1; ++k, o += plane) {
+            const V ut = x[o + plane];
+            const V uw = x[o - 1], ue = x[o + 1], us = x[o - pitch], un = x[o + pitch];
+            const V kw = kval(L.kx[o - 1]), ke = kval(L.kx[o]), ks = kval(L.ky[o - pitch]),
+                    kn = kval(L.ky[o]), kt = kval(L.kz[o]);
+            const V ax = apply7(up, uw, ue, us, un, ub, ut, kw, ke, ks, kn, kb, kt, L.s);
+            const V d = diag7(kw, ke, ks, kn, kb, kt, L.s);
+            const V diff = PM == 0 ? V(0) : PM == 1 ? up : up - xp[o];
+            const V v = cheb_step_val(up, diff, b[o], ax, d, PM == 0 ? V(0) : c1, c2);
+            out[o] = v;
+            if (DOTR) dot = fmaT(r64[o], (double)v, dot);
+            ub = up;
+            up = ut;
+            kb = kt;
+        }
+    }
+    if (DOTR) {
+        const double s = block_sum<NT>(dot);
+        if (threadIdx.x == 0) partial[blockIdx.x] = s;
+    }
+}
+
+// ---------------------------------------------------------------- transfer operators
+// Full-weighting restriction of the residual, summed in a fixed order:
+// x first, then y, then z, each with weights (1/4, 1/2, 1/4).
+template <typename V, typename K>
+__device__ __forceinline__ V resid_at(const Lev<V, K> &F, const V *b, const V *x, int i, int j, int k) {
+    if (i < 1 || j < 1 || k < 1 || i > F.n - 2 || j > F.n - 2 || k > F.n - 2) return V(0);
+    const long long o = (long long)k * F.plane + (long long)j * F.pitch + i;
+    return b[o] - apply_at(F, x, o);
+}
+template <typename V, typename K>
+__device__ __forceinline__ V restrict_resid_at(const Lev<V, K> &F, const V *b, const V *x, int I, int J,
+                                               int K_) {
+    const V w[3] = {V(0.25), V(0.5), V(0.25)};
+    V accz = V(0);
+    for (int c = 0; c < 3; ++c) {
+        V accy = V(0);
+        for (int bb = 0; bb < 3; ++bb) {
+            V accx = V(0);
+            for (int a = 0; a < 3; ++a)
+                accx = fmaT(w[a], resid_at(F, b, x, 2 * I + a - 1, 2 * J + bb - 1, 2 * K_ + c - 1), accx);
+            accy = fmaT(w[bb], accx, accy);
+        }
+        accz = fmaT(w[c], accy, accz);
+    }
+    return accz;
+}
+// (P e) at fine vertex (i,j,k): trilinear, tensor product of the 1D rules
+// (even index -> coarse i/2, odd -> mean of (i-1)/2 and (i+1)/2).
+template <typename V>
+__device__ __forceinline__ V prolong_at(const V *e, int pc, long long plc, int i, int j, int k) {
+    const int i0 = i >> 1, i1 = (i + 1) >> 1, j0 = j >> 1, j1 = (j + 1) >> 1, k0 = k >> 1,
+              k1 = (k + 1) >> 1;
+    const V wi = (i & 1) ? V(0.5) : V(1), wj = (j & 1) ? V(0.5) : V(1), wk = (k & 1) ? V(0.5) : V(1);
+    const int ni = (i & 1) ? 2 : 1, nj = (j & 1) ? 2 : 1, nk = (k & 1) ? 2 : 1;
+    V accz = V(0);
+    for (int c = 0; c < nk; ++c) {
+        const int kk = c ? k1 : k0;
+        V accy = V(0);
+        for (int bb = 0; bb < nj; ++bb) {
+            const int jj = bb ? j1 : j0;
+            V accx = V(0);
+            for (int a = 0; a < ni; ++a) {
+                const int ii = a ? i1 : i0;
+                accx = fmaT(wi, e[(long long)kk * plc + (long long)jj * pc + ii], accx);
+            }
+            accy = fmaT(wj, accx, accy);
+        }
+        accz = fmaT(wk, accy, accz);
+    }
+    return accz;
+}
+
+// b_c = R (b - A x), one thread per interior coarse vertex.
+template <typename V, typename K>
+__global__ __launch_bounds__(256) void k_resid_restrict(Lev<V, K> F, const V *__restrict__ b,
+                                                        const V *__restrict__ x, int nc, int pc, long long plc,
+                                                        V *__restrict__ bc, const int *__restrict__ skip) {
+    if (skip && *skip) return;
+    const int m = nc - 2;
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long long)m * m * m) return;
+    const int I = 1 + (int)(idx % m), J = 1 + (int)((idx / m) % m), K_ = 1 + (int)(idx / ((long long)m * m));
+    bc[(long long)K_ * plc + (long long)J * pc + I] = restrict_resid_at(F, b, x, I, J, K_);
+}
+
+// x += P e, one thread per interior fine vertex.
+template <typename V>
+__global__ __launch_bounds__(256) void k_prolong_add(int n, int pitch, long long plane, const V *__restrict__ e,
+                                                     int pc, long long plc, V *__restrict__ x,
+                                                     const int *__restrict__ skip) {
+    if (skip && *skip) return;
+    const int m = n - 2;
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long long)m * m * m) return;
+    const int i = 1 + (int)(idx % m), j = 1 + (int)((idx / m) % m), k = 1 + (int)(idx / ((long long)m * m));
+    const long long o = (long long)k * plane + (long long)j * pitch + i;
+    x[o] = x[o] + prolong_at(e, pc, plc, i, j, k);
+}
+
+// ---------------------------------------------------------------- coarsest solve
+// x = (L L^T)^-1 b over the m interior unknowns of the coarsest level, by one
+// workgroup: column-oriented forward and backward substitution in FP64.
+template <typename V>
+__device__ void chol_solve_block(int n, int pitch, long long plane, int m, const double *Lf, const V *b, V *x,
+                                 double *y) {
+    const int nn = n - 2;
+    for (int u = threadIdx.x; u < m; u += blockDim.x) {
+        const int i = 1 + u % nn, j = 1 + (u / nn) % nn, k = 1 + u / (nn * nn);
+        y[u] = (double)b[(long long)k * plane + (long long)j * pitch + i];
+    }
+    __syncthreads();
+    for (int c = 0; c < m; ++c) {  // L w = b
+        const double yc = y[c] / Lf[(long long)c * m + c];
+        __syncthreads();
+        if (threadIdx.x == 0) y[c] = yc;
+        for (int r = c + 1 + threadIdx.x; r < m; r += blockDim.x) y[r] = fmaT(-Lf[(long long)r * m + c], yc, y[r]);
+        __syncthreads();
+    }
+    for (int c = m - 1; c >= 0; --c) {  // L^T y = w
+        const double yc = y[c] / Lf[(long long)c * m + c];
+        __syncthreads();
+        if (threadIdx.x == 0) y[c] = yc;
+        for (int r = threadIdx.x; r < c; r += blockDim.x) y[r] = fmaT(-Lf[(long long)c * m + r], yc, y[r]);
+        __syncthreads();
+    }
+    for (int u = threadIdx.x; u < m; u += blockDim.x) {
+        const int i = 1 + u % nn, j = 1 + (u / nn) % nn, k = 1 + u / (nn * nn);
+        x[(long long)k * plane + (long long)j * pitch + i] = (V)y[u];
+    }
+    __syncthreads();
+}
+
+template <typename V>
+__global__ __launch_bounds__(256) void k_coarse_solve(int n, int pitch, long long plane, int m,
+                                                      const double *__restrict__ Lf, const V *__restrict__ b,
+                                                      V *__restrict__ x, const int *__restrict__ skip) {
+    if (skip && *skip) return;
+    __shared__ double y[MAX_COARSE];
+    chol_solve_block(n, pitch, plane, m, Lf, b, x, y);
+}
+
+// ---------------------------------------------------------------- persistent coarse kernel
+// Levels s..last-1 of the V-cycle plus the coarsest solve, all inside one
+// workgroup: every sweep is a block-strided loop over the level's interior
+// vertices followed by a workgroup barrier.  The per-vertex arithmetic is the
+// same value functions the grid kernels call.
+template <typename V, typename K>
+__device__ __forceinline__ void vertex_of(int n, int u, int &i, int &j, int &k) {
+    const int nn = n - 2;
+    i = 1 + u % nn;
+    j = 1 + (u / nn) % nn;
+    k = 1 + u / (nn * nn);
+}
+
+template <typename V, typename K>
+__device__ void p_cheb_first(const LevBuf<V, K> &lb, V *out, V c) {
+    const Lev<V, K> &L = lb.L;
+    const int np = (L.n - 2) * (L.n - 2) * (L.n - 2);
+    for (int u = threadIdx.x; u < np; u += blockDim.x) {
+        int i, j, k;
+        vertex_of<V, K>(L.n, u, i, j, k);
+        const long long o = (long long)k * L.plane + (long long)j * L.pitch + i;
+        Nbr<V, K> q;
+        load_k(L, o, q);
+        out[o] = cheb_first_val(lb.b[o], diag7(q.kw, q.ke, q.ks, q.kn, q.kb, q.kt, L.s), c);
+    }
+    __syncthreads();
+}
+template <typename V, typename K>
+__device__ void p_cheb_step(const LevBuf<V, K> &lb, const V *x, const V *xp, int pm, V *out, V c1, V c2) {
+    const Lev<V, K> &L = lb.L;
+    const int np = (L.n - 2) * (L.n - 2) * (L.n - 2);
+    for (int u = threadIdx.x; u < np; u += blockDim.x) {
+        int i, j, k;
+        vertex_of<V, K>(L.n, u, i, j, k);
+        const long long o = (long long)k * L.plane + (long long)j * L.pitch + i;
+        Nbr<V, K> q;
+        load_k(L, o, q);
+        load_u(L, x, o, q);
+        const V ax = apply7(q.up, q.uw, q.ue, q.us, q.un, q.ub, q.ut, q.kw, q.ke, q.ks, q.kn, q.kb, q.kt, L.s);
+        const V d = diag7(q.kw, q.ke, q.ks, q.kn, q.kb, q.kt, L.s);
+        const V diff = pm == 0 ? V(0) : pm == 1 ? q.up : q.up - xp[o];
+        out[o] = cheb_step_val(q.up, diff, lb.b[o], ax, d, pm == 0 ? V(0) : c1, c2);
+    }
+    __syncthreads();
+}
+template <typename V>
+__device__ void p_copy(int n, int pitch, long long plane, const V *src, V *dst) {
+    const int np = (n - 2) * (n - 2) * (n - 2);
+    const int nn = n - 2;
+    for (int u = threadIdx.x; u < np; u += blockDim.x) {
+        const int i = 1 + u % nn, j = 1 + (u / nn) % nn, k = 1 + u / (nn * nn);
+        const long long o = (long long)k * plane + (long long)j * pitch + i;
+        dst[o] = src[o];
+    }
+    __syncthreads();
+}
+
+// Smoothing schedule shared by both paths (see the host-side driver): the
+// iterate alternates between x and t1; odd degrees end with a copy into x.
+template <typename V, typename K>
+__device__ void p_smooth(const LevBuf<V, K> &lb, const ChebCoef<V> &cc, bool from_zero) {
+    const Lev<V, K> &L = lb.L;
+    V *bufs[2] = {lb.x, lb.t1};
+    int cur;  // index of the buffer holding x_j
+    int prev; // buffer holding x_{j-1} (or -1)
+    if (from_zero) {
+        if (cc.m == 1) {
+            p_cheb_first(lb, lb.x, cc.cfirst);
+            return;
+        }
+        p_cheb_first(lb, lb.t1, cc.cfirst);  // x_1 in t1
+        cur = 1;
+        prev = -1;  // x_0 = 0
+    } else {
+        p_cheb_step(lb, lb.x, (const V *)nullptr, 0, lb.t1, V(0), cc.cfirst);  // x_1 in t1
+        cur = 1;
+        prev = 0;
+        if (cc.m == 1) {
+            p_copy(L.n, L.pitch, L.plane, lb.t1, lb.x);
+            return;
+        }
+    }
+    for (int j = 1; j < cc.m; ++j) {
+        const int dst = 1 - cur;  // the buffer of x_{j-1} (or the free one)
+        if (prev < 0)
+            p_cheb_step(lb, bufs[cur], (const V *)nullptr, 1, bufs[dst], cc.c1[j], cc.c2[j]);
+        else
+            p_cheb_step(lb, bufs[cur], bufs[prev], 2, bufs[dst], cc.c1[j], cc.c2[j]);
+        prev = cur;
+        cur = dst;
+    }
+    if (cur != 0) p_copy(L.n, L.pitch, L.plane, lb.t1, lb.x);
+}
+
+template <typename V, typename K>
+__global__ __launch_bounds__(NT_PERSIST) void k_persistent(const LevBuf<V, K> *__restrict__ lv, int s, int last,
+                                                           ChebCoef<V> cc, const double *__restrict__ Lf, int m,
+                                                           const int *__restrict__ skip) {
+    if (skip && *skip) return;
+    __shared__ double y[MAX_COARSE];
+    for (int l = s; l < last; ++l) {
+        const LevBuf<V, K> F = lv[l];
+        const LevBuf<V, K> C = lv[l + 1];
+        p_smooth(F, cc, true);
+        const int nc = C.L.n, mc = nc - 2;
+        const int np = mc * mc * mc;
+        for (int u = threadIdx.x; u < np; u += blockDim.x) {
+            const int I = 1 + u % mc, J = 1 + (u / mc) % mc, K_ = 1 + u / (mc * mc);
+            C.b[(long long)K_ * C.L.plane + (long long)J * C.L.pitch + I] =
+                restrict_resid_at(F.L, F.b, F.x, I, J, K_);
+        }
+        __syncthreads();
+    }
+    {
+        const LevBuf<V, K> C = lv[last];
+        chol_solve_block(C.L.n, C.L.pitch, C.L.plane, m, Lf, C.b, C.x, y);
+    }
+    for (int l = last - 1; l >= s; --l) {
+        const LevBuf<V, K> F = lv[l];
+        const LevBuf<V, K> C = lv[l + 1];
+        const int mf = F.L.n - 2;
+        const int np = mf * mf * mf;
+        for (int u = threadIdx.x; u < np; u += blockDim.x) {
+            const int i = 1 + u % mf, j = 1 + (u / mf) % mf, k = 1 + u / (mf * mf);
+            const long long o = (long long)k * F.L.plane + (long long)j * F.L.pitch + i;
+            F.x[o] = F.x[o] + prolong_at(C.x, C.L.pitch, C.L.plane, i, j, k);
+        }
+        __syncthreads();
+        p_smooth(F, cc, false);
+    }
+}
+
+// ================================================================ PCG vector kernels (FP64)
+struct PcgState {
+    double bb;      // ||f||^2
+    double rho;     // r.z
+    double alpha, beta;
+    double rr;      // ||r||^2 (recursive)
+    double tt;      // ||f - A x||^2 (true)
+    double rtol2;   // rtol^2
+    int its, max_it;
+    int done;       // 1: stop (converged, breakdown or max_it); every loop kernel skips
+    int status;     // 0 running/converged, 6 not converged, 7 breakdown
+    int restart;    // 1: next p-update uses beta = 0
+    int pad;
+};
+
+// x += alpha p ; r -= alpha q ; partial = sum r^2
+__global__ __launch_bounds__(NT_FLAT) void k_update_xr(long long nel, double *__restrict__ x, double *__restrict__ r,
+                                                       const double *__restrict__ p, const double *__restrict__ q,
+                                                       const PcgState *__restrict__ st, double *__restrict__ partial) {
+    if (st->done) return;
+    const double a = st->alpha;
+    double acc = 0.0;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nel; e += stride) {
+        x[e] = fmaT(a, p[e], x[e]);
+        const double rn = fmaT(-a, q[e], r[e]);
+        r[e] = rn;
+        acc = fmaT(rn, rn, acc);
+    }
+    const double s = block_sum<NT_FLAT>(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// p = z + beta p   (z FP64 or FP32)
+template <typename Z>
+__global__ __launch_bounds__(NT_FLAT) void k_update_p(long long nel, double *__restrict__ p, const Z *__restrict__ z,
+                                                      const PcgState *__restrict__ st) {
+    if (st->done) return;
+    const double bta = st->restart ? 0.0 : st->beta;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    if (bta == 0.0) {
+        for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nel; e += stride) p[e] = (double)z[e];
+    } else {
+        for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nel; e += stride)
+            p[e] = fmaT(bta, p[e], (double)z[e]);
+    }
+}
+
+// partial = sum a.b  (b FP64 or FP32)
+template <typename Z>
+__global__ __launch_bounds__(NT_FLAT) void k_dot(long long nel, const double *__restrict__ a, const Z *__restrict__ b,
+                                                 double *__restrict__ partial, const int *__restrict__ skip) {
+    if (skip && *skip) return;
+    double acc = 0.0;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nel; e += stride)
+        acc = fmaT(a[e], (double)b[e], acc);
+    const double s = block_sum<NT_FLAT>(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+enum Stage { ST_BB = 0, ST_RR0 = 1, ST_RHO0 = 2, ST_ALPHA = 3, ST_RR = 4, ST_BETA = 5, ST_TT = 6 };
+
+// Sum `count` partials in a fixed order and advance the PCG state.
+__global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ partial, int count, int stage,
+                                                  PcgState *__restrict__ st) {
+    if ((stage == ST_ALPHA || stage == ST_RR || stage == ST_BETA) && st->done) return;
+    double acc = 0.0;
+    for (int w = threadIdx.x; w < count; w += 256) acc += partial[w];
+    const double sum = block_sum<256>(acc);
+    if (threadIdx.x != 0) return;
+    switch (stage) {
+    case ST_BB:
+        st->bb = sum;
+        break;
+    case ST_RR0:  // residual of the initial guess
+        st->rr = sum;
+        if (!(sum == sum) || sum > 1.7e308) {
+            st->status = 7;
+            st->done = 1;
+        } else if (sum <= st->rtol2 * st->bb) {
+            st->done = 1;
+        }
+        break;
+    case ST_RHO0:
+        st->rho = sum;
+        st->restart = 1;
+        break;
+    case ST_ALPHA:
+        if (!(sum > 0.0) || sum > 1.7e308) {  // p.Ap <= 0, NaN or Inf
+            st->status = 7;
+            st->done = 1;
+        } else {
+            st->alpha = st->rho / sum;
+        }
+        break;
+    case ST_RR:
+        st->rr = sum;
+        st->its += 1;
+        if (!(sum == sum) || sum > 1.7e308) {
+            st->status = 7;
+            st->done = 1;
+        } else if (sum <= st->rtol2 * st->bb) {
+            st->done = 1;
+        } else if (st->its >= st->max_it) {
+            st->status = 6;
+            st->done = 1;
+        }
+        break;
+    case ST_BETA:
+        st->beta = sum / st->rho;
+        st->rho = sum;
+        break;
+    case ST_TT:
+        st->tt = sum;
+        break;
+    }
+}
+
+// clear the restart flag after a p-update has consumed it
+__global__ void k_clear_restart(PcgState *st) {
+    if (threadIdx.x == 0 && !st->done) st->restart = 0;
+}
+
+// ================================================================ layout and setup kernels
+// natural (N,N,N) FP64 -> padded V; boundary entries written as 0
+template <typename V>
+__global__ __launch_bounds__(256) void k_to_padded(int n, int pitch, const double *__restrict__ src,
+                                                   V *__restrict__ dst) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long tot = (long long)n * n * n;
+    if (idx >= tot) return;
+    const int i = (int)(idx % n), j = (int)((idx / n) % n), k = (int)(idx / ((long long)n * n));
+    const bool in = i >= 1 && j >= 1 && k >= 1 && i <= n - 2 && j <= n - 2 && k <= n - 2;
+    dst[((long long)k * n + j) * pitch + i] = in ? (V)src[idx] : V(0);
+}
+// padded V -> natural FP64 (boundary 0)
+template <typename V>
+__global__ __launch_bounds__(256) void k_to_natural(int n, int pitch, const V *__restrict__ src,
+                                                    double *__restrict__ dst) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long tot = (long long)n * n * n;
+    if (idx >= tot) return;
+    const int i = (int)(idx % n), j = (int)((idx / n) % n), k = (int)(idx / ((long long)n * n));
+    const bool in = i >= 1 && j >= 1 && k >= 1 && i <= n - 2 && j <= n - 2 && k <= n - 2;
+    dst[idx] = in ? (double)src[((long long)k * n + j) * pitch + i] : 0.0;
+}
+
+// Caller's face arrays (natural shapes, k or ln k) -> padded FP64 level-0
+// coefficients.  Active links must be positive and finite; partial[wg] counts
+// the violations.  Inactive links are stored as 0.
+__global__ __launch_bounds__(256) void k_faces_in(int n, int pitch, const double *__restrict__ kx,
+                                                  const double *__restrict__ ky, const double *__restrict__ kz,
+                                                  int is_log, double *__restrict__ px, double *__restrict__ py,
+                                                  double *__restrict__ pz, double *__restrict__ partial) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long tot = (long long)n * n * n;
+    double bad = 0.0;
+    if (idx < tot) {
+        const int i = (int)(idx % n), j = (int)((idx / n) % n), k = (int)(idx / ((long long)n * n));
+        const long long o = ((long long)k * n + j) * pitch + i;
+        const bool ij = j >= 1 && j <= n - 2, ik = k >= 1 && k <= n - 2, ii = i >= 1 && i <= n - 2;
+        double v;
+        // x link (i,i+1): active if j, k interior
+        v = 0.0;
+        if (i <= n - 2) {
+            v = kx[((long long)k * n + j) * (n - 1) + i];
+            if (is_log) v = exp(v);
+            if (ij && ik) {
+                if (!(v > 0.0) || v > 1.7e308) bad += 1.0;
+            } else {
+                v = 0.0;
+            }
+        }
+        px[o] = v;
+        v = 0.0;
+        if (j <= n - 2) {
+            v = ky[((long long)k * (n - 1) + j) * n + i];
+            if (is_log) v = exp(v);
+            if (ii && ik) {
+                if (!(v > 0.0) || v > 1.7e308) bad += 1.0;
+            } else {
+                v = 0.0;
+            }
+        }
+        py[o] = v;
+        v = 0.0;
+        if (k <= n - 2) {
+            v = kz[((long long)k * n + j) * n + i];
+            if (is_log) v = exp(v);
+            if (ii && ij) {
+                if (!(v > 0.0) || v > 1.7e308) bad += 1.0;
+            } else {
+                v = 0.0;
+            }
+        }
+        pz[o] = v;
+    }
+    const double s = block_sum<256>(bad);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// Coarse link coefficients from the fine level (both padded FP64): the two
+// fine links along the coarse link combine by `rule` (0: (p+q)/2, 1:
+// 2pq/(p+q)); the 3x3 lines around it are weighted (1/4,1/2,1/4)^2, summed
+// with b (outer) then a (inner) in increasing order.
+__device__ __forceinline__ double along_rule(int rule, double p, double q) {
+    if (rule == 1) return (p + q) > 0.0 ? 2.0 * p * q / (p + q) : 0.0;
+    return 0.5 * (p + q);
+}
+__global__ __launch_bounds__(256) void k_coarsen(int n, int pitch, long long plane, const double *__restrict__ fx,
+                                                 const double *__restrict__ fy, const double *__restrict__ fz, int nc,
+                                                 int pc, long long plc, double *__restrict__ cx,
+                                                 double *__restrict__ cy, double *__restrict__ cz, int rule) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long tot = (long long)nc * nc * nc;
+    if (idx >= tot) return;
+    const int I = (int)(idx % nc), J = (int)((idx / nc) % nc), K_ = (int)(idx / ((long long)nc * nc));
+    const long long oc = (long long)K_ * plc + (long long)J * pc + I;
+    const double w[3] = {0.25, 0.5, 0.25};
+    const bool iI = I >= 1 && I <= nc - 2, iJ = J >= 1 && J <= nc - 2, iK = K_ >= 1 && K_ <= nc - 2;
+    auto fo = [&](int i, int j, int k) { return (long long)k * plane + (long long)j * pitch + i; };
+    double v = 0.0;
+    if (I <= nc - 2 && iJ && iK) {
+        for (int b = -1; b <= 1; ++b)
+            for (int a = -1; a <= 1; ++a)
+                v += w[a + 1] * w[b + 1] *
+                     along_rule(rule, fx[fo(2 * I, 2 * J + a, 2 * K_ + b)], fx[fo(2 * I + 1, 2 * J + a, 2 * K_ + b)]);
+    }
+    cx[oc] = v;
+    v = 0.0;
+    if (J <= nc - 2 && iI && iK) {
+        for (int b = -1; b <= 1; ++b)
+            for (int a = -1; a <= 1; ++a)
+                v += w[a + 1] * w[b + 1] *
+                     along_rule(rule, fy[fo(2 * I + a, 2 * J, 2 * K_ + b)], fy[fo(2 * I + a, 2 * J + 1, 2 * K_ + b)]);
+    }
+    cy[oc] = v;
+    v = 0.0;
+    if (K_ <= nc - 2 && iI && iJ) {
+        for (int b = -1; b <= 1; ++b)
+            for (int a = -1; a <= 1; ++a)
+                v += w[a + 1] * w[b + 1] *
+                     along_rule(rule, fz[fo(2 * I + a, 2 * J + b, 2 * K_)], fz[fo(2 * I + a, 2 * J + b, 2 * K_ + 1)]);
+    }
+    cz[oc] = v;
+}
+
+__global__ __launch_bounds__(256) void k_to_bf16(long long nel, const double *__restrict__ src, bf16 *__restrict__ dst) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nel; e += stride)
+        dst[e] = f64_to_bf16_rne(src[e]);
+}
+
+// padded level coefficients (any K) -> natural face shapes, FP64
+template <typename K>
+__global__ __launch_bounds__(256) void k_faces_out(int n, int pitch, const K *__restrict__ px,
+                                                   const K *__restrict__ py, const K *__restrict__ pz,
+                                                   double *__restrict__ kx, double *__restrict__ ky,
+                                                   double *__restrict__ kz) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long tot = (long long)n * n * n;
+    if (idx >= tot) return;
+    const int i = (int)(idx % n), j = (int)((idx / n) % n), k = (int)(idx / ((long long)n * n));
+    const long long o = ((long long)k * n + j) * pitch + i;
+    if (i <= n - 2) kx[((long long)k * n + j) * (n - 1) + i] = (double)kval(px[o]);
+    if (j <= n - 2) ky[((long long)k * (n - 1) + j) * n + i] = (double)kval(py[o]);
+    if (k <= n - 2) kz[((long long)k * n + j) * n + i] = (double)kval(pz[o]);
+}
+
+// Adjoint link gradient: for every active link (p,q)
+//   g = -h^-2 k (lam_p - lam_q)(phi_p - phi_q)     (= dL/d ln k)
+// lam: padded FP64 (boundary 0); phi: caller's natural array (boundary read as 0);
+// k: padded FP64 level-0 coefficients.  One thread per vertex p = lower end.
+__global__ __launch_bounds__(256) void k_face_gradient(int n, int pitch, double s, const double *__restrict__ lam,
+                                                       const double *__restrict__ phi, const double *__restrict__ px,
+                                                       const double *__restrict__ py, const double *__restrict__ pz,
+                                                       double *__restrict__ gx, double *__restrict__ gy,
+                                                       double *__restrict__ gz) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long tot = (long long)n * n * n;
+    if (idx >= tot) return;
+    const int i = (int)(idx % n), j = (int)((idx / n) % n), k = (int)(idx / ((long long)n * n));
+    const long long o = ((long long)k * n + j) * pitch + i;
+    auto inner = [&](int a, int b, int c) { return a >= 1 && b >= 1 && c >= 1 && a <= n - 2 && b <= n - 2 && c <= n - 2; };
+    const bool pin = inner(i, j, k);
+    const double lp = lam[o];
+    const double fp = pin ? phi[idx] : 0.0;
+    if (i <= n - 2) {
+        double g = 0.0;
+        const bool qin = inner(i + 1, j, k);
+        if (pin || qin) {
+            const double fq = qin ? phi[idx + 1] : 0.0;
+            g = -s * px[o] * ((lp - lam[o + 1]) * (fp - fq));
+        }
+        gx[((long long)k * n + j) * (n - 1) + i] = g;
+    }
+    if (j <= n - 2) {
+        double g = 0.0;
+        const bool qin = inner(i, j + 1, k);
+        if (pin || qin) {
+            const double fq = qin ? phi[idx + n] : 0.0;
+            g = -s * py[o] * ((lp - lam[o + pitch]) * (fp - fq));
+        }
+        gy[((long long)k * (n - 1) + j) * n + i] = g;
+    }
+    if (k <= n - 2) {
+        double g = 0.0;
+        const bool qin = inner(i, j, k + 1);
+        if (pin || qin) {
+            const double fq = qin ? phi[idx + (long long)n * n] : 0.0;
+            g = -s * pz[o] * ((lp - lam[o + (long long)n * pitch]) * (fp - fq));
+        }
+        gz[((long long)k * n + j) * n + i] = g;
+    }
+}
+
+// flat copy / cast between two padded arrays of the same level
+template <typename A, typename B>
+__global__ __launch_bounds__(NT_FLAT) void k_cast(long long nel, const A *__restrict__ src, B *__restrict__ dst,
+                                                  const int *__restrict__ skip) {
+    if (skip && *skip) return;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nel; e += stride) dst[e] = (B)src[e];
+}
+
+}  // namespace gmg

@@ -1,0 +1,305 @@
+"""ctypes binding of libgmg.so (the C ABI in include/gmg.h).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels.  Tensors are torch CUDA (HIP) tensors, float64, contiguous; the
+library works on torch's current stream.  If the library is not built the
+first call raises -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgmg.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "gmg.h")
+
+STATUS = {0: "GMG_OK", 1: "GMG_ERR_ARG", 2: "GMG_ERR_DIMS", 3: "GMG_ERR_COEFF", 4: "GMG_ERR_NOMEM",
+          5: "GMG_ERR_HIP", 6: "GMG_ERR_NOT_CONVERGED", 7: "GMG_ERR_BREAKDOWN"}
+OK, ERR_NOT_CONVERGED, ERR_BREAKDOWN = 0, 6, 7
+FP64, MIXED = 0, 1
+COARSE_ARITHMETIC, COARSE_HARMONIC = 0, 1
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("levels", ctypes.c_int32), ("cheb_degree", ctypes.c_int32),
+                ("cheb_lo", ctypes.c_double), ("cheb_hi", ctypes.c_double), ("switch_n", ctypes.c_int32),
+                ("persistent_wgs", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("coarse_rule", ctypes.c_int32), ("coeff_is_log", ctypes.c_int32),
+                ("check_every", ctypes.c_int32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("restarts", ctypes.c_int32), ("rel_res", ctypes.c_double),
+                ("rel_res_true", ctypes.c_double), ("setup_ms", ctypes.c_double), ("solve_ms", ctypes.c_double)]
+
+    def as_dict(self, status: int):
+        return {"status": STATUS.get(status, str(status)), "iterations": self.iterations,
+                "restarts": self.restarts, "rel_res": self.rel_res, "rel_res_true": self.rel_res_true,
+                "setup_ms": self.setup_ms, "solve_ms": self.solve_ms}
+
+
+class GmgError(RuntimeError):
+    def __init__(self, status: int, msg: str = ""):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def declared_functions():
+    """Names of the functions include/gmg.h declares."""
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gmg_[a-z_0-9]+)\s*\(", src)))
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1604_07163_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    st = ctypes.c_int
+    L.gmg_default_options.argtypes = [ctypes.POINTER(Options), I32]
+    L.gmg_default_options.restype = None
+    L.gmg_create.argtypes = [ctypes.POINTER(Options), P, P, P, P, ctypes.POINTER(P)]
+    L.gmg_create.restype = st
+    L.gmg_set_coefficients.argtypes = [P, P, P, P]
+    L.gmg_set_coefficients.restype = st
+    L.gmg_set_stream.argtypes = [P, P]
+    L.gmg_set_stream.restype = st
+    L.gmg_solve.argtypes = [P, P, P, P, D, I32, ctypes.POINTER(Info)]
+    L.gmg_solve.restype = st
+    L.gmg_adjoint_gradient.argtypes = [P, P, P, P, P, P, P, D, I32, ctypes.POINTER(Info)]
+    L.gmg_adjoint_gradient.restype = st
+    L.gmg_level_n.argtypes = [P, I32]
+    L.gmg_level_n.restype = I32
+    L.gmg_apply_operator.argtypes = [P, I32, I32, P, P]
+    L.gmg_apply_operator.restype = st
+    L.gmg_debug_smooth.argtypes = [P, I32, P, P, I32]
+    L.gmg_debug_smooth.restype = st
+    L.gmg_debug_residual_restrict.argtypes = [P, I32, P, P, P]
+    L.gmg_debug_residual_restrict.restype = st
+    L.gmg_debug_prolong.argtypes = [P, I32, P, P]
+    L.gmg_debug_prolong.restype = st
+    L.gmg_debug_coarse_solve.argtypes = [P, P, P]
+    L.gmg_debug_coarse_solve.restype = st
+    L.gmg_debug_vcycle.argtypes = [P, P, P]
+    L.gmg_debug_vcycle.restype = st
+    L.gmg_get_level_coefficients.argtypes = [P, I32, P, P, P]
+    L.gmg_get_level_coefficients.restype = st
+    L.gmg_destroy.argtypes = [P]
+    L.gmg_destroy.restype = None
+    L.gmg_status_string.argtypes = [st]
+    L.gmg_status_string.restype = ctypes.c_char_p
+    L.gmg_last_error.argtypes = [P]
+    L.gmg_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _dev(t: torch.Tensor, name: str):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float64 tensor on the GPU")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def face_shapes(n: int):
+    return (n, n, n - 1), (n, n - 1, n), (n - 1, n, n)
+
+
+def default_levels(n: int) -> int:
+    lv, t = 0, n - 1
+    while t > 1 and t % 2 == 0:
+        lv += 1
+        t //= 2
+    return max(lv, 1)
+
+
+class Solver:
+    """A hierarchy on the GPU plus its solver state (one handle)."""
+
+    def __init__(self, kx, ky, kz, *, levels=None, precision="fp64", switch_n=0, coarse_rule="arithmetic",
+                 cheb_degree=2, cheb_lo=0.25, cheb_hi=2.0, coeff_is_log=False, check_every=0,
+                 persistent_wgs=1):
+        L = lib()
+        n = int(kx.shape[0])
+        self.n = n
+        o = Options()
+        L.gmg_default_options(ctypes.byref(o), n)
+        o.levels = default_levels(n) if levels is None else int(levels)
+        o.cheb_degree = cheb_degree
+        o.cheb_lo = cheb_lo
+        o.cheb_hi = cheb_hi
+        o.switch_n = int(switch_n)
+        o.persistent_wgs = int(persistent_wgs)
+        o.precision = {"fp64": FP64, "mixed": MIXED}[precision] if isinstance(precision, str) else int(precision)
+        o.coarse_rule = ({"arithmetic": COARSE_ARITHMETIC, "harmonic": COARSE_HARMONIC}[coarse_rule]
+                         if isinstance(coarse_rule, str) else int(coarse_rule))
+        o.coeff_is_log = 1 if coeff_is_log else 0
+        o.check_every = int(check_every)
+        self.options = o
+        self.levels = o.levels
+        self._h = ctypes.c_void_p()
+        self._check_faces(kx, ky, kz)
+        stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        s = L.gmg_create(ctypes.byref(o), _dev(kx, "kx"), _dev(ky, "ky"), _dev(kz, "kz"), stream,
+                         ctypes.byref(self._h))
+        if s != OK:
+            raise GmgError(s, "gmg_create")
+        self.version = 0
+
+    # ------------------------------------------------------------------ helpers
+    def _check_faces(self, kx, ky, kz):
+        for t, shp, nm in zip((kx, ky, kz), face_shapes(self.n), ("kx", "ky", "kz")):
+            if tuple(t.shape) != shp:
+                raise ValueError(f"{nm} must have shape {shp}, got {tuple(t.shape)}")
+
+    def _vec(self, t, name, level=0):
+        n = self.level_n(level)
+        if tuple(t.shape) != (n, n, n):
+            raise ValueError(f"{name} must have shape {(n, n, n)}")
+        return _dev(t, name)
+
+    def _err(self, s, what):
+        msg = lib().gmg_last_error(self._h)
+        raise GmgError(s, f"{what}: {msg.decode() if msg else ''}")
+
+    def _sync_stream(self):
+        lib().gmg_set_stream(self._h, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+
+    def _empty(self, n):
+        return torch.empty((n, n, n), dtype=torch.float64, device="cuda")
+
+    # ------------------------------------------------------------------ API
+    def close(self):
+        if self._h:
+            lib().gmg_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def level_n(self, level: int) -> int:
+        return lib().gmg_level_n(self._h, level)
+
+    def set_coefficients(self, kx, ky, kz):
+        self._check_faces(kx, ky, kz)
+        self._sync_stream()
+        s = lib().gmg_set_coefficients(self._h, _dev(kx, "kx"), _dev(ky, "ky"), _dev(kz, "kz"))
+        if s != OK:
+            self._err(s, "gmg_set_coefficients")
+        self.version += 1
+
+    def solve(self, f, rtol=1e-8, max_it=500, x0=None, out=None, raise_on_failure=False):
+        """Returns (x, info).  info["status"] is GMG_OK, GMG_ERR_NOT_CONVERGED or GMG_ERR_BREAKDOWN."""
+        self._sync_stream()
+        x = self._empty(self.n) if out is None else out
+        info = Info()
+        s = lib().gmg_solve(self._h, self._vec(f, "f"), self._vec(x, "x"),
+                            None if x0 is None else self._vec(x0, "x0"), float(rtol), int(max_it),
+                            ctypes.byref(info))
+        if s not in (OK, ERR_NOT_CONVERGED, ERR_BREAKDOWN) or (raise_on_failure and s != OK):
+            self._err(s, "gmg_solve")
+        return x, info.as_dict(s)
+
+    def adjoint_gradient(self, phi, dl_dphi, rtol=1e-10, max_it=500, want_lambda=True):
+        """Returns (g_x, g_y, g_z, lambda, info): g = dL/d(ln k) on the three link arrays."""
+        self._sync_stream()
+        sx, sy, sz = face_shapes(self.n)
+        gx = torch.empty(sx, dtype=torch.float64, device="cuda")
+        gy = torch.empty(sy, dtype=torch.float64, device="cuda")
+        gz = torch.empty(sz, dtype=torch.float64, device="cuda")
+        lam = self._empty(self.n) if want_lambda else None
+        info = Info()
+        s = lib().gmg_adjoint_gradient(self._h, self._vec(phi, "phi"), self._vec(dl_dphi, "dl_dphi"),
+                                       _dev(gx, "g_x"), _dev(gy, "g_y"), _dev(gz, "g_z"),
+                                       None if lam is None else self._vec(lam, "lambda"), float(rtol),
+                                       int(max_it), ctypes.byref(info))
+        if s not in (OK, ERR_NOT_CONVERGED, ERR_BREAKDOWN):
+            self._err(s, "gmg_adjoint_gradient")
+        return gx, gy, gz, lam, info.as_dict(s)
+
+    # ------------------------------------------------------------------ test hooks
+    def apply_operator(self, level, x, use_fp64=False):
+        self._sync_stream()
+        y = self._empty(self.level_n(level))
+        s = lib().gmg_apply_operator(self._h, level, 1 if use_fp64 else 0, self._vec(x, "x", level),
+                                     _dev(y, "y"))
+        if s != OK:
+            self._err(s, "gmg_apply_operator")
+        return y
+
+    def smooth(self, level, b, x0=None):
+        self._sync_stream()
+        n = self.level_n(level)
+        x = torch.zeros((n, n, n), dtype=torch.float64, device="cuda") if x0 is None else x0.clone()
+        s = lib().gmg_debug_smooth(self._h, level, self._vec(b, "b", level), _dev(x, "x"),
+                                   1 if x0 is None else 0)
+        if s != OK:
+            self._err(s, "gmg_debug_smooth")
+        return x
+
+    def residual_restrict(self, level, b, x):
+        self._sync_stream()
+        bc = self._empty(self.level_n(level + 1))
+        s = lib().gmg_debug_residual_restrict(self._h, level, self._vec(b, "b", level), self._vec(x, "x", level),
+                                              _dev(bc, "b_coarse"))
+        if s != OK:
+            self._err(s, "gmg_debug_residual_restrict")
+        return bc
+
+    def prolong(self, level, e, x):
+        self._sync_stream()
+        out = x.clone()
+        s = lib().gmg_debug_prolong(self._h, level, self._vec(e, "e", level + 1), self._vec(out, "x", level))
+        if s != OK:
+            self._err(s, "gmg_debug_prolong")
+        return out
+
+    def coarse_solve(self, b):
+        self._sync_stream()
+        lc = self.levels - 1
+        x = self._empty(self.level_n(lc))
+        s = lib().gmg_debug_coarse_solve(self._h, self._vec(b, "b", lc), _dev(x, "x"))
+        if s != OK:
+            self._err(s, "gmg_debug_coarse_solve")
+        return x
+
+    def vcycle(self, r):
+        self._sync_stream()
+        z = self._empty(self.n)
+        s = lib().gmg_debug_vcycle(self._h, self._vec(r, "r"), _dev(z, "z"))
+        if s != OK:
+            self._err(s, "gmg_debug_vcycle")
+        return z
+
+    def level_coefficients(self, level):
+        self._sync_stream()
+        n = self.level_n(level)
+        sx, sy, sz = face_shapes(n)
+        kx = torch.empty(sx, dtype=torch.float64, device="cuda")
+        ky = torch.empty(sy, dtype=torch.float64, device="cuda")
+        kz = torch.empty(sz, dtype=torch.float64, device="cuda")
+        s = lib().gmg_get_level_coefficients(self._h, level, _dev(kx, "kx"), _dev(ky, "ky"), _dev(kz, "kz"))
+        if s != OK:
+            self._err(s, "gmg_get_level_coefficients")
+        return kx, ky, kz
+
+
+def raw_create(options: Options, kx, ky, kz):
+    """gmg_create with an explicit options struct; returns (status, handle)."""
+    h = ctypes.c_void_p()
+    s = lib().gmg_create(ctypes.byref(options), _dev(kx, "kx"), _dev(ky, "ky"), _dev(kz, "kz"),
+                         ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), ctypes.byref(h))
+    return s, h

@@ -1,0 +1,153 @@
+"""Kernel-level parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Sizes span several x tiles (64 wide) and y tiles (4 rows), ragged last tiles
+(N = 81, 161) and the small levels that the persistent kernel handles.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1604_07163_amd import gmg, inputs
+from tests.gpu_util import bf16_rne, rand_vec, rel_max, say, to_gpu, to_np
+
+pytestmark = pytest.mark.gpu
+
+CASES = [(17, 4), (33, 5), (81, 5), (161, 6)]
+
+
+def make(n, levels, seed=2, precision="fp64", **kw):
+    k = inputs.lognormal_k(n, seed, width=3.0)
+    say(f"  case n={n} levels={levels} precision={precision} {kw}")
+    s = gmg.Solver(*[to_gpu(a) for a in k], levels=levels, precision=precision, **kw)
+    H = oracle.Hierarchy(*k, levels=levels)
+    return k, s, H
+
+
+@pytest.mark.parametrize("n,levels", CASES)
+def test_apply_fp64(n, levels):
+    k, s, H = make(n, levels)
+    u = rand_vec(n, 1)
+    ref = oracle.apply(*k, u)
+    for use64 in (True, False):
+        got = to_np(s.apply_operator(0, to_gpu(u), use_fp64=use64))
+        assert rel_max(got, ref) <= 1e-14, (use64, rel_max(got, ref))
+        assert np.all(got[0] == 0) and np.all(got[:, :, -1] == 0)
+
+
+def active_masks(n):
+    """Links with at least one interior end point: transverse indices interior."""
+    sx, sy, sz = inputs.face_shapes(n)
+    mx, my, mz = np.zeros(sx, bool), np.zeros(sy, bool), np.zeros(sz, bool)
+    mx[1:-1, 1:-1, :] = True
+    my[1:-1, :, 1:-1] = True
+    mz[:, 1:-1, 1:-1] = True
+    return mx, my, mz
+
+
+@pytest.mark.parametrize("n,levels", CASES)
+def test_coarse_coefficients_bitwise(n, levels):
+    k, s, H = make(n, levels)
+    for l in range(levels):
+        g = [to_np(t) for t in s.level_coefficients(l)]
+        o = H.level_k(l)
+        for a, b, m in zip(g, o, active_masks(H.level_n(l))):
+            np.testing.assert_array_equal(a[m], b[m])
+            assert np.all(a[~m] == 0)
+
+
+@pytest.mark.parametrize("n,levels", CASES)
+def test_level_operations_fp64(n, levels):
+    k, s, H = make(n, levels)
+    for l in range(levels - 1):
+        nl = H.level_n(l)
+        kl = H.level_k(l)
+        b, x0 = rand_vec(nl, 10 + l), rand_vec(nl, 20 + l)
+        # operator on level l
+        got = to_np(s.apply_operator(l, to_gpu(x0)))
+        assert rel_max(got, oracle.apply(*kl, x0)) <= 1e-14
+        # smoothing from zero and from x0
+        assert rel_max(to_np(s.smooth(l, to_gpu(b))), H.smooth(l, b)) <= 1e-13
+        assert rel_max(to_np(s.smooth(l, to_gpu(b), to_gpu(x0))), H.smooth(l, b, x0)) <= 1e-13
+        # residual + full weighting
+        ref = oracle.restrict(b - H.apply(l, x0))
+        assert rel_max(to_np(s.residual_restrict(l, to_gpu(b), to_gpu(x0))), ref) <= 1e-13
+        # trilinear prolongation + correction
+        e = rand_vec(H.level_n(l + 1), 30 + l)
+        assert rel_max(to_np(s.prolong(l, to_gpu(e), to_gpu(x0))), oracle.prolong_add(e, x0)) <= 1e-15
+
+
+@pytest.mark.parametrize("n,levels", [(17, 3), (33, 4), (81, 4), (161, 5)])
+def test_coarsest_cholesky(n, levels):
+    k, s, H = make(n, levels)
+    nc = H.level_n(levels - 1)
+    b = rand_vec(nc, 5)
+    assert rel_max(to_np(s.coarse_solve(to_gpu(b))), H.coarse_solve(b)) <= 1e-12
+
+
+@pytest.mark.parametrize("n,levels", CASES)
+def test_vcycle_and_switch_invariance(n, levels):
+    k, s, H = make(n, levels)
+    r = rand_vec(n, 3)
+    ref = H.vcycle(r)
+    base = to_np(s.vcycle(to_gpu(r)))
+    assert rel_max(base, ref) <= 1e-12, rel_max(base, ref)
+    sizes = sorted({H.level_n(l) for l in range(1, levels)})
+    for sw in sizes:
+        sp = gmg.Solver(*[to_gpu(a) for a in k], levels=levels, switch_n=sw)
+        z = to_np(sp.vcycle(to_gpu(r)))
+        d = rel_max(z, base)
+        say(f"    switch {sw}: max rel diff vs grid path {d:.3e} (bitwise: {np.array_equal(z, base)})")
+        assert d <= 1e-14
+
+
+def test_bf16_coefficients_round_to_nearest_even():
+    n, levels = 33, 5
+    k, s, H = make(n, levels, precision="mixed")
+    for l in range(levels):
+        g = [to_np(t) for t in s.level_coefficients(l)]
+        o = H.level_k(l)
+        for a, b, m in zip(g, o, active_masks(H.level_n(l))):
+            np.testing.assert_array_equal(a[m], bf16_rne(b[m]))
+
+
+@pytest.mark.parametrize("n,levels", [(33, 5), (81, 5)])
+def test_mixed_level_operations(n, levels):
+    """FP32 arithmetic with BF16 links vs the FP64 oracle fed the same BF16 links."""
+    k, s, H = make(n, levels, precision="mixed")
+    for l in range(levels - 1):
+        nl = H.level_n(l)
+        kl = [to_np(t) for t in s.level_coefficients(l)]
+        b = rand_vec(nl, 40 + l).astype(np.float32).astype(np.float64)
+        x0 = rand_vec(nl, 50 + l).astype(np.float32).astype(np.float64)
+        assert rel_max(to_np(s.apply_operator(l, to_gpu(x0))), oracle.apply(*kl, x0)) <= 2e-6
+        ref = oracle.cheb(*kl, b, x0=x0)
+        assert rel_max(to_np(s.smooth(l, to_gpu(b), to_gpu(x0))), ref) <= 2e-6
+        ref = oracle.restrict(b - oracle.apply(*kl, x0))
+        assert rel_max(to_np(s.residual_restrict(l, to_gpu(b), to_gpu(x0))), ref) <= 2e-6
+
+
+def test_errors_are_reported():
+    n = 17
+    k = inputs.const_k(n)
+    kg = [to_gpu(a) for a in k]
+    o = gmg.Options()
+    gmg.lib().gmg_default_options(o, n)
+    o.levels = 6  # 16 not divisible by 32
+    st, h = gmg.raw_create(o, *kg)
+    assert st == 2 and not h.value
+    o.levels = 3
+    bad = k[0].copy()
+    bad[4, 4, 4] = -1.0
+    st, h = gmg.raw_create(o, to_gpu(bad), kg[1], kg[2])
+    assert st == 3
+    bad[4, 4, 4] = np.nan
+    st, h = gmg.raw_create(o, to_gpu(bad), kg[1], kg[2])
+    assert st == 3
+    s = gmg.Solver(*kg, levels=3)
+    x, info = s.solve(to_gpu(inputs.uniform_rhs(n, 1)), rtol=1e-12, max_it=1)
+    assert info["status"] == "GMG_ERR_NOT_CONVERGED" and info["iterations"] == 1
+    x, info = s.solve(torch.zeros((n, n, n), dtype=torch.float64, device="cuda"))
+    assert info["status"] == "GMG_OK" and info["iterations"] == 0 and float(x.abs().max()) == 0.0
+    with pytest.raises(gmg.GmgError):
+        s.solve(to_gpu(np.full((n, n, n), np.nan)))

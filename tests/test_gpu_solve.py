@@ -1,0 +1,135 @@
+"""Solve-level parity of the HIP path with the FP64 CPU oracle (through the C ABI).
+
+Parity reading for an iterative solve: with the same rtol the iteration counts
+differ by at most 1; forced to the oracle's iteration count (rtol = 0,
+max_it = its), the two iterates agree to a relative 2-norm difference of 1e-10.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1604_07163_amd import gmg, inputs
+from tests.gpu_util import rel_l2, rel_max, say, to_gpu, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def solve_both(k, f, levels, rtol=1e-8, **kw):
+    n = k[0].shape[0]
+    say(f"  solve n={n} levels={levels} {kw}")
+    H = oracle.Hierarchy(*k, levels=levels)
+    xo, io = H.solve(f, rtol=rtol)
+    s = gmg.Solver(*[to_gpu(a) for a in k], levels=levels, **kw)
+    fg = to_gpu(f)
+    xg, ig = s.solve(fg, rtol=rtol)
+    say(f"    oracle its={io['iterations']} gpu its={ig['iterations']} "
+        f"gpu rel_res={ig['rel_res']:.3e} true={ig['rel_res_true']:.3e} ms={ig['solve_ms']:.2f}")
+    return H, s, fg, xo, io, to_np(xg), ig
+
+
+def forced_parity(s, fg, xo, its, **kw):
+    xg, ig = s.solve(fg, rtol=0.0, max_it=its)
+    assert ig["iterations"] == its
+    d = rel_l2(to_np(xg), xo)
+    say(f"    forced {its} its: rel diff {d:.3e}")
+    return d
+
+
+def test_poisson33_config():
+    """Config 1: constant k = 1, 33^3, 4 levels (coarsest 5^3 = 27 unknowns, Cholesky),
+    f = 3 pi^2 sin sin sin.  Closed form: the discrete solution is
+    pi^2 h^2 / (4 sin^2(pi h / 2)) * phi."""
+    n, levels = 33, 4
+    k = inputs.const_k(n)
+    f = inputs.sine_rhs(n)
+    H, s, fg, xo, io, xg, ig = solve_both(k, f, levels)
+    assert ig["status"] == "GMG_OK" and abs(ig["iterations"] - io["iterations"]) <= 1
+    assert ig["rel_res_true"] <= 1e-8
+    assert forced_parity(s, fg, xo, io["iterations"]) <= 1e-10
+    h = 1.0 / (n - 1)
+    exact = np.pi ** 2 * h ** 2 / (4 * np.sin(np.pi * h / 2) ** 2) * inputs.sine_solution(n)
+    assert rel_max(xg, exact) <= 1e-7
+    # second-order discretization error against the continuous solution
+    err = np.abs(xg - inputs.sine_solution(n)).max()
+    assert abs(err - np.pi ** 2 * h ** 2 / 12) < 1e-5
+
+
+@pytest.mark.parametrize("n", [65, 129])
+@pytest.mark.parametrize("switch_n", [0, 17])
+def test_lognormal_solves(n, switch_n):
+    levels = int(np.log2(n - 1))
+    k = inputs.lognormal_k(n, 2, width=8.0, clip=2.0)
+    f = inputs.uniform_rhs(n, 3)
+    H, s, fg, xo, io, xg, ig = solve_both(k, f, levels, switch_n=switch_n)
+    assert ig["status"] == "GMG_OK" and abs(ig["iterations"] - io["iterations"]) <= 1
+    assert ig["rel_res_true"] <= 1e-8
+    assert forced_parity(s, fg, xo, io["iterations"]) <= 1e-10
+
+
+@pytest.mark.parametrize("rule", ["arithmetic", "harmonic"])
+def test_inclusions_65(rule):
+    n, levels = 65, 6
+    kx, ky, kz, _ = inputs.inclusion_k(n, 4)
+    f = inputs.uniform_rhs(n, 5)
+    r = oracle.RULE_ARITHMETIC if rule == "arithmetic" else oracle.RULE_HARMONIC
+    H = oracle.Hierarchy(kx, ky, kz, levels=levels, rule=r)
+    xo, io = H.solve(f, rtol=1e-8, max_it=400)
+    s = gmg.Solver(*[to_gpu(a) for a in (kx, ky, kz)], levels=levels, coarse_rule=rule)
+    fg = to_gpu(f)
+    xg, ig = s.solve(fg, rtol=1e-8, max_it=400)
+    say(f"    rule={rule} oracle its={io['iterations']} gpu its={ig['iterations']}")
+    assert abs(ig["iterations"] - io["iterations"]) <= 1
+    assert forced_parity(s, fg, xo, io["iterations"]) <= 1e-10
+
+
+def test_initial_guess_and_determinism():
+    n, levels = 65, 6
+    k = inputs.lognormal_k(n, 2, width=4.0)
+    f = inputs.uniform_rhs(n, 3)
+    s = gmg.Solver(*[to_gpu(a) for a in k], levels=levels)
+    fg = to_gpu(f)
+    x1, i1 = s.solve(fg)
+    x2, i2 = s.solve(fg)
+    assert torch.equal(x1, x2) and i1["iterations"] == i2["iterations"]
+    # warm start from the solution: converged at once
+    x3, i3 = s.solve(fg, x0=x1)
+    assert i3["iterations"] <= 1 and i3["rel_res_true"] <= 1e-8
+
+
+def test_mixed_precision_solve():
+    n, levels = 129, 7
+    kx, ky, kz, _ = inputs.inclusion_k(n, 4)
+    f = inputs.uniform_rhs(n, 5)
+    kg = [to_gpu(a) for a in (kx, ky, kz)]
+    fg = to_gpu(f)
+    s64 = gmg.Solver(*kg, levels=levels)
+    x64, i64 = s64.solve(fg, rtol=1e-8, max_it=1000)
+    smx = gmg.Solver(*kg, levels=levels, precision="mixed")
+    xmx, imx = smx.solve(fg, rtol=1e-8, max_it=1000)
+    H = oracle.Hierarchy(kx, ky, kz, levels=levels)
+    xo, io = H.solve(f, rtol=1e-8, max_it=1000)
+    say(f"    fp64 its={i64['iterations']} mixed its={imx['iterations']} restarts={imx['restarts']} "
+        f"oracle its={io['iterations']}; mixed true res {imx['rel_res_true']:.3e}; "
+        f"err vs oracle fp64 {rel_l2(to_np(x64), xo):.3e} mixed {rel_l2(to_np(xmx), xo):.3e}")
+    assert imx["status"] == "GMG_OK" and imx["rel_res_true"] <= 1e-8
+    assert imx["iterations"] <= i64["iterations"] + 2 + i64["iterations"] // 10
+
+
+def test_adjoint_gradient_vs_oracle():
+    n, levels = 33, 5
+    k = inputs.lognormal_k(n, 6, width=3.0)
+    kobs = inputs.lognormal_k(n, 7, width=3.0)
+    f = inputs.uniform_rhs(n, 8)
+    Hobs = oracle.Hierarchy(*kobs, levels=levels)
+    phi_obs, _ = Hobs.solve(f, rtol=1e-13)
+    H = oracle.Hierarchy(*k, levels=levels)
+    phi, _ = H.solve(f, rtol=1e-13)
+    gxo, gyo, gzo, lamo, _ = H.adjoint_gradient(phi, phi - phi_obs, rtol=1e-13)
+    s = gmg.Solver(*[to_gpu(a) for a in k], levels=levels)
+    phig, _ = s.solve(to_gpu(f), rtol=1e-13)
+    gx, gy, gz, lam, info = s.adjoint_gradient(phig, phig - to_gpu(phi_obs), rtol=1e-13)
+    scale = max(np.abs(a).max() for a in (gxo, gyo, gzo))
+    for a, b in ((gx, gxo), (gy, gyo), (gz, gzo)):
+        assert np.abs(to_np(a) - b).max() <= 1e-6 * scale
+    assert rel_max(to_np(lam), lamo) <= 1e-9

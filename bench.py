@@ -1,0 +1,250 @@
+#!/usr/bin/env python3
+"""Benchmark of the multigrid-preconditioned CG hot path on one MI355X.
+
+Workload (default "inclusions513"): -div(k grad phi) = f on a 513^3 vertex grid
+(511^3 = 133,432,831 unknowns), two-phase k (random spheres, radius 4-16 cells,
+20 % volume, k = 1e3 inside, 1 outside), f ~ U(-1,1), 9 levels (coarsest 3^3),
+Chebyshev-Jacobi degree 2 pre/post, levels N <= 17 agglomerated into the
+persistent coarse kernel.
+
+One step = the whole hot path once:
+  hierarchy setup from k  ->  mixed-precision PCG solve to an FP64 relative
+  residual of 1e-8  ->  adjoint gradient dL/d ln k for L = 0.5 ||phi - phi_obs||^2
+  (adjoint PCG solve + link-gradient kernel).
+value = fine-grid unknowns solved per second = 2 solves x 511^3 / step time.
+The same step in plain FP64 is timed beside it (speedup, error).
+
+Inputs are generated on the host and copied to HBM before the timed region.
+Kernel durations come from HIP events the library records around every
+finest-level launch on its stream during the timed steps.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+# Algorithmic HBM bytes per interior fine-grid unknown for each finest-level
+# kernel class: every array read or written once, neighbours from cache.
+BYTES_PER_POINT = {
+    "fp64": {"apply_dot": 40, "residual": 48, "update_xr": 48, "update_p": 24, "cheb_first": 40,
+             "cheb_step": 48, "cheb_step_prev": 56, "cheb_step_dot": 56, "level_residual": 48,
+             "restrict": 9, "prolong": 17, "face_gradient": 64},
+    "mixed": {"apply_dot": 40, "residual": 48, "update_xr": 48, "update_p": 20, "cheb_first": 22,
+              "cheb_step": 18, "cheb_step_prev": 22, "cheb_step_dot": 30, "level_residual": 18,
+              "restrict": 4.5, "prolong": 8.5, "face_gradient": 64},
+}
+
+WORKLOADS = {
+    "inclusions513": dict(n=513, levels=9, kind="inclusions", k_seed=4, kobs_seed=7, f_seed=5,
+                          desc="513^3 two-phase inclusions (k=1e3 in 1, 20% volume, r 4-16 cells), "
+                               "f~U(-1,1), 9 levels, V(2,2) Chebyshev-Jacobi, rtol 1e-8, forward + adjoint"),
+    "lognormal257": dict(n=257, levels=8, kind="lognormal", k_seed=2, kobs_seed=7, f_seed=3, clip=2.0,
+                         desc="257^3 log-normal k (sigma 8 cells, contrast 1e4), f~U(-1,1), 8 levels, "
+                              "V(2,2) Chebyshev-Jacobi, rtol 1e-8, forward + adjoint"),
+    "lognormal1025": dict(n=1025, levels=10, kind="lognormal", k_seed=10, kobs_seed=11, f_seed=12, clip=3.0,
+                          desc="1025^3 log-normal k (contrast 1e6), f~U(-1,1), 10 levels, forward + adjoint"),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_inputs(w):
+    from paper_1604_07163_amd import inputs
+    n = w["n"]
+    if w["kind"] == "inclusions":
+        kx, ky, kz, _ = inputs.inclusion_k(n, w["k_seed"])
+        kox, koy, koz, _ = inputs.inclusion_k(n, w["kobs_seed"])
+    else:
+        kx, ky, kz = inputs.lognormal_k(n, w["k_seed"], clip=w["clip"])
+        kox, koy, koz = inputs.lognormal_k(n, w["kobs_seed"], clip=w["clip"])
+    f = inputs.uniform_rhs(n, w["f_seed"])
+    return (kx, ky, kz), (kox, koy, koz), f
+
+
+def run_steps(solver, k, f, phi_obs, steps, rtol, profile=False):
+    """Time `steps` full steps; returns (seconds per step list, last infos, profile dict)."""
+    import torch
+    from paper_1604_07163_amd import gmg
+    times, fwd, adj, phi = [], None, None, None
+    prof = gmg.Profile(solver) if profile else None
+    if prof:
+        prof.__enter__()
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        solver.set_coefficients(*k)
+        phi, fwd = solver.solve(f, rtol=rtol, max_it=2000)
+        dl = phi - phi_obs  # the loss gradient (user side of the step)
+        gx, gy, gz, lam, adj = solver.adjoint_gradient(phi, dl, rtol=rtol, max_it=2000, want_lambda=False)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    if prof:
+        prof.__exit__(None, None, None)
+    return times, fwd, adj, (prof.result if prof else {}), phi
+
+
+def copy_bandwidth(nbytes=2 << 30, reps=5):
+    """Achievable HBM bandwidth of a plain streaming copy (read + write bytes / time)."""
+    import torch
+    from paper_1604_07163_amd import gmg
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    gmg.calibration_copy(b, a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        gmg.calibration_copy(b, a)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms / 1e3) / 1e9
+
+
+def cpu_baseline(w, k, f, its_needed, iters=2):
+    """Time the FP64 CPU oracle for `iters` PCG iterations at the full size and
+    scale to the iteration count the solve needs (setup not timed)."""
+    import oracle
+    oracle.build(force=False)
+    H = oracle.Hierarchy(*k, levels=w["levels"])
+    t0 = time.perf_counter()
+    _, info = H.solve(f, rtol=1e-8, max_it=iters)
+    dt = time.perf_counter() - t0
+    H.close()
+    per_it = dt / max(info["iterations"], 1)
+    t_solve = per_it * its_needed
+    n_unk = (w["n"] - 2) ** 3
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    return {"value": n_unk / t_solve, "unit": "unknowns/s", "cores": cores, "kind": "oracle",
+            "sample": f"{info['iterations']} FP64 PCG iterations of the oracle at {w['n']}^3 "
+                      f"({dt:.1f} s, setup excluded), scaled to the {its_needed} iterations of one solve",
+            "seconds_per_iteration": per_it}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="inclusions513", choices=sorted(WORKLOADS))
+    ap.add_argument("--switch-n", type=int, default=17)
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison leg")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1).", flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1604_07163_amd import gmg
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w = WORKLOADS[args.workload]
+    n, levels = w["n"], w["levels"]
+    n_unk = (n - 2) ** 3
+    t0 = time.perf_counter()
+    k_np, kobs_np, f_np = make_inputs(w)
+    log(f"inputs generated in {time.perf_counter() - t0:.1f}s")
+    k = [torch.from_numpy(a).cuda() for a in k_np]
+    kobs = [torch.from_numpy(a).cuda() for a in kobs_np]
+    f = torch.from_numpy(f_np).cuda()
+
+    copy_gbs = copy_bandwidth()
+    log(f"plain copy: {copy_gbs:.0f} GB/s")
+    legs = {}
+    results = {}
+    for prec in (["mixed"] if args.no_fp64 else ["mixed", "fp64"]):
+        s = gmg.Solver(*k, levels=levels, precision=prec, switch_n=args.switch_n)
+        # phi_obs: forward solve with the observation coefficients (untimed)
+        s.set_coefficients(*kobs)
+        phi_obs, _ = s.solve(f, rtol=1e-10, max_it=2000)
+        s.set_coefficients(*k)
+        steps = args.steps if prec == "mixed" else max(1, (args.steps + 1) // 2)
+        run_steps(s, k, f, phi_obs, args.warmup, args.rtol)
+        log(f"[{prec}] warmup done; timing {steps} steps")
+        times, fwd, adj, prof, phi = run_steps(s, k, f, phi_obs, steps, args.rtol, profile=True)
+        legs[prec] = {"ms_per_step": 1e3 * float(np.mean(times)), "ms_min": 1e3 * float(np.min(times)),
+                      "forward": fwd, "adjoint": adj, "kernels": prof}
+        results[prec] = phi.clone()
+        log(f"[{prec}] {legs[prec]['ms_per_step']:.1f} ms/step; fwd its {fwd['iterations']} "
+            f"true {fwd['rel_res_true']:.2e}; adj its {adj['iterations']}")
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+
+    mixed = legs["mixed"]
+    ms = mixed["ms_per_step"]
+    value = 2 * n_unk / (ms / 1e3)
+    # dominant finest-level HBM kernel of the mixed step
+    bpp = BYTES_PER_POINT["mixed"]
+    cands = {c: v for c, v in mixed["kernels"].items() if c in bpp}
+    dom = max(cands, key=lambda c: cands[c]["total_ms"])
+    bytes_per_launch = bpp[dom] * n_unk
+    achieved = bytes_per_launch / (cands[dom]["avg_ms"] / 1e3) / 1e9
+    kernels = {}
+    for prec, leg in legs.items():
+        for c, v in leg["kernels"].items():
+            entry = dict(v)
+            if c in BYTES_PER_POINT[prec]:
+                entry["GBs"] = BYTES_PER_POINT[prec][c] * n_unk / (v["avg_ms"] / 1e3) / 1e9
+                entry["frac_peak"] = entry["GBs"] / HBM_PEAK_GBS
+            kernels[f"{prec}:{c}"] = entry
+
+    out = {
+        "metric": "fine-grid unknowns solved/s to 1e-8 rel res (mixed vs FP64) + stencil HBM GB/s",
+        "value": value,
+        "unit": "unknowns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+bf16 V-cycle, f64 outer",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {w['desc']}", "n": n, "levels": levels,
+                   "unknowns": n_unk, "switch_n": args.switch_n, "rtol": args.rtol,
+                   "step": "setup + mixed PCG solve + adjoint gradient"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": bytes_per_launch, "avg_ms": cands[dom]["avg_ms"],
+                     "copy_GBs": copy_gbs},
+        "forward": {"iterations": mixed["forward"]["iterations"], "rel_res_true": mixed["forward"]["rel_res_true"],
+                    "restarts": mixed["forward"]["restarts"], "solve_ms": mixed["forward"]["solve_ms"]},
+        "adjoint": {"iterations": mixed["adjoint"]["iterations"], "solve_ms": mixed["adjoint"]["solve_ms"]},
+        "kernels": kernels,
+    }
+    if "fp64" in legs:
+        f64 = legs["fp64"]
+        out["fp64"] = {"ms_per_step": f64["ms_per_step"], "value": 2 * n_unk / (f64["ms_per_step"] / 1e3),
+                       "forward_iterations": f64["forward"]["iterations"],
+                       "forward_solve_ms": f64["forward"]["solve_ms"],
+                       "rel_res_true": f64["forward"]["rel_res_true"],
+                       "speedup_mixed": f64["ms_per_step"] / ms,
+                       "speedup_mixed_forward": f64["forward"]["solve_ms"] / mixed["forward"]["solve_ms"]}
+        d = torch.linalg.vector_norm(results["mixed"] - results["fp64"]) / torch.linalg.vector_norm(results["fp64"])
+        out["fp64"]["mixed_vs_fp64_rel_l2"] = float(d)
+    if not args.no_cpu_baseline:
+        its = legs.get("fp64", mixed)["forward"]["iterations"]
+        log("timing the CPU oracle sample ...")
+        out["cpu_baseline"] = cpu_baseline(w, k_np, f_np, its, iters=args.cpu_iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -149,6 +149,37 @@ gmg_status gmg_debug_vcycle(gmg_handle *h, const double *r, double *z);
 /* Copy level coefficients out in face shapes (MIXED: the BF16 values). */
 gmg_status gmg_get_level_coefficients(gmg_handle *h, int32_t level, double *kx, double *ky, double *kz);
 
+/* ---- kernel timing.  While profiling is on, every launch of a class on the
+ * FINEST level (plus the coarse-level classes) is bracketed by HIP events on
+ * the handle's stream; gmg_profile_get returns the launch count and the summed
+ * device time.  Used by the benchmark to measure kernels live. */
+typedef enum {
+    GMG_K_APPLY_DOT = 0,      /* q = A p and partial p.q (outer FP64 operator) */
+    GMG_K_RESIDUAL = 1,       /* r = f - A x (FP64 true residual) */
+    GMG_K_UPDATE_XR = 2,      /* x += alpha p, r -= alpha q, partial r.r */
+    GMG_K_UPDATE_P = 3,       /* p = z + beta p */
+    GMG_K_CHEB_FIRST = 4,     /* first Chebyshev step from zero (MIXED: converts r) */
+    GMG_K_CHEB_STEP = 5,      /* Chebyshev step without previous iterate */
+    GMG_K_CHEB_STEP_PREV = 6, /* three-term Chebyshev step (previous iterate) */
+    GMG_K_CHEB_STEP_DOT = 7,  /* last post-smoothing step + partial r.z */
+    GMG_K_LEVEL_RESIDUAL = 8, /* r = b - A x inside the V-cycle */
+    GMG_K_PROLONG = 9,        /* x += P e */
+    GMG_K_PERSISTENT = 10,    /* persistent coarse-level kernel (all levels below the switch) */
+    GMG_K_COARSE_SOLVE = 11,  /* grid-path coarsest Cholesky solve */
+    GMG_K_FACE_GRADIENT = 12, /* adjoint link gradient */
+    GMG_K_RESTRICT = 13,      /* b_c = R r (full weighting) */
+    GMG_K_COUNT = 14
+} gmg_kernel_class;
+gmg_status gmg_profile_start(gmg_handle *h);  /* clear counters, start recording */
+gmg_status gmg_profile_stop(gmg_handle *h);   /* stop recording, wait for the stream */
+gmg_status gmg_profile_get(gmg_handle *h, int32_t kclass, int32_t *launches, double *total_ms);
+const char *gmg_kernel_class_name(int32_t kclass);
+
+/* Plain device-to-device copy of `bytes` (a multiple of 16) with a simple
+ * streaming kernel on `stream`; returns after it completes.  Used to calibrate
+ * the profiler's HBM byte counters and to measure achievable copy bandwidth. */
+gmg_status gmg_calibration_copy(void *dst, const void *src, uint64_t bytes, void *stream);
+
 void gmg_destroy(gmg_handle *h);
 const char *gmg_status_string(gmg_status s);
 const char *gmg_last_error(const gmg_handle *h);

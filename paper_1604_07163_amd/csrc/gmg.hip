@@ -35,6 +35,7 @@ struct LevelHost {
     bf16 *kx16 = nullptr, *ky16 = nullptr, *kz16 = nullptr;
     void *b = nullptr, *x = nullptr, *t1 = nullptr;
     Tiling til{};
+    gmg::Rows rows{};
 };
 
 }  // namespace
@@ -61,6 +62,10 @@ struct gmg_handle {
     std::vector<void *> allocs;
     std::string err;
     double setup_ms = 0;
+    // kernel timing: event pairs per kernel class
+    bool prof_on = false;
+    std::vector<hipEvent_t> prof_ev[GMG_K_COUNT];
+    int prof_used[GMG_K_COUNT] = {};
 };
 
 namespace {
@@ -109,6 +114,18 @@ Tiling make_tiling(int n) {
     nch = (planes + t.zchunk - 1) / t.zchunk;
     t.nblocks = t.tiles_x * t.tiles_y * nch;
     return t;
+}
+
+gmg::Rows make_rows(int n, int pitch, long long plane) {
+    gmg::Rows r;
+    r.n = n;
+    r.pitch = pitch;
+    r.plane = plane;
+    r.half_w = n / 2;  // pairs cover x = 0 .. 2*half_w-1 (>= n-2, <= pitch)
+    int l = 0;
+    while ((1 << l) < r.half_w && (1 << l) < gmg::NT_FLAT) ++l;
+    r.tpr_log2 = l;
+    return r;
 }
 
 template <typename T>
@@ -163,6 +180,37 @@ const ChebCoef<double> &cheb<double>(const gmg_handle *h) { return h->cheb64; }
 template <>
 const ChebCoef<float> &cheb<float>(const gmg_handle *h) { return h->cheb32; }
 
+// ------------------------------------------------------------------ kernel timing
+// Brackets one launch with HIP events on the handle's stream when profiling
+// is on and `on` holds (finest-level launches and the coarse-level kernels).
+constexpr int kProfMax = 1 << 15;
+struct Prof {
+    gmg_handle *h;
+    int cls, idx = -1;
+    Prof(gmg_handle *h_, int c, bool on) : h(h_), cls(c) {
+        if (!on || !h->prof_on) return;
+        std::vector<hipEvent_t> &v = h->prof_ev[c];
+        const int i = h->prof_used[c];
+        if (i >= kProfMax) return;
+        if ((int)v.size() < 2 * (i + 1)) {
+            hipEvent_t a, b;
+            if (hipEventCreate(&a) != hipSuccess) return;
+            if (hipEventCreate(&b) != hipSuccess) {
+                (void)hipEventDestroy(a);
+                return;
+            }
+            v.push_back(a);
+            v.push_back(b);
+        }
+        if (hipEventRecord(v[2 * i], h->stream) != hipSuccess) return;
+        idx = i;
+    }
+    ~Prof() {
+        if (idx < 0) return;
+        if (hipEventRecord(h->prof_ev[cls][2 * idx + 1], h->stream) == hipSuccess) h->prof_used[cls] = idx + 1;
+    }
+};
+
 // ------------------------------------------------------------------ smoothing
 // Chebyshev-Jacobi smoothing of A_l x = b_l on the grid path.  The iterate
 // alternates between x and t1 (x_{j+1} overwrites the buffer of x_{j-1});
@@ -180,8 +228,10 @@ gmg_status smooth_grid(gmg_handle *h, int l, bool from_zero, const double *r64_c
     const dim3 grid(lh.til.nblocks), blk(gmg::NT);
     int cur, prev;
     if (nparts) *nparts = 0;
+    const bool fin = l == 0;
     if (from_zero) {
         V *dst = cc.m == 1 ? bufs[0] : bufs[1];
+        Prof pf(h, GMG_K_CHEB_FIRST, fin);
         if (r64_cvt)
             gmg::k_cheb_first<V, K, true><<<grid, blk, 0, h->stream>>>(L, lh.til, nullptr, r64_cvt, b, dst, cc.cfirst,
                                                                         skip);
@@ -193,6 +243,7 @@ gmg_status smooth_grid(gmg_handle *h, int l, bool from_zero, const double *r64_c
         cur = 1;
         prev = -1;
     } else {
+        Prof pf(h, GMG_K_CHEB_STEP, fin);
         gmg::k_cheb_step<V, K, 0, false><<<grid, blk, 0, h->stream>>>(L, lh.til, b, bufs[0], nullptr, bufs[1], V(0),
                                                                         cc.cfirst, nullptr, nullptr, skip);
         LAUNCHCHK();
@@ -202,6 +253,7 @@ gmg_status smooth_grid(gmg_handle *h, int l, bool from_zero, const double *r64_c
     for (int j = 1; j < cc.m; ++j) {
         const int dst = 1 - cur;
         const bool fuse = dot_r64 && (j == cc.m - 1) && dst == 0;
+        Prof pf(h, prev < 0 ? GMG_K_CHEB_STEP : fuse ? GMG_K_CHEB_STEP_DOT : GMG_K_CHEB_STEP_PREV, fin);
         if (prev < 0) {
             gmg::k_cheb_step<V, K, 1, false><<<grid, blk, 0, h->stream>>>(L, lh.til, b, bufs[cur], nullptr, bufs[dst],
                                                                             cc.c1[j], cc.c2[j], nullptr, nullptr, skip);
@@ -222,16 +274,35 @@ gmg_status smooth_grid(gmg_handle *h, int l, bool from_zero, const double *r64_c
         LAUNCHCHK();
     }
     if (dot_r64 && nparts && *nparts == 0) {
-        gmg::k_dot<V><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(lh.nel, dot_r64, bufs[0], h->partial, skip);
+        gmg::k_dot<V><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(lh.rows, dot_r64, bufs[0], h->partial, skip);
         LAUNCHCHK();
         *nparts = gmg::NB_FLAT;
     }
     return GMG_OK;
 }
 
+// b_{l+1} = R (b_l - A_l x_l): the residual into t1 (free between pre- and
+// post-smoothing), then full weighting onto the coarse right-hand side.
+template <typename V, typename K>
+gmg_status residual_restrict(gmg_handle *h, int l, const int *skip) {
+    LevelHost &f = h->lv[l], &c = h->lv[l + 1];
+    {
+        Prof pf(h, GMG_K_LEVEL_RESIDUAL, l == 0);
+        gmg::k_residual<V, K><<<f.til.nblocks, gmg::NT, 0, h->stream>>>(view<V, K>(f), f.til, (const V *)f.b,
+                                                                        (const V *)f.x, (V *)f.t1, skip);
+        LAUNCHCHK();
+    }
+    Prof pf(h, GMG_K_RESTRICT, l == 0);
+    gmg::k_restrict<V><<<c.til.nblocks, gmg::NT, 0, h->stream>>>(c.n, c.pitch, c.plane, c.til, f.pitch, f.plane,
+                                                                 (const V *)f.t1, (V *)c.b, skip);
+    LAUNCHCHK();
+    return GMG_OK;
+}
+
 template <typename V, typename K>
 gmg_status coarse_part(gmg_handle *h, const int *skip) {
     const int last = h->L - 1;
+    Prof pf(h, h->persist ? GMG_K_PERSISTENT : GMG_K_COARSE_SOLVE, true);
     if (h->persist) {
         gmg::k_persistent<V, K><<<1, gmg::NT_PERSIST, 0, h->stream>>>(
             (const LevBuf<V, K> *)h->dev_levels, h->s_persist, last, cheb<V>(h), h->chol, h->m, skip);
@@ -260,7 +331,7 @@ gmg_status vcycle(gmg_handle *h, const int *skip, bool want_dot, int *nparts) {
         }
         STCHK((coarse_part<V, K>(h, skip)));
         if (want_dot) {
-            gmg::k_dot<V><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(l0.nel, h->R, (const V *)l0.x, h->partial, skip);
+            gmg::k_dot<V><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(l0.rows, h->R, (const V *)l0.x, h->partial, skip);
             LAUNCHCHK();
             *nparts = gmg::NB_FLAT;
         }
@@ -270,18 +341,17 @@ gmg_status vcycle(gmg_handle *h, const int *skip, bool want_dot, int *nparts) {
     for (int l = 0; l < s; ++l) {
         STCHK((smooth_grid<V, K>(h, l, true, (l == 0 && mx) ? h->R : nullptr, nullptr, skip, nullptr)));
         LevelHost &f = h->lv[l], &c = h->lv[l + 1];
-        const long long mc = (long long)(c.n - 2) * (c.n - 2) * (c.n - 2);
-        gmg::k_resid_restrict<V, K><<<blocks_for(mc, 256), 256, 0, h->stream>>>(
-            view<V, K>(f), (const V *)f.b, (const V *)f.x, c.n, c.pitch, c.plane, (V *)c.b, skip);
-        LAUNCHCHK();
+        STCHK((residual_restrict<V, K>(h, l, skip)));
     }
     STCHK((coarse_part<V, K>(h, skip)));
     for (int l = s - 1; l >= 0; --l) {
         LevelHost &f = h->lv[l], &c = h->lv[l + 1];
-        const long long mf = (long long)(f.n - 2) * (f.n - 2) * (f.n - 2);
-        gmg::k_prolong_add<V><<<blocks_for(mf, 256), 256, 0, h->stream>>>(f.n, f.pitch, f.plane, (const V *)c.x,
-                                                                          c.pitch, c.plane, (V *)f.x, skip);
-        LAUNCHCHK();
+        {
+            Prof pf(h, GMG_K_PROLONG, l == 0);
+            gmg::k_prolong<V><<<f.til.nblocks, gmg::NT, 0, h->stream>>>(f.n, f.pitch, f.plane, f.til, (const V *)c.x,
+                                                                        c.pitch, c.plane, (V *)f.x, skip);
+            LAUNCHCHK();
+        }
         STCHK((smooth_grid<V, K>(h, l, false, nullptr, (l == 0 && want_dot) ? h->R : nullptr, skip,
                                  l == 0 ? nparts : nullptr)));
     }
@@ -299,7 +369,7 @@ gmg_status finalize(gmg_handle *h, int count, int stage) {
 }
 
 gmg_status dot64(gmg_handle *h, const double *a, const double *b, int stage, const int *skip) {
-    gmg::k_dot<double><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(h->lv[0].nel, a, b, h->partial, skip);
+    gmg::k_dot<double><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(h->lv[0].rows, a, b, h->partial, skip);
     LAUNCHCHK();
     return finalize(h, gmg::NB_FLAT, stage);
 }
@@ -316,11 +386,12 @@ gmg_status pcg_start(gmg_handle *h) {
     const int *skip = &h->st->done;
     STCHK(vcycle_any(h, skip, true, &np));
     STCHK(finalize(h, np, gmg::ST_RHO0));
+    Prof pf(h, GMG_K_UPDATE_P, true);
     if (mixed(h))
-        gmg::k_update_p<float><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(h->lv[0].nel, h->P,
+        gmg::k_update_p<float><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(h->lv[0].rows, h->P,
                                                                               (const float *)h->lv[0].x, h->st);
     else
-        gmg::k_update_p<double><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(h->lv[0].nel, h->P,
+        gmg::k_update_p<double><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(h->lv[0].rows, h->P,
                                                                                (const double *)h->lv[0].x, h->st);
     LAUNCHCHK();
     gmg::k_clear_restart<<<1, 64, 0, h->stream>>>(h->st);
@@ -331,20 +402,28 @@ gmg_status pcg_start(gmg_handle *h) {
 gmg_status pcg_iteration(gmg_handle *h) {
     LevelHost &l0 = h->lv[0];
     const int *skip = &h->st->done;
-    gmg::k_apply<double, double, true><<<l0.til.nblocks, gmg::NT, 0, h->stream>>>(view<double, double>(l0), l0.til,
-                                                                                  h->P, h->Q, h->partial, skip);
-    LAUNCHCHK();
+    {
+        Prof pf(h, GMG_K_APPLY_DOT, true);
+        gmg::k_apply<double, double, true><<<l0.til.nblocks, gmg::NT, 0, h->stream>>>(view<double, double>(l0), l0.til,
+                                                                                      h->P, h->Q, h->partial, skip);
+        LAUNCHCHK();
+    }
     STCHK(finalize(h, l0.til.nblocks, gmg::ST_ALPHA));
-    gmg::k_update_xr<<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(l0.nel, h->X, h->R, h->P, h->Q, h->st, h->partial);
-    LAUNCHCHK();
+    {
+        Prof pf(h, GMG_K_UPDATE_XR, true);
+        gmg::k_update_xr<<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(l0.rows, h->X, h->R, h->P, h->Q, h->st,
+                                                                       h->partial);
+        LAUNCHCHK();
+    }
     STCHK(finalize(h, gmg::NB_FLAT, gmg::ST_RR));
     int np = 0;
     STCHK(vcycle_any(h, skip, true, &np));
     STCHK(finalize(h, np, gmg::ST_BETA));
+    Prof pf(h, GMG_K_UPDATE_P, true);
     if (mixed(h))
-        gmg::k_update_p<float><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(l0.nel, h->P, (const float *)l0.x, h->st);
+        gmg::k_update_p<float><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(l0.rows, h->P, (const float *)l0.x, h->st);
     else
-        gmg::k_update_p<double><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(l0.nel, h->P, (const double *)l0.x,
+        gmg::k_update_p<double><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(l0.rows, h->P, (const double *)l0.x,
                                                                                h->st);
     LAUNCHCHK();
     return GMG_OK;
@@ -381,8 +460,9 @@ gmg_status solve_core(gmg_handle *h, const double *f, const double *x0, double r
     if (x0) {
         gmg::k_to_padded<double><<<blocks_for(nv, 256), 256, 0, h->stream>>>(l0.n, l0.pitch, x0, h->X);
         LAUNCHCHK();
+        Prof pf(h, GMG_K_RESIDUAL, true);
         gmg::k_residual<double, double><<<l0.til.nblocks, gmg::NT, 0, h->stream>>>(view<double, double>(l0), l0.til,
-                                                                                   h->F, h->X, h->R);
+                                                                                   h->F, h->X, h->R, nullptr);
         LAUNCHCHK();
     } else {
         HIPCHK(hipMemsetAsync(h->X, 0, l0.nel * sizeof(double), h->stream));
@@ -406,9 +486,13 @@ gmg_status solve_core(gmg_handle *h, const double *f, const double *x0, double r
         }
         for (;;) {
             // FP64 true residual
-            gmg::k_residual<double, double><<<l0.til.nblocks, gmg::NT, 0, h->stream>>>(view<double, double>(l0),
-                                                                                       l0.til, h->F, h->X, h->Q);
-            LAUNCHCHK();
+            {
+                Prof pf(h, GMG_K_RESIDUAL, true);
+                gmg::k_residual<double, double><<<l0.til.nblocks, gmg::NT, 0, h->stream>>>(view<double, double>(l0),
+                                                                                           l0.til, h->F, h->X, h->Q,
+                                                                                           nullptr);
+                LAUNCHCHK();
+            }
             STCHK(dot64(h, h->Q, h->Q, gmg::ST_TT, nullptr));
             STCHK(read_state(h));
             const PcgState &so = *h->st_out;
@@ -593,6 +677,8 @@ void gmg_destroy(gmg_handle *h) {
     if (!h) return;
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     for (void *p : h->allocs) (void)hipFree(p);
+    for (int c = 0; c < GMG_K_COUNT; ++c)
+        for (hipEvent_t e : h->prof_ev[c]) (void)hipEventDestroy(e);
     if (h->st_in) (void)hipHostFree(h->st_in);
     if (h->st_out) (void)hipHostFree(h->st_out);
     if (h->ev0) (void)hipEventDestroy(h->ev0);
@@ -645,6 +731,7 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
         lh.nel = (long long)n * lh.plane;
         lh.s = (double)(n - 1) * (double)(n - 1);
         lh.til = make_tiling(n);
+        lh.rows = make_rows(n, lh.pitch, lh.plane);
         n = (n - 1) / 2 + 1;
     }
     // persistent switch: first level l >= 1 with N_l <= switch_n
@@ -796,9 +883,12 @@ gmg_status gmg_adjoint_gradient(gmg_handle *h, const double *phi, const double *
     if (st != GMG_OK && st != GMG_ERR_NOT_CONVERGED && st != GMG_ERR_BREAKDOWN) return st;
     LevelHost &l0 = h->lv[0];
     const long long nv = (long long)l0.n * l0.n * l0.n;
-    gmg::k_face_gradient<<<blocks_for(nv, 256), 256, 0, h->stream>>>(l0.n, l0.pitch, l0.s, h->X, phi, l0.kx64,
-                                                                     l0.ky64, l0.kz64, g_x, g_y, g_z);
-    LAUNCHCHK();
+    {
+        Prof pf(h, GMG_K_FACE_GRADIENT, true);
+        gmg::k_face_gradient<<<blocks_for(nv, 256), 256, 0, h->stream>>>(l0.n, l0.pitch, l0.s, h->X, phi, l0.kx64,
+                                                                         l0.ky64, l0.kz64, g_x, g_y, g_z);
+        LAUNCHCHK();
+    }
     if (lambda) {
         gmg::k_to_natural<double><<<blocks_for(nv, 256), 256, 0, h->stream>>>(l0.n, l0.pitch, h->X, lambda);
         LAUNCHCHK();
@@ -857,11 +947,7 @@ gmg_status hook_restrict(gmg_handle *h, int level, const double *b, const double
     LevelHost &f = h->lv[level], &c = h->lv[level + 1];
     STCHK(in_vec<V>(h, f, b, (V *)f.b));
     STCHK(in_vec<V>(h, f, x, (V *)f.x));
-    const long long mc = (long long)(c.n - 2) * (c.n - 2) * (c.n - 2);
-    gmg::k_resid_restrict<V, K><<<blocks_for(mc, 256), 256, 0, h->stream>>>(view<V, K>(f), (const V *)f.b,
-                                                                             (const V *)f.x, c.n, c.pitch, c.plane,
-                                                                             (V *)c.b, nullptr);
-    LAUNCHCHK();
+    STCHK((residual_restrict<V, K>(h, level, nullptr)));
     return out_vec<V>(h, c, (const V *)c.b, bc);
 }
 
@@ -870,9 +956,8 @@ gmg_status hook_prolong(gmg_handle *h, int level, const double *e, double *x) {
     LevelHost &f = h->lv[level], &c = h->lv[level + 1];
     STCHK(in_vec<V>(h, c, e, (V *)c.x));
     STCHK(in_vec<V>(h, f, x, (V *)f.x));
-    const long long mf = (long long)(f.n - 2) * (f.n - 2) * (f.n - 2);
-    gmg::k_prolong_add<V><<<blocks_for(mf, 256), 256, 0, h->stream>>>(f.n, f.pitch, f.plane, (const V *)c.x, c.pitch,
-                                                                      c.plane, (V *)f.x, nullptr);
+    gmg::k_prolong<V><<<f.til.nblocks, gmg::NT, 0, h->stream>>>(f.n, f.pitch, f.plane, f.til, (const V *)c.x, c.pitch,
+                                                                c.plane, (V *)f.x, nullptr);
     LAUNCHCHK();
     return out_vec<V>(h, f, (const V *)f.x, x);
 }
@@ -970,3 +1055,55 @@ gmg_status gmg_get_level_coefficients(gmg_handle *h, int32_t level, double *kx, 
 }
 
 }  // extern "C"
+
+extern "C" {
+
+gmg_status gmg_profile_start(gmg_handle *h) {
+    if (!h) return GMG_ERR_ARG;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    for (int c = 0; c < GMG_K_COUNT; ++c) h->prof_used[c] = 0;
+    h->prof_on = true;
+    return GMG_OK;
+}
+
+gmg_status gmg_profile_stop(gmg_handle *h) {
+    if (!h) return GMG_ERR_ARG;
+    h->prof_on = false;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return GMG_OK;
+}
+
+gmg_status gmg_profile_get(gmg_handle *h, int32_t kclass, int32_t *launches, double *total_ms) {
+    if (!h || kclass < 0 || kclass >= GMG_K_COUNT || !launches || !total_ms) return GMG_ERR_ARG;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    double tot = 0.0;
+    const int n = h->prof_used[kclass];
+    for (int i = 0; i < n; ++i) {
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, h->prof_ev[kclass][2 * i], h->prof_ev[kclass][2 * i + 1]));
+        tot += ms;
+    }
+    *launches = n;
+    *total_ms = tot;
+    return GMG_OK;
+}
+
+const char *gmg_kernel_class_name(int32_t c) {
+    static const char *names[GMG_K_COUNT] = {"apply_dot",      "residual",  "update_xr",      "update_p",
+                                             "cheb_first",     "cheb_step", "cheb_step_prev", "cheb_step_dot",
+                                             "level_residual", "prolong",   "persistent",     "coarse_solve",
+                                             "face_gradient",  "restrict"};
+    return (c >= 0 && c < GMG_K_COUNT) ? names[c] : "unknown";
+}
+
+}  // extern "C"
+
+extern "C" gmg_status gmg_calibration_copy(void *dst, const void *src, uint64_t bytes, void *stream) {
+    if (!dst || !src || (bytes % 16) != 0) return GMG_ERR_ARG;
+    const long long n16 = (long long)(bytes / 16);
+    const int nb = (int)std::min<long long>((n16 + 255) / 256, 1 << 16);
+    gmg::k_copy<<<nb > 0 ? nb : 1, 256, 0, (hipStream_t)stream>>>(n16, (const uint4 *)src, (uint4 *)dst);
+    if (hipGetLastError() != hipSuccess) return GMG_ERR_HIP;
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return GMG_ERR_HIP;
+    return GMG_OK;
+}

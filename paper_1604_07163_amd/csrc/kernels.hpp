@@ -8,7 +8,7 @@
 //   * kx[o] is the coefficient of the link (i,j,k)-(i+1,j,k) stored at the
 //     offset o of its lower end point (ky, kz likewise along y, z);
 //   * boundary vertices and padding hold 0 in every vector and are never
-//     written, so flat (1D) vector kernels may sweep whole arrays.
+//     written, so vector kernels may sweep whole rows including them.
 //
 // Two precisions share the code through templates: V is the arithmetic /
 // vector type (double or float) and K the stored coefficient type (double or
@@ -243,7 +243,9 @@ __global__ __launch_bounds__(NT) void k_apply(Lev<V, K> L, Tiling t, const V *__
 // r = b - A u   (FP64 true residual and the x0 != 0 start)
 template <typename V, typename K>
 __global__ __launch_bounds__(NT) void k_residual(Lev<V, K> L, Tiling t, const V *__restrict__ b,
-                                                 const V *__restrict__ u, V *__restrict__ r) {
+                                                 const V *__restrict__ u, V *__restrict__ r,
+                                                 const int *__restrict__ skip) {
+    if (skip && *skip) return;
     const Column c = tile_column(L.n, t);
     if (!c.active) return;
     const int pitch = L.pitch;
@@ -385,31 +387,85 @@ __device__ __forceinline__ V prolong_at(const V *e, int pc, long long plc, int i
     return accz;
 }
 
-// b_c = R (b - A x), one thread per interior coarse vertex.
-template <typename V, typename K>
-__global__ __launch_bounds__(256) void k_resid_restrict(Lev<V, K> F, const V *__restrict__ b,
-                                                        const V *__restrict__ x, int nc, int pc, long long plc,
-                                                        V *__restrict__ bc, const int *__restrict__ skip) {
+// b_c = R r for a fine residual r held in memory (written by k_residual).
+// One thread per coarse column (I, J) marching in K; the in-plane 3x3 sum of
+// fine plane 2K+1 is reused as the lower plane of K+1.  The summation order
+// is that of restrict_resid_at, so both paths round identically.
+template <typename V>
+__device__ __forceinline__ V plane_sum(const V *r, long long base, int pf) {
+    const V w[3] = {V(0.25), V(0.5), V(0.25)};
+    V accy = V(0);
+#pragma unroll
+    for (int bb = 0; bb < 3; ++bb) {
+        const V *row = r + base + (long long)(bb - 1) * pf;
+        V accx = V(0);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) accx = fmaT(w[a], row[a - 1], accx);
+        accy = fmaT(w[bb], accx, accy);
+    }
+    return accy;
+}
+template <typename V>
+__global__ __launch_bounds__(NT) void k_restrict(int nc, int pc, long long plc, Tiling t, int pf, long long plf,
+                                                 const V *__restrict__ r, V *__restrict__ bc,
+                                                 const int *__restrict__ skip) {
     if (skip && *skip) return;
-    const int m = nc - 2;
-    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (long long)m * m * m) return;
-    const int I = 1 + (int)(idx % m), J = 1 + (int)((idx / m) % m), K_ = 1 + (int)(idx / ((long long)m * m));
-    bc[(long long)K_ * plc + (long long)J * pc + I] = restrict_resid_at(F, b, x, I, J, K_);
+    const Column c = tile_column(nc, t);
+    if (!c.active) return;
+    const long long col = (long long)(2 * c.j) * pf + 2 * c.i;
+    V lo = plane_sum(r, (long long)(2 * c.k0 - 1) * plf + col, pf);
+    long long oc = (long long)c.k0 * plc + (long long)c.j * pc + c.i;
+    for (int K = c.k0; K < c.k1; ++K, oc += plc) {
+        const V mid = plane_sum(r, (long long)(2 * K) * plf + col, pf);
+        const V hi = plane_sum(r, (long long)(2 * K + 1) * plf + col, pf);
+        V acc = fmaT(V(0.25), lo, V(0));
+        acc = fmaT(V(0.5), mid, acc);
+        acc = fmaT(V(0.25), hi, acc);
+        bc[oc] = acc;
+        lo = hi;
+    }
 }
 
-// x += P e, one thread per interior fine vertex.
+// x += P e marching fine columns in z; the x-y interpolation of a coarse
+// plane is computed once and reused by the (up to) three fine planes that
+// need it.  Summation order as in prolong_at.
 template <typename V>
-__global__ __launch_bounds__(256) void k_prolong_add(int n, int pitch, long long plane, const V *__restrict__ e,
-                                                     int pc, long long plc, V *__restrict__ x,
-                                                     const int *__restrict__ skip) {
+__device__ __forceinline__ V plane_interp(const V *e, long long kbase, int pc, int i, int j) {
+    const int i0 = i >> 1, i1 = (i + 1) >> 1, j0 = j >> 1, j1 = (j + 1) >> 1;
+    const V wi = (i & 1) ? V(0.5) : V(1), wj = (j & 1) ? V(0.5) : V(1);
+    const V *r0 = e + kbase + (long long)j0 * pc;
+    V accx = fmaT(wi, r0[i0], V(0));
+    if (i & 1) accx = fmaT(wi, r0[i1], accx);
+    V accy = fmaT(wj, accx, V(0));
+    if (j & 1) {
+        const V *r1 = e + kbase + (long long)j1 * pc;
+        V ax = fmaT(wi, r1[i0], V(0));
+        if (i & 1) ax = fmaT(wi, r1[i1], ax);
+        accy = fmaT(wj, ax, accy);
+    }
+    return accy;
+}
+template <typename V>
+__global__ __launch_bounds__(NT) void k_prolong(int n, int pitch, long long plane, Tiling t, const V *__restrict__ e,
+                                                int pc, long long plc, V *__restrict__ x,
+                                                const int *__restrict__ skip) {
     if (skip && *skip) return;
-    const int m = n - 2;
-    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (long long)m * m * m) return;
-    const int i = 1 + (int)(idx % m), j = 1 + (int)((idx / m) % m), k = 1 + (int)(idx / ((long long)m * m));
-    const long long o = (long long)k * plane + (long long)j * pitch + i;
-    x[o] = x[o] + prolong_at(e, pc, plc, i, j, k);
+    const Column c = tile_column(n, t);
+    if (!c.active) return;
+    int Klo = c.k0 >> 1;
+    V elo = plane_interp(e, (long long)Klo * plc, pc, c.i, c.j);
+    V ehi = plane_interp(e, (long long)(Klo + 1) * plc, pc, c.i, c.j);
+    long long o = (long long)c.k0 * plane + (long long)c.j * pitch + c.i;
+    for (int k = c.k0; k < c.k1; ++k, o += plane) {
+        const int K = k >> 1;
+        if (K != Klo) {
+            Klo = K;
+            elo = ehi;
+            ehi = plane_interp(e, (long long)(K + 1) * plc, pc, c.i, c.j);
+        }
+        const V v = (k & 1) ? fmaT(V(0.5), ehi, fmaT(V(0.5), elo, V(0))) : fmaT(V(1), elo, V(0));
+        x[o] = x[o] + v;
+    }
 }
 
 // ---------------------------------------------------------------- coarsest solve
@@ -601,19 +657,55 @@ struct PcgState {
     int pad;
 };
 
+// The PCG vector kernels sweep only the interior rows (j, k in 1..n-2) of
+// the padded arrays, x index 0 .. 2*half_w-1 in pairs (index 0 and the tail
+// are boundary zeros, so a pair never straddles live and stale data).  A row
+// is handled by 2^tpr_log2 threads; a workgroup covers 256 >> tpr_log2 rows at
+// a time and strides over the rows by the whole grid.
+struct Rows {
+    int n, pitch, half_w, tpr_log2;
+    long long plane;
+};
+template <typename T>
+struct Vec2;
+template <>
+struct Vec2<double> {
+    typedef double2 type;
+};
+template <>
+struct Vec2<float> {
+    typedef float2 type;
+};
+
+#define ROW_LOOP(R)                                                                                  \
+    const int tpr = 1 << (R).tpr_log2, rpb = NT_FLAT >> (R).tpr_log2;                               \
+    const int lane_ = threadIdx.x & (tpr - 1);                                                       \
+    const long long nrows = (long long)((R).n - 2) * ((R).n - 2);                                   \
+    for (long long row = (long long)blockIdx.x * rpb + (threadIdx.x >> (R).tpr_log2); row < nrows;   \
+         row += (long long)gridDim.x * rpb)                                                          \
+        for (long long base_ = (1 + row / ((R).n - 2)) * (R).plane + (1 + row % ((R).n - 2)) * (long long)(R).pitch, \
+                       q_ = lane_;                                                                   \
+             q_ < (R).half_w; q_ += tpr)
+
 // x += alpha p ; r -= alpha q ; partial = sum r^2
-__global__ __launch_bounds__(NT_FLAT) void k_update_xr(long long nel, double *__restrict__ x, double *__restrict__ r,
+__global__ __launch_bounds__(NT_FLAT) void k_update_xr(Rows R, double *__restrict__ x, double *__restrict__ r,
                                                        const double *__restrict__ p, const double *__restrict__ q,
                                                        const PcgState *__restrict__ st, double *__restrict__ partial) {
     if (st->done) return;
     const double a = st->alpha;
     double acc = 0.0;
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nel; e += stride) {
-        x[e] = fmaT(a, p[e], x[e]);
-        const double rn = fmaT(-a, q[e], r[e]);
-        r[e] = rn;
-        acc = fmaT(rn, rn, acc);
+    ROW_LOOP(R) {
+        const long long e = base_ + 2 * q_;
+        double2 xv = *(const double2 *)(x + e), rv = *(const double2 *)(r + e);
+        const double2 pv = *(const double2 *)(p + e), qv = *(const double2 *)(q + e);
+        xv.x = fmaT(a, pv.x, xv.x);
+        xv.y = fmaT(a, pv.y, xv.y);
+        rv.x = fmaT(-a, qv.x, rv.x);
+        rv.y = fmaT(-a, qv.y, rv.y);
+        *(double2 *)(x + e) = xv;
+        *(double2 *)(r + e) = rv;
+        acc = fmaT(rv.x, rv.x, acc);
+        acc = fmaT(rv.y, rv.y, acc);
     }
     const double s = block_sum<NT_FLAT>(acc);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
@@ -621,30 +713,49 @@ __global__ __launch_bounds__(NT_FLAT) void k_update_xr(long long nel, double *__
 
 // p = z + beta p   (z FP64 or FP32)
 template <typename Z>
-__global__ __launch_bounds__(NT_FLAT) void k_update_p(long long nel, double *__restrict__ p, const Z *__restrict__ z,
+__global__ __launch_bounds__(NT_FLAT) void k_update_p(Rows R, double *__restrict__ p, const Z *__restrict__ z,
                                                       const PcgState *__restrict__ st) {
     if (st->done) return;
     const double bta = st->restart ? 0.0 : st->beta;
-    const long long stride = (long long)gridDim.x * blockDim.x;
+    typedef typename Vec2<Z>::type Z2;
     if (bta == 0.0) {
-        for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nel; e += stride) p[e] = (double)z[e];
+        ROW_LOOP(R) {
+            const long long e = base_ + 2 * q_;
+            const Z2 zv = *(const Z2 *)(z + e);
+            *(double2 *)(p + e) = make_double2((double)zv.x, (double)zv.y);
+        }
     } else {
-        for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nel; e += stride)
-            p[e] = fmaT(bta, p[e], (double)z[e]);
+        ROW_LOOP(R) {
+            const long long e = base_ + 2 * q_;
+            const Z2 zv = *(const Z2 *)(z + e);
+            const double2 pv = *(const double2 *)(p + e);
+            *(double2 *)(p + e) = make_double2(fmaT(bta, pv.x, (double)zv.x), fmaT(bta, pv.y, (double)zv.y));
+        }
     }
 }
 
-// partial = sum a.b  (b FP64 or FP32)
+// partial = sum a.b over the interior rows  (b FP64 or FP32)
 template <typename Z>
-__global__ __launch_bounds__(NT_FLAT) void k_dot(long long nel, const double *__restrict__ a, const Z *__restrict__ b,
+__global__ __launch_bounds__(NT_FLAT) void k_dot(Rows R, const double *__restrict__ a, const Z *__restrict__ b,
                                                  double *__restrict__ partial, const int *__restrict__ skip) {
     if (skip && *skip) return;
+    typedef typename Vec2<Z>::type Z2;
     double acc = 0.0;
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nel; e += stride)
-        acc = fmaT(a[e], (double)b[e], acc);
+    ROW_LOOP(R) {
+        const long long e = base_ + 2 * q_;
+        const double2 av = *(const double2 *)(a + e);
+        const Z2 bv = *(const Z2 *)(b + e);
+        acc = fmaT(av.x, (double)bv.x, acc);
+        acc = fmaT(av.y, (double)bv.y, acc);
+    }
     const double s = block_sum<NT_FLAT>(acc);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// Plain device copy (bandwidth calibration of the profiler counters).
+__global__ __launch_bounds__(256) void k_copy(long long n16, const uint4 *__restrict__ src, uint4 *__restrict__ dst) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n16; e += stride) dst[e] = src[e];
 }
 
 enum Stage { ST_BB = 0, ST_RR0 = 1, ST_RHO0 = 2, ST_ALPHA = 3, ST_RR = 4, ST_BETA = 5, ST_TT = 6 };

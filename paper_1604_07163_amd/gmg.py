@@ -95,6 +95,16 @@ def lib():
     L.gmg_debug_vcycle.restype = st
     L.gmg_get_level_coefficients.argtypes = [P, I32, P, P, P]
     L.gmg_get_level_coefficients.restype = st
+    L.gmg_profile_start.argtypes = [P]
+    L.gmg_profile_start.restype = st
+    L.gmg_profile_stop.argtypes = [P]
+    L.gmg_profile_stop.restype = st
+    L.gmg_profile_get.argtypes = [P, I32, ctypes.POINTER(I32), ctypes.POINTER(D)]
+    L.gmg_profile_get.restype = st
+    L.gmg_kernel_class_name.argtypes = [I32]
+    L.gmg_kernel_class_name.restype = ctypes.c_char_p
+    L.gmg_calibration_copy.argtypes = [P, P, ctypes.c_uint64, P]
+    L.gmg_calibration_copy.restype = st
     L.gmg_destroy.argtypes = [P]
     L.gmg_destroy.restype = None
     L.gmg_status_string.argtypes = [st]
@@ -295,6 +305,50 @@ class Solver:
         if s != OK:
             self._err(s, "gmg_get_level_coefficients")
         return kx, ky, kz
+
+
+KERNEL_CLASSES = ["apply_dot", "residual", "update_xr", "update_p", "cheb_first", "cheb_step", "cheb_step_prev",
+                  "cheb_step_dot", "level_residual", "prolong", "persistent", "coarse_solve", "face_gradient",
+                  "restrict"]
+
+
+class Profile:
+    """Context manager: per-kernel-class launch counts and device time (HIP events)."""
+
+    def __init__(self, solver: "Solver"):
+        self.solver = solver
+        self.result = {}
+
+    def __enter__(self):
+        self.solver._sync_stream()
+        s = lib().gmg_profile_start(self.solver._h)
+        if s != OK:
+            self.solver._err(s, "gmg_profile_start")
+        return self
+
+    def __exit__(self, *exc):
+        L = lib()
+        L.gmg_profile_stop(self.solver._h)
+        for c, name in enumerate(KERNEL_CLASSES):
+            n = ctypes.c_int32(0)
+            ms = ctypes.c_double(0.0)
+            s = L.gmg_profile_get(self.solver._h, c, ctypes.byref(n), ctypes.byref(ms))
+            if s != OK:
+                self.solver._err(s, "gmg_profile_get")
+            if n.value:
+                self.result[name] = {"launches": n.value, "total_ms": ms.value, "avg_ms": ms.value / n.value}
+        return False
+
+
+def calibration_copy(dst: torch.Tensor, src: torch.Tensor):
+    """dst <- src with the library's plain streaming copy kernel (same byte count)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes or not (dst.is_cuda and src.is_cuda):
+        raise ValueError("calibration_copy: device tensors of equal byte size required")
+    s = lib().gmg_calibration_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nbytes,
+                                   ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if s != OK:
+        raise GmgError(s, "gmg_calibration_copy")
 
 
 def raw_create(options: Options, kx, ky, kz):

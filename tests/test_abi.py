@@ -55,3 +55,10 @@ def test_header_cites_no_missing_type():
     src = open(gmg.HEADER).read()
     for t in ("gmg_options", "gmg_info", "gmg_status", "gmg_handle"):
         assert t in src
+
+
+def test_kernel_class_names_match_binding():
+    L = gmg.lib()
+    assert [L.gmg_kernel_class_name(i).decode() for i in range(len(gmg.KERNEL_CLASSES))] == gmg.KERNEL_CLASSES
+    assert L.gmg_kernel_class_name(len(gmg.KERNEL_CLASSES)).decode() == "unknown"
+    assert L.gmg_calibration_copy(None, None, 16, None) == 1

@@ -34,10 +34,10 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # Algorithmic HBM bytes per interior fine-grid unknown for each finest-level
 # kernel class: every array read or written once, neighbours from cache.
 BYTES_PER_POINT = {
-    "fp64": {"apply_dot": 40, "residual": 48, "update_xr": 48, "update_p": 24, "cheb_first": 40,
+    "fp64": {"apply_dot": 40, "residual": 48, "update_r": 24, "update_xp": 40, "update_p": 16, "cheb_first": 24, "cheb_pre2": 48,
              "cheb_step": 48, "cheb_step_prev": 56, "cheb_step_dot": 56, "level_residual": 48,
              "restrict": 9, "prolong": 17, "face_gradient": 64},
-    "mixed": {"apply_dot": 40, "residual": 48, "update_xr": 48, "update_p": 20, "cheb_first": 22,
+    "mixed": {"apply_dot": 40, "residual": 48, "update_r": 28, "update_xp": 36, "update_p": 12, "cheb_first": 12, "cheb_pre2": 18,
               "cheb_step": 18, "cheb_step_prev": 22, "cheb_step_dot": 30, "level_residual": 18,
               "restrict": 4.5, "prolong": 8.5, "face_gradient": 64},
 }

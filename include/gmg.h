@@ -80,6 +80,15 @@ typedef struct {
     int32_t coeff_is_log;   /* 1: kx/ky/kz hold ln k (natural log) instead of k */
     int32_t check_every;    /* host reads the convergence flag every this many PCG
                                iterations (0 = automatic by grid size) */
+    int32_t coarse_solver;  /* 0: exact Cholesky on the coarsest level.  1: truncated
+                               hierarchy (the truncation strategy of Sec. 1 / Sec. 3.3.1):
+                               the coarsest level, of any size, is solved inexactly by
+                               Jacobi-preconditioned CG on grid-wide launches; needs
+                               switch_n = 0 */
+    double coarse_rtol;     /* coarse CG relative residual target (default 1e-4) */
+    int32_t coarse_max_it;  /* coarse CG iteration cap (default 500) */
+    int32_t flexible;       /* 1: Polak-Ribiere beta in the outer CG, for preconditioners
+                               that change between iterations (inexact coarse solves) */
 } gmg_options;
 
 typedef struct {
@@ -89,6 +98,7 @@ typedef struct {
     double rel_res_true;  /* ||f - A x|| / ||f|| at exit, FP64 */
     double setup_ms;      /* gmg_create / gmg_set_coefficients wall time */
     double solve_ms;      /* device time of the solve (HIP events on the stream) */
+    int32_t coarse_iterations; /* truncated hierarchy: coarse CG iterations over the solve */
 } gmg_info;
 
 /* Fill *opt with the defaults above for n vertices per side and
@@ -156,8 +166,8 @@ gmg_status gmg_get_level_coefficients(gmg_handle *h, int32_t level, double *kx, 
 typedef enum {
     GMG_K_APPLY_DOT = 0,      /* q = A p and partial p.q (outer FP64 operator) */
     GMG_K_RESIDUAL = 1,       /* r = f - A x (FP64 true residual) */
-    GMG_K_UPDATE_XR = 2,      /* x += alpha p, r -= alpha q, partial r.r */
-    GMG_K_UPDATE_P = 3,       /* p = z + beta p */
+    GMG_K_UPDATE_R = 2,       /* r -= alpha q, partial r.r (MIXED: and the FP32 copy of r) */
+    GMG_K_UPDATE_P = 3,       /* p = z (start of a CG recurrence) */
     GMG_K_CHEB_FIRST = 4,     /* first Chebyshev step from zero (MIXED: converts r) */
     GMG_K_CHEB_STEP = 5,      /* Chebyshev step without previous iterate */
     GMG_K_CHEB_STEP_PREV = 6, /* three-term Chebyshev step (previous iterate) */
@@ -168,7 +178,9 @@ typedef enum {
     GMG_K_COARSE_SOLVE = 11,  /* grid-path coarsest Cholesky solve */
     GMG_K_FACE_GRADIENT = 12, /* adjoint link gradient */
     GMG_K_RESTRICT = 13,      /* b_c = R r (full weighting) */
-    GMG_K_COUNT = 14
+    GMG_K_UPDATE_XP = 14,     /* x += alpha p, p = z + beta p */
+    GMG_K_CHEB_PRE2 = 15,     /* first two Chebyshev steps from zero, fused */
+    GMG_K_COUNT = 16
 } gmg_kernel_class;
 gmg_status gmg_profile_start(gmg_handle *h);  /* clear counters, start recording */
 gmg_status gmg_profile_stop(gmg_handle *h);   /* stop recording, wait for the stream */

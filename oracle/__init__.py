@@ -64,6 +64,11 @@ def lib():
         L.or_chol_solve_raw.argtypes = [I, P, P]
         L.or_create.argtypes = [I, I, I, D, D, I, P, P, P, ctypes.POINTER(P)]
         L.or_create.restype = I
+        L.or_create2.argtypes = [I, I, I, D, D, I, I, D, I, P, P, P, ctypes.POINTER(P)]
+        L.or_create2.restype = I
+        L.or_pcg2.argtypes = [P, P, P, D, I, I, ctypes.POINTER(I), ctypes.POINTER(D), ctypes.POINTER(D),
+                              ctypes.POINTER(ctypes.c_long)]
+        L.or_pcg2.restype = I
         L.or_destroy.argtypes = [P]
         L.or_level_n.argtypes = [P, I]
         L.or_level_n.restype = I
@@ -193,13 +198,16 @@ class Hierarchy:
     """Multigrid hierarchy + PCG on the CPU in FP64."""
 
     def __init__(self, kx, ky, kz, levels: int, degree: int = 2, lo: float = 0.25, hi: float = 2.0,
-                 rule: int = RULE_ARITHMETIC):
+                 rule: int = RULE_ARITHMETIC, coarse_solver: int = 0, coarse_rtol: float = 1e-4,
+                 coarse_max_it: int = 500):
+        """coarse_solver 0: exact Cholesky on the coarsest level; 1: truncated
+        hierarchy whose coarsest level is solved by Jacobi-CG to coarse_rtol."""
         self._kx, self._ky, self._kz = _f64(kx), _f64(ky), _f64(kz)
         self.n = self._kx.shape[0]
         self.levels = levels
         h = ctypes.c_void_p()
-        st = lib().or_create(self.n, levels, degree, lo, hi, rule, _p(self._kx), _p(self._ky),
-                             _p(self._kz), ctypes.byref(h))
+        st = lib().or_create2(self.n, levels, degree, lo, hi, rule, coarse_solver, coarse_rtol, coarse_max_it,
+                              _p(self._kx), _p(self._ky), _p(self._kz), ctypes.byref(h))
         if st != 0:
             raise OracleError(st)
         self._h = h
@@ -249,19 +257,21 @@ class Hierarchy:
         lib().or_vcycle(self._h, _p(r), _p(z))
         return z
 
-    def solve(self, f, rtol=1e-8, max_it=200):
-        """PCG from x0 = 0.  Returns (x, info dict); raises only on argument errors."""
+    def solve(self, f, rtol=1e-8, max_it=200, flexible=False):
+        """PCG from x0 = 0 (flexible: Polak-Ribiere beta).  Returns (x, info dict);
+        raises only on argument errors."""
         f = _f64(f)
         x = np.zeros_like(f)
         its = ctypes.c_int(0)
         rr = ctypes.c_double(0)
         rt = ctypes.c_double(0)
-        st = lib().or_pcg(self._h, _p(f), _p(x), rtol, max_it, ctypes.byref(its), ctypes.byref(rr),
-                          ctypes.byref(rt))
+        cits = ctypes.c_long(0)
+        st = lib().or_pcg2(self._h, _p(f), _p(x), rtol, max_it, 1 if flexible else 0, ctypes.byref(its),
+                           ctypes.byref(rr), ctypes.byref(rt), ctypes.byref(cits))
         if st in (1, 4):
             raise OracleError(st)
         return x, {"status": STATUS[st], "iterations": its.value, "rel_res": rr.value,
-                   "rel_res_true": rt.value}
+                   "rel_res_true": rt.value, "coarse_iterations": cits.value}
 
     def adjoint_gradient(self, phi, dl_dphi, rtol=1e-12, max_it=200):
         """Return (g_x, g_y, g_z, lambda, info): g = dL/d(ln k) on the face arrays."""

@@ -371,7 +371,11 @@ typedef struct {
     double lo, hi;
     or_level lv[OR_MAX_LEVELS];
     int m;       /* unknowns on the coarsest level */
-    double *chol; /* m x m, lower triangle = L */
+    double *chol; /* m x m, lower triangle = L (exact coarse solve only) */
+    int coarse_solver;     /* 0: exact Cholesky; 1: truncated hierarchy, inexact coarse CG */
+    double coarse_rtol;    /* coarse CG relative residual target */
+    int coarse_max_it;
+    long coarse_its;       /* coarse CG iterations since the last reset */
 } or_hier;
 
 enum { OR_OK = 0, OR_ERR_ARG = 1, OR_ERR_DIMS = 2, OR_ERR_COEFF = 3, OR_ERR_NOMEM = 4,
@@ -395,12 +399,14 @@ void or_destroy(void *hp)
     free(H);
 }
 
-int or_create(int n, int levels, int degree, double lo, double hi, int rule, const double *kx,
-              const double *ky, const double *kz, void **out)
+int or_create2(int n, int levels, int degree, double lo, double hi, int rule, int coarse_solver,
+               double coarse_rtol, int coarse_max_it, const double *kx, const double *ky, const double *kz,
+               void **out)
 {
     *out = NULL;
     if (n < 3 || levels < 1 || levels > OR_MAX_LEVELS || degree < 1 || !(lo > 0.0) || !(hi > lo) ||
-        rule < 0 || rule > 1)
+        rule < 0 || rule > 1 || coarse_solver < 0 || coarse_solver > 1 ||
+        (coarse_solver == 1 && (!(coarse_rtol > 0.0) || coarse_max_it < 1)))
         return OR_ERR_ARG;
     if ((n - 1) % (1 << (levels - 1)) != 0)
         return OR_ERR_DIMS;
@@ -408,7 +414,7 @@ int or_create(int n, int levels, int degree, double lo, double hi, int rule, con
     if (ncoarse < 3)
         return OR_ERR_DIMS;
     int m = (ncoarse - 2) * (ncoarse - 2) * (ncoarse - 2);
-    if (m > OR_MAX_COARSE)
+    if (coarse_solver == 0 && m > OR_MAX_COARSE)
         return OR_ERR_DIMS;
     /* coefficients must be positive and finite on every active link (a link
      * is active when one of its end points is interior; the values on links
@@ -427,6 +433,9 @@ int or_create(int n, int levels, int degree, double lo, double hi, int rule, con
     H->levels = levels;
     H->degree = degree;
     H->rule = rule;
+    H->coarse_solver = coarse_solver;
+    H->coarse_rtol = coarse_rtol;
+    H->coarse_max_it = coarse_max_it;
     H->lo = lo;
     H->hi = hi;
     int nl = n;
@@ -458,6 +467,10 @@ int or_create(int n, int levels, int degree, double lo, double hi, int rule, con
     }
     or_level *C = &H->lv[levels - 1];
     H->m = m;
+    if (coarse_solver == 1) { /* truncated hierarchy: no factorization */
+        *out = H;
+        return OR_OK;
+    }
     H->chol = (double *)malloc(sizeof(double) * (size_t)m * m);
     if (!H->chol) {
         or_destroy(H);
@@ -470,6 +483,12 @@ int or_create(int n, int levels, int degree, double lo, double hi, int rule, con
     }
     *out = H;
     return OR_OK;
+}
+
+int or_create(int n, int levels, int degree, double lo, double hi, int rule, const double *kx,
+              const double *ky, const double *kz, void **out)
+{
+    return or_create2(n, levels, degree, lo, hi, rule, 0, 0.0, 0, kx, ky, kz, out);
 }
 
 int or_level_n(void *hp, int l)
@@ -491,10 +510,65 @@ int or_get_k(void *hp, int l, double *kx, double *ky, double *kz)
     return OR_OK;
 }
 
-/* exact coarsest solve: x = A_c^-1 b on the coarsest level */
+static double dot_int(int n, const double *a, const double *b);
+
+/* Inexact coarsest solve of a truncated hierarchy (the truncation strategy of
+ * Sec. 1 and Sec. 3.3.1: fewer levels, an iterative coarse solver to a
+ * relative tolerance): CG preconditioned by Jacobi from x = 0, stopped when
+ * ||r|| <= coarse_rtol ||b|| or after coarse_max_it iterations. */
+static int coarse_cg(or_hier *H, const double *b, double *x)
+{
+    or_level *C = &H->lv[H->levels - 1];
+    int n = C->n;
+    size_t nv = nvert(n);
+    double *r = C->work, *p = C->work + nv, *q = C->work + 2 * nv, *dg = C->work + 3 * nv;
+    double *z = (double *)calloc(nv, sizeof(double));
+    if (!z)
+        return OR_ERR_NOMEM;
+    or_diag_raw(n, C->kx, C->ky, C->kz, dg);
+    for (size_t i = 0; i < nv; i++) {
+        x[i] = 0.0;
+        r[i] = b[i];
+        z[i] = dg[i] > 0.0 ? r[i] / dg[i] : 0.0;
+        p[i] = z[i];
+    }
+    double bb = dot_int(n, b, b);
+    double rho = dot_int(n, r, z);
+    if (bb == 0.0) {
+        free(z);
+        return OR_OK;
+    }
+    for (int it = 0; it < H->coarse_max_it; it++) {
+        or_apply_raw(n, C->kx, C->ky, C->kz, p, q);
+        double pq = dot_int(n, p, q);
+        if (!(pq > 0.0))
+            break;
+        double alpha = rho / pq;
+        for (size_t i = 0; i < nv; i++) {
+            x[i] += alpha * p[i];
+            r[i] -= alpha * q[i];
+        }
+        H->coarse_its++;
+        if (dot_int(n, r, r) <= H->coarse_rtol * H->coarse_rtol * bb)
+            break;
+        for (size_t i = 0; i < nv; i++)
+            z[i] = dg[i] > 0.0 ? r[i] / dg[i] : 0.0;
+        double rho_new = dot_int(n, r, z);
+        double beta = rho_new / rho;
+        rho = rho_new;
+        for (size_t i = 0; i < nv; i++)
+            p[i] = z[i] + beta * p[i];
+    }
+    free(z);
+    return OR_OK;
+}
+
+/* coarsest solve: x = A_c^-1 b (exact), or the inexact CG of a truncated hierarchy */
 int or_coarse_solve(void *hp, const double *b, double *x)
 {
     or_hier *H = (or_hier *)hp;
+    if (H->coarse_solver == 1)
+        return coarse_cg(H, b, x);
     int n = H->lv[H->levels - 1].n;
     double *y = (double *)malloc(sizeof(double) * (size_t)H->m);
     if (!y)
@@ -606,8 +680,32 @@ static double dot_int(int n, const double *a, const double *b)
 /* with x0 = 0).  its counts the updates of x.  On exit relres is the       */
 /* recursive residual ratio and relres_true = ||b - A x|| / ||b||.          */
 /* ------------------------------------------------------------------------ */
+static int pcg_impl(void *hp, const double *f, double *x, double rtol, int max_it, int flexible, int *its,
+                    double *relres, double *relres_true);
+
 int or_pcg(void *hp, const double *f, double *x, double rtol, int max_it, int *its,
            double *relres, double *relres_true)
+{
+    return pcg_impl(hp, f, x, rtol, max_it, 0, its, relres, relres_true);
+}
+
+/* flexible = 1: Polak-Ribiere beta = z_{k+1}.(r_{k+1} - r_k) / (r_k.z_k), which
+ * with r_{k+1} - r_k = -alpha q_k is -alpha (q_k.z_{k+1}) / rho_k; it keeps CG
+ * convergent when the preconditioner varies between iterations (an inexact
+ * coarse solve). */
+int or_pcg2(void *hp, const double *f, double *x, double rtol, int max_it, int flexible, int *its,
+            double *relres, double *relres_true, long *coarse_its)
+{
+    or_hier *H = (or_hier *)hp;
+    H->coarse_its = 0;
+    int st = pcg_impl(hp, f, x, rtol, max_it, flexible, its, relres, relres_true);
+    if (coarse_its)
+        *coarse_its = H->coarse_its;
+    return st;
+}
+
+static int pcg_impl(void *hp, const double *f, double *x, double rtol, int max_it, int flexible, int *its,
+                    double *relres, double *relres_true)
 {
     or_hier *H = (or_hier *)hp;
     or_level *L = &H->lv[0];
@@ -669,7 +767,7 @@ int or_pcg(void *hp, const double *f, double *x, double rtol, int max_it, int *i
         }
         or_vcycle(H, r, z);
         double rho_new = dot_int(n, r, z);
-        double beta = rho_new / rho;
+        double beta = flexible ? -alpha * dot_int(n, q, z) / rho : rho_new / rho;
         rho = rho_new;
         for (size_t i = 0; i < nv; i++)
             p[i] = z[i] + beta * p[i];

@@ -33,7 +33,7 @@ struct LevelHost {
     double s = 0;                  // h^-2
     double *kx64 = nullptr, *ky64 = nullptr, *kz64 = nullptr;
     bf16 *kx16 = nullptr, *ky16 = nullptr, *kz16 = nullptr;
-    void *b = nullptr, *x = nullptr, *t1 = nullptr;
+    void *b = nullptr, *x = nullptr, *t1 = nullptr, *dinv = nullptr;
     Tiling til{};
     gmg::Rows rows{};
 };
@@ -51,6 +51,10 @@ struct gmg_handle {
     PcgState *st = nullptr;       // device
     PcgState *st_in = nullptr;    // pinned host (uploads)
     PcgState *st_out = nullptr;   // pinned host (read-back)
+    PcgState *cst = nullptr;      // device: inexact coarse CG (truncated hierarchy)
+    PcgState *cst_out = nullptr;  // pinned host
+    void *cp = nullptr, *cq = nullptr;  // coarse CG direction and A p (coarsest level, V type)
+    long long coarse_its = 0;     // coarse CG iterations in the current solve
     double *chol = nullptr;       // coarsest factor, device
     int m = 0;
     void *dev_levels = nullptr;   // LevBuf<V,K>[L] on the device
@@ -170,6 +174,7 @@ Lev<V, K> view(const LevelHost &l) {
     v.kx = KSel<K>::x(l);
     v.ky = KSel<K>::y(l);
     v.kz = KSel<K>::z(l);
+    v.dinv = (const V *)l.dinv;
     return v;
 }
 
@@ -211,6 +216,8 @@ struct Prof {
     }
 };
 
+gmg_status finalize(gmg_handle *h, int count, int stage, PcgState *state = nullptr);
+
 // ------------------------------------------------------------------ smoothing
 // Chebyshev-Jacobi smoothing of A_l x = b_l on the grid path.  The iterate
 // alternates between x and t1 (x_{j+1} overwrites the buffer of x_{j-1});
@@ -219,7 +226,7 @@ struct Prof {
 // of partials written (0 if none).
 template <typename V, typename K>
 gmg_status smooth_grid(gmg_handle *h, int l, bool from_zero, const double *r64_cvt, const double *dot_r64,
-                       const int *skip, int *nparts) {
+                       const int *skip, int *nparts, const double *dot_q64 = nullptr) {
     LevelHost &lh = h->lv[l];
     const Lev<V, K> L = view<V, K>(lh);
     const ChebCoef<V> &cc = cheb<V>(h);
@@ -229,6 +236,33 @@ gmg_status smooth_grid(gmg_handle *h, int l, bool from_zero, const double *r64_c
     int cur, prev;
     if (nparts) *nparts = 0;
     const bool fin = l == 0;
+    if (from_zero && !r64_cvt && cc.m >= 2) {
+        // x1 and x2 in one sweep; x1 is stored only when a third step needs it
+        Prof pf(h, GMG_K_CHEB_PRE2, fin);
+        if (cc.m == 2)
+            gmg::k_cheb_pre2<V, K, false><<<grid, blk, 0, h->stream>>>(L, lh.til, b, bufs[0], nullptr, cc.cfirst,
+                                                                        cc.c1[1], cc.c2[1], skip);
+        else
+            gmg::k_cheb_pre2<V, K, true><<<grid, blk, 0, h->stream>>>(L, lh.til, b, bufs[0], bufs[1], cc.cfirst,
+                                                                       cc.c1[1], cc.c2[1], skip);
+        LAUNCHCHK();
+        cur = 0;
+        prev = 1;
+        for (int j = 2; j < cc.m; ++j) {
+            const int dst = 1 - cur;
+            Prof pf2(h, GMG_K_CHEB_STEP_PREV, fin);
+            gmg::k_cheb_step<V, K, 2, false><<<grid, blk, 0, h->stream>>>(L, lh.til, b, bufs[cur], bufs[prev], bufs[dst],
+                                                                            cc.c1[j], cc.c2[j], nullptr, nullptr, skip);
+            LAUNCHCHK();
+            prev = cur;
+            cur = dst;
+        }
+        if (cur != 0) {
+            gmg::k_cast<V, V><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(lh.nel, bufs[1], bufs[0], skip);
+            LAUNCHCHK();
+        }
+        return GMG_OK;
+    }
     if (from_zero) {
         V *dst = cc.m == 1 ? bufs[0] : bufs[1];
         Prof pf(h, GMG_K_CHEB_FIRST, fin);
@@ -259,7 +293,8 @@ gmg_status smooth_grid(gmg_handle *h, int l, bool from_zero, const double *r64_c
                                                                             cc.c1[j], cc.c2[j], nullptr, nullptr, skip);
         } else if (fuse) {
             gmg::k_cheb_step<V, K, 2, true><<<grid, blk, 0, h->stream>>>(L, lh.til, b, bufs[cur], bufs[prev], bufs[dst],
-                                                                           cc.c1[j], cc.c2[j], dot_r64, h->partial, skip);
+                                                                           cc.c1[j], cc.c2[j], dot_r64, h->partial, skip,
+                                                                           dot_q64);
             if (nparts) *nparts = lh.til.nblocks;
         } else {
             gmg::k_cheb_step<V, K, 2, false><<<grid, blk, 0, h->stream>>>(L, lh.til, b, bufs[cur], bufs[prev], bufs[dst],
@@ -276,8 +311,50 @@ gmg_status smooth_grid(gmg_handle *h, int l, bool from_zero, const double *r64_c
     if (dot_r64 && nparts && *nparts == 0) {
         gmg::k_dot<V><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(lh.rows, dot_r64, bufs[0], h->partial, skip);
         LAUNCHCHK();
+        if (dot_q64) {
+            gmg::k_dot<V><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(lh.rows, dot_q64, bufs[0],
+                                                                         h->partial + gmg::NB_FLAT, skip);
+            LAUNCHCHK();
+        }
         *nparts = gmg::NB_FLAT;
     }
+    return GMG_OK;
+}
+
+// Inexact coarsest solve of a truncated hierarchy: Jacobi-CG on grid-wide
+// launches, its scalars on the device; the host polls the stop flag every 8
+// iterations (the coarse solve of the truncation strategy pays these launches
+// and reductions on every V-cycle).
+template <typename V, typename K>
+gmg_status coarse_cg(gmg_handle *h, const int *skip) {
+    LevelHost &c = h->lv[h->L - 1];
+    const int *cskip = &h->cst->done;
+    gmg::k_cg_begin<<<1, 64, 0, h->stream>>>(h->cst, skip, h->opt.coarse_rtol * h->opt.coarse_rtol,
+                                             h->opt.coarse_max_it);
+    LAUNCHCHK();
+    gmg::k_cg_start<V><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(c.rows, (const V *)c.b, (V *)c.x, (V *)c.t1,
+                                                                      (V *)h->cp, (const V *)c.dinv, h->partial, cskip);
+    LAUNCHCHK();
+    STCHK(finalize(h, gmg::NB_FLAT, gmg::ST_C_INIT, h->cst));
+    for (int chunk = 0; chunk * 8 < h->opt.coarse_max_it + 8; ++chunk) {
+        for (int i = 0; i < 8; ++i) {
+            gmg::k_apply<V, K, true><<<c.til.nblocks, gmg::NT, 0, h->stream>>>(view<V, K>(c), c.til, (const V *)h->cp,
+                                                                               (V *)h->cq, h->partial, cskip);
+            LAUNCHCHK();
+            STCHK(finalize(h, c.til.nblocks, gmg::ST_C_ALPHA, h->cst));
+            gmg::k_cg_update<V><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(
+                c.rows, (V *)c.x, (V *)c.t1, (const V *)h->cp, (const V *)h->cq, (const V *)c.dinv, h->cst, h->partial);
+            LAUNCHCHK();
+            STCHK(finalize(h, gmg::NB_FLAT, gmg::ST_C_RR, h->cst));
+            gmg::k_cg_p<V><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(c.rows, (const V *)c.t1, (V *)h->cp,
+                                                                          (const V *)c.dinv, h->cst);
+            LAUNCHCHK();
+        }
+        HIPCHK(hipMemcpyAsync(h->cst_out, h->cst, sizeof(PcgState), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        if (h->cst_out->done) break;
+    }
+    h->coarse_its += h->cst_out->its;
     return GMG_OK;
 }
 
@@ -302,6 +379,7 @@ gmg_status residual_restrict(gmg_handle *h, int l, const int *skip) {
 template <typename V, typename K>
 gmg_status coarse_part(gmg_handle *h, const int *skip) {
     const int last = h->L - 1;
+    if (h->opt.coarse_solver == 1) return coarse_cg<V, K>(h, skip);
     Prof pf(h, h->persist ? GMG_K_PERSISTENT : GMG_K_COARSE_SOLVE, true);
     if (h->persist) {
         gmg::k_persistent<V, K><<<1, gmg::NT_PERSIST, 0, h->stream>>>(
@@ -319,7 +397,7 @@ gmg_status coarse_part(gmg_handle *h, const int *skip) {
 // lv[0].x (FP64 or FP32).  With want_dot, partial sums of r.z are left in
 // h->partial and their count in *nparts.
 template <typename V, typename K>
-gmg_status vcycle(gmg_handle *h, const int *skip, bool want_dot, int *nparts) {
+gmg_status vcycle(gmg_handle *h, const int *skip, bool want_dot, int *nparts, bool b_ready = false) {
     const int last = h->L - 1;
     const bool mx = mixed(h);
     if (nparts) *nparts = 0;
@@ -333,13 +411,18 @@ gmg_status vcycle(gmg_handle *h, const int *skip, bool want_dot, int *nparts) {
         if (want_dot) {
             gmg::k_dot<V><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(l0.rows, h->R, (const V *)l0.x, h->partial, skip);
             LAUNCHCHK();
+            if (h->opt.flexible) {
+                gmg::k_dot<V><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(l0.rows, h->Q, (const V *)l0.x,
+                                                                             h->partial + gmg::NB_FLAT, skip);
+                LAUNCHCHK();
+            }
             *nparts = gmg::NB_FLAT;
         }
         return GMG_OK;
     }
     const int s = h->s_persist;  // levels 0..s-1 on the grid path
     for (int l = 0; l < s; ++l) {
-        STCHK((smooth_grid<V, K>(h, l, true, (l == 0 && mx) ? h->R : nullptr, nullptr, skip, nullptr)));
+        STCHK((smooth_grid<V, K>(h, l, true, (l == 0 && mx && !b_ready) ? h->R : nullptr, nullptr, skip, nullptr)));
         LevelHost &f = h->lv[l], &c = h->lv[l + 1];
         STCHK((residual_restrict<V, K>(h, l, skip)));
     }
@@ -353,17 +436,21 @@ gmg_status vcycle(gmg_handle *h, const int *skip, bool want_dot, int *nparts) {
             LAUNCHCHK();
         }
         STCHK((smooth_grid<V, K>(h, l, false, nullptr, (l == 0 && want_dot) ? h->R : nullptr, skip,
-                                 l == 0 ? nparts : nullptr)));
+                                 l == 0 ? nparts : nullptr,
+                                 (l == 0 && want_dot && h->opt.flexible) ? h->Q : nullptr)));
     }
     return GMG_OK;
 }
 
-gmg_status vcycle_any(gmg_handle *h, const int *skip, bool want_dot, int *nparts) {
-    return mixed(h) ? vcycle<float, bf16>(h, skip, want_dot, nparts) : vcycle<double, double>(h, skip, want_dot, nparts);
+// b_ready: MIXED only -- the FP32 finest right-hand side was already written
+// from r (by k_update_r), so the first sweep need not convert r.
+gmg_status vcycle_any(gmg_handle *h, const int *skip, bool want_dot, int *nparts, bool b_ready = false) {
+    return mixed(h) ? vcycle<float, bf16>(h, skip, want_dot, nparts, b_ready)
+                    : vcycle<double, double>(h, skip, want_dot, nparts);
 }
 
-gmg_status finalize(gmg_handle *h, int count, int stage) {
-    gmg::k_finalize<<<1, 256, 0, h->stream>>>(h->partial, count, stage, h->st);
+gmg_status finalize(gmg_handle *h, int count, int stage, PcgState *state) {
+    gmg::k_finalize<<<1, 256, 0, h->stream>>>(h->partial, count, stage, state ? state : h->st);
     LAUNCHCHK();
     return GMG_OK;
 }
@@ -399,9 +486,13 @@ gmg_status pcg_start(gmg_handle *h) {
     return GMG_OK;
 }
 
+// One CG iteration, every scalar on the device:
+//   q = A p, p.q -> alpha ; r -= alpha q, ||r||^2 -> stop? ; z = B r, r.z -> beta ;
+//   x += alpha p_old, p = z + beta p_old.
 gmg_status pcg_iteration(gmg_handle *h) {
     LevelHost &l0 = h->lv[0];
     const int *skip = &h->st->done;
+    const bool mx = mixed(h);
     {
         Prof pf(h, GMG_K_APPLY_DOT, true);
         gmg::k_apply<double, double, true><<<l0.til.nblocks, gmg::NT, 0, h->stream>>>(view<double, double>(l0), l0.til,
@@ -410,21 +501,30 @@ gmg_status pcg_iteration(gmg_handle *h) {
     }
     STCHK(finalize(h, l0.til.nblocks, gmg::ST_ALPHA));
     {
-        Prof pf(h, GMG_K_UPDATE_XR, true);
-        gmg::k_update_xr<<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(l0.rows, h->X, h->R, h->P, h->Q, h->st,
-                                                                       h->partial);
+        Prof pf(h, GMG_K_UPDATE_R, true);
+        if (mx)
+            gmg::k_update_r<float><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(l0.rows, h->R, h->Q, (float *)l0.b,
+                                                                                 h->st, h->partial);
+        else
+            gmg::k_update_r<double><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(l0.rows, h->R, h->Q, nullptr, h->st,
+                                                                                  h->partial);
         LAUNCHCHK();
     }
     STCHK(finalize(h, gmg::NB_FLAT, gmg::ST_RR));
     int np = 0;
-    STCHK(vcycle_any(h, skip, true, &np));
-    STCHK(finalize(h, np, gmg::ST_BETA));
-    Prof pf(h, GMG_K_UPDATE_P, true);
-    if (mixed(h))
-        gmg::k_update_p<float><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(l0.rows, h->P, (const float *)l0.x, h->st);
-    else
-        gmg::k_update_p<double><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(l0.rows, h->P, (const double *)l0.x,
-                                                                               h->st);
+    STCHK(vcycle_any(h, skip, true, &np, true));
+    STCHK(finalize(h, np, h->opt.flexible ? gmg::ST_BETA_FLEX : gmg::ST_BETA));
+    {
+        Prof pf(h, GMG_K_UPDATE_XP, true);
+        if (mx)
+            gmg::k_update_xp<float><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(l0.rows, h->X, h->P,
+                                                                                  (const float *)l0.x, h->st);
+        else
+            gmg::k_update_xp<double><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(l0.rows, h->X, h->P,
+                                                                                   (const double *)l0.x, h->st);
+        LAUNCHCHK();
+    }
+    gmg::k_clear_pending<<<1, 64, 0, h->stream>>>(h->st);
     LAUNCHCHK();
     return GMG_OK;
 }
@@ -449,6 +549,7 @@ gmg_status pcg_loop(gmg_handle *h) {
 gmg_status solve_core(gmg_handle *h, const double *f, const double *x0, double rtol, int max_it, gmg_info *info) {
     LevelHost &l0 = h->lv[0];
     const long long nv = (long long)l0.n * l0.n * l0.n;
+    h->coarse_its = 0;
     HIPCHK(hipEventRecord(h->ev0, h->stream));
     gmg::k_to_padded<double><<<blocks_for(nv, 256), 256, 0, h->stream>>>(l0.n, l0.pitch, f, h->F);
     LAUNCHCHK();
@@ -527,6 +628,7 @@ gmg_status solve_core(gmg_handle *h, const double *f, const double *x0, double r
         info->rel_res_true = bb > 0 ? std::sqrt(so.tt / bb) : 0.0;
         info->setup_ms = h->setup_ms;
         info->solve_ms = ms;
+        info->coarse_iterations = (int32_t)h->coarse_its;
     }
     if (status == GMG_ERR_BREAKDOWN) h->err = "breakdown: p.Ap <= 0 or non-finite residual";
     if (status == GMG_ERR_NOT_CONVERGED) h->err = "not converged within max_it";
@@ -624,7 +726,17 @@ gmg_status load_coefficients(gmg_handle *h, const double *kx, const double *ky, 
             LAUNCHCHK();
         }
     }
-    STCHK(factor_coarsest(h));
+    for (int l = 0; l < h->L; ++l) {
+        LevelHost &c = h->lv[l];
+        if (mixed(h))
+            gmg::k_dinv<float, bf16><<<c.til.nblocks, gmg::NT, 0, h->stream>>>(view<float, bf16>(c), c.til,
+                                                                                (float *)c.dinv);
+        else
+            gmg::k_dinv<double, double><<<c.til.nblocks, gmg::NT, 0, h->stream>>>(view<double, double>(c), c.til,
+                                                                                  (double *)c.dinv);
+        LAUNCHCHK();
+    }
+    if (h->opt.coarse_solver == 0) STCHK(factor_coarsest(h));
     return GMG_OK;
 }
 
@@ -655,6 +767,10 @@ void gmg_default_options(gmg_options *o, int32_t n) {
     o->coarse_rule = GMG_COARSE_ARITHMETIC;
     o->coeff_is_log = 0;
     o->check_every = 0;
+    o->coarse_solver = 0;
+    o->coarse_rtol = 1e-4;
+    o->coarse_max_it = 500;
+    o->flexible = 0;
 }
 
 const char *gmg_status_string(gmg_status s) {
@@ -681,6 +797,7 @@ void gmg_destroy(gmg_handle *h) {
         for (hipEvent_t e : h->prof_ev[c]) (void)hipEventDestroy(e);
     if (h->st_in) (void)hipHostFree(h->st_in);
     if (h->st_out) (void)hipHostFree(h->st_out);
+    if (h->cst_out) (void)hipHostFree(h->cst_out);
     if (h->ev0) (void)hipEventDestroy(h->ev0);
     if (h->ev1) (void)hipEventDestroy(h->ev1);
     delete h;
@@ -696,11 +813,14 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
     if (o.cheb_degree < 1 || o.cheb_degree > gmg::MAX_DEGREE || !(o.cheb_lo > 0.0) || !(o.cheb_hi > o.cheb_lo) ||
         (o.precision != GMG_FP64 && o.precision != GMG_MIXED) ||
         (o.coarse_rule != GMG_COARSE_ARITHMETIC && o.coarse_rule != GMG_COARSE_HARMONIC) || o.switch_n < 0 ||
-        o.persistent_wgs != 1 || o.check_every < 0 || (o.coeff_is_log != 0 && o.coeff_is_log != 1))
+        o.persistent_wgs != 1 || o.check_every < 0 || (o.coeff_is_log != 0 && o.coeff_is_log != 1) ||
+        (o.coarse_solver != 0 && o.coarse_solver != 1) || (o.flexible != 0 && o.flexible != 1) ||
+        (o.coarse_solver == 1 && (!(o.coarse_rtol > 0.0) || o.coarse_max_it < 1 || o.switch_n != 0)))
         return GMG_ERR_ARG;
     if ((o.n - 1) % (1 << (o.levels - 1)) != 0) return GMG_ERR_DIMS;
     const int nc = (o.n - 1) / (1 << (o.levels - 1)) + 1;
-    if (nc < 3 || (nc - 2) * (nc - 2) * (nc - 2) > gmg::MAX_COARSE) return GMG_ERR_DIMS;
+    if (nc < 3 || (o.coarse_solver == 0 && (long long)(nc - 2) * (nc - 2) * (nc - 2) > gmg::MAX_COARSE))
+        return GMG_ERR_DIMS;
 
     gmg_handle *h = new gmg_handle();
     h->opt = o;
@@ -718,7 +838,8 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
         return bail(GMG_ERR_HIP);
     (void)hipEventRecord(t0, h->stream);
     if (hipHostMalloc((void **)&h->st_in, sizeof(PcgState)) != hipSuccess ||
-        hipHostMalloc((void **)&h->st_out, sizeof(PcgState)) != hipSuccess)
+        hipHostMalloc((void **)&h->st_out, sizeof(PcgState)) != hipSuccess ||
+        hipHostMalloc((void **)&h->cst_out, sizeof(PcgState)) != hipSuccess)
         return bail(GMG_ERR_NOMEM);
     const bool mx = o.precision == GMG_MIXED;
     // level geometry
@@ -762,8 +883,9 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
         const long long nfaces_blocks = blocks_for((long long)l0.n * l0.n * l0.n, 256);
         if (nfaces_blocks > h->npartial) h->npartial = (int)nfaces_blocks;
     }
-    ALLOC(h->partial, (long long)h->npartial);
+    ALLOC(h->partial, 2LL * h->npartial);  // two partial arrays for paired sums
     ALLOC(h->st, 1LL);
+    ALLOC(h->cst, 1LL);
     for (int l = 0; l < h->L; ++l) {
         LevelHost &lh = h->lv[l];
         ALLOC(lh.kx64, lh.nel);
@@ -773,27 +895,46 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
             ALLOC(lh.kx16, lh.nel);
             ALLOC(lh.ky16, lh.nel);
             ALLOC(lh.kz16, lh.nel);
-            float *b, *x, *t1;
+            float *b, *x, *t1, *dv;
             ALLOC(b, lh.nel);
             ALLOC(x, lh.nel);
             ALLOC(t1, lh.nel);
+            ALLOC(dv, lh.nel);
             lh.b = b;
             lh.x = x;
             lh.t1 = t1;
+            lh.dinv = dv;
         } else {
-            double *b = nullptr, *x, *t1;
+            double *b = nullptr, *x, *t1, *dv;
             if (l > 0) ALLOC(b, lh.nel);
             ALLOC(x, lh.nel);
             ALLOC(t1, lh.nel);
+            ALLOC(dv, lh.nel);
+            lh.dinv = dv;
             lh.b = l == 0 ? (void *)h->R : (void *)b;  // FP64: the finest V-cycle input is r itself
             lh.x = x;
             lh.t1 = t1;
         }
     }
-    {
+    if (o.coarse_solver == 0) {
         const int nn = h->lv[h->L - 1].n - 2;
         h->m = nn * nn * nn;
         ALLOC(h->chol, (long long)h->m * h->m);
+    } else {  // truncated hierarchy: coarse CG direction and product on the coarsest level
+        const LevelHost &c = h->lv[h->L - 1];
+        if (mx) {
+            float *a, *b;
+            ALLOC(a, c.nel);
+            ALLOC(b, c.nel);
+            h->cp = a;
+            h->cq = b;
+        } else {
+            double *a, *b;
+            ALLOC(a, c.nel);
+            ALLOC(b, c.nel);
+            h->cp = a;
+            h->cq = b;
+        }
     }
     {
         char *dl;
@@ -966,6 +1107,10 @@ template <typename V, typename K>
 gmg_status hook_coarse(gmg_handle *h, const double *b, double *x) {
     LevelHost &c = h->lv[h->L - 1];
     STCHK(in_vec<V>(h, c, b, (V *)c.b));
+    if (h->opt.coarse_solver == 1) {
+        STCHK((coarse_cg<V, K>(h, nullptr)));
+        return out_vec<V>(h, c, (const V *)c.x, x);
+    }
     gmg::k_coarse_solve<V><<<1, 256, 0, h->stream>>>(c.n, c.pitch, c.plane, h->m, h->chol, (const V *)c.b, (V *)c.x,
                                                       nullptr);
     LAUNCHCHK();
@@ -1089,10 +1234,10 @@ gmg_status gmg_profile_get(gmg_handle *h, int32_t kclass, int32_t *launches, dou
 }
 
 const char *gmg_kernel_class_name(int32_t c) {
-    static const char *names[GMG_K_COUNT] = {"apply_dot",      "residual",  "update_xr",      "update_p",
+    static const char *names[GMG_K_COUNT] = {"apply_dot",      "residual",  "update_r",       "update_p",
                                              "cheb_first",     "cheb_step", "cheb_step_prev", "cheb_step_dot",
                                              "level_residual", "prolong",   "persistent",     "coarse_solve",
-                                             "face_gradient",  "restrict"};
+                                             "face_gradient",  "restrict",  "update_xp",      "cheb_pre2"};
     return (c >= 0 && c < GMG_K_COUNT) ? names[c] : "unknown";
 }
 

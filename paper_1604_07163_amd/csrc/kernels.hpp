@@ -74,6 +74,7 @@ struct Lev {
     long long plane; // n * pitch
     V s;             // h^-2
     const K *kx, *ky, *kz;
+    const V *dinv;   // 1 / diagonal of A at interior vertices, 0 elsewhere
 };
 
 // Per-level buffers the V-cycle uses (device-resident array of these).
@@ -111,9 +112,9 @@ template <typename T>
 __device__ __forceinline__ T diag7(T kw, T ke, T ks, T kn, T kb, T kt, T s) {
     return s * (((kw + ke) + (ks + kn)) + (kb + kt));
 }
-// first Chebyshev step from x0 = 0:  x1 = (1/theta) D^-1 b
+// first Chebyshev step from x0 = 0:  x1 = (1/theta) D^-1 b, with the stored D^-1
 template <typename T>
-__device__ __forceinline__ T cheb_first_val(T bv, T d, T c) { return c * (bv / d); }
+__device__ __forceinline__ T cheb_first_val(T bv, T dinv, T c) { return c * (bv * dinv); }
 // Chebyshev step: x_{j+1} = x_j + c1 (x_j - x_{j-1}) + c2 D^-1 (b - A x_j)
 template <typename T>
 __device__ __forceinline__ T cheb_step_val(T xc, T diff, T bv, T ax, T d, T c1, T c2) {
@@ -162,6 +163,7 @@ __device__ __forceinline__ double block_sum(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();  // a previous call's reader (thread 0) is done with red[]
     if (lane == 0) red[wave] = v;
     __syncthreads();
     double s = 0.0;
@@ -275,13 +277,8 @@ __global__ __launch_bounds__(NT) void k_cheb_first(Lev<V, K> L, Tiling t, const 
     if (skip && *skip) return;
     const Column col = tile_column(L.n, t);
     if (!col.active) return;
-    const int pitch = L.pitch;
-    const long long plane = L.plane;
-    long long o = (long long)col.k0 * plane + (long long)col.j * pitch + col.i;
-    V kb = kval(L.kz[o - plane]);
-    for (int k = col.k0; k < col.k1; ++k, o += plane) {
-        const V kw = kval(L.kx[o - 1]), ke = kval(L.kx[o]), ks = kval(L.ky[o - pitch]),
-                kn = kval(L.ky[o]), kt = kval(L.kz[o]);
+    long long o = (long long)col.k0 * L.plane + (long long)col.j * L.pitch + col.i;
+    for (int k = col.k0; k < col.k1; ++k, o += L.plane) {
         V bv;
         if (CVT) {
             bv = (V)r64[o];
@@ -289,8 +286,59 @@ __global__ __launch_bounds__(NT) void k_cheb_first(Lev<V, K> L, Tiling t, const 
         } else {
             bv = b[o];
         }
-        x_out[o] = cheb_first_val(bv, diag7(kw, ke, ks, kn, kb, kt, L.s), c);
+        x_out[o] = cheb_first_val(bv, L.dinv[o], c);
+    }
+}
+
+// The first two Chebyshev steps from zero in one sweep: x1 = c0 D^-1 b is
+// evaluated on the fly at the seven stencil points (it is pointwise), and
+//   x2 = x1 + c1 x1 + c2 D^-1 (b - A x1).
+// Same values as k_cheb_first followed by the PM = 1 step.  WX1 also stores
+// x1 (needed as the previous iterate when the degree exceeds 2).
+template <typename V, typename K, bool WX1>
+__global__ __launch_bounds__(NT) void k_cheb_pre2(Lev<V, K> L, Tiling t, const V *__restrict__ b,
+                                                  V *__restrict__ out, V *__restrict__ x1out, V c0, V c1, V c2,
+                                                  const int *__restrict__ skip) {
+    if (skip && *skip) return;
+    const Column col = tile_column(L.n, t);
+    if (!col.active) return;
+    const int pitch = L.pitch;
+    const long long plane = L.plane;
+    const V *__restrict__ dv = L.dinv;
+    long long o = (long long)col.k0 * plane + (long long)col.j * pitch + col.i;
+    V ub = cheb_first_val(b[o - plane], dv[o - plane], c0);
+    V bp = b[o];
+    V up = cheb_first_val(bp, dv[o], c0);
+    V kb = kval(L.kz[o - plane]);
+    for (int k = col.k0; k < col.k1; ++k, o += plane) {
+        const V bt = b[o + plane];
+        const V ut = cheb_first_val(bt, dv[o + plane], c0);
+        const V uw = cheb_first_val(b[o - 1], dv[o - 1], c0), ue = cheb_first_val(b[o + 1], dv[o + 1], c0);
+        const V us = cheb_first_val(b[o - pitch], dv[o - pitch], c0),
+                un = cheb_first_val(b[o + pitch], dv[o + pitch], c0);
+        const V kw = kval(L.kx[o - 1]), ke = kval(L.kx[o]), ks = kval(L.ky[o - pitch]), kn = kval(L.ky[o]),
+                kt = kval(L.kz[o]);
+        const V ax = apply7(up, uw, ue, us, un, ub, ut, kw, ke, ks, kn, kb, kt, L.s);
+        const V d = diag7(kw, ke, ks, kn, kb, kt, L.s);
+        out[o] = cheb_step_val(up, up, bp, ax, d, c1, c2);
+        if (WX1) x1out[o] = up;
+        ub = up;
+        up = ut;
+        bp = bt;
         kb = kt;
+    }
+}
+
+// D^-1 at the interior vertices of a level (setup).
+template <typename V, typename K>
+__global__ __launch_bounds__(NT) void k_dinv(Lev<V, K> L, Tiling t, V *__restrict__ dinv) {
+    const Column col = tile_column(L.n, t);
+    if (!col.active) return;
+    long long o = (long long)col.k0 * L.plane + (long long)col.j * L.pitch + col.i;
+    for (int k = col.k0; k < col.k1; ++k, o += L.plane) {
+        const V d = diag7(kval(L.kx[o - 1]), kval(L.kx[o]), kval(L.ky[o - L.pitch]), kval(L.ky[o]),
+                          kval(L.kz[o - L.plane]), kval(L.kz[o]), L.s);
+        dinv[o] = V(1) / d;
     }
 }
 
@@ -303,10 +351,11 @@ template <typename V, typename K, int PM, bool DOTR>
 __global__ __launch_bounds__(NT) void k_cheb_step(Lev<V, K> L, Tiling t, const V *__restrict__ b,
                                                   const V *__restrict__ x, const V *xp, V *out, V c1, V c2,
                                                   const double *__restrict__ r64, double *__restrict__ partial,
-                                                  const int *__restrict__ skip) {
+                                                  const int *__restrict__ skip,
+                                                  const double *__restrict__ q64 = nullptr) {
     if (skip && *skip) return;
     const Column col = tile_column(L.n, t);
-    double dot = 0.0;
+    double dot = 0.0, dotq = 0.0;
     if (col.active) {
         const int pitch = L.pitch;
         const long long plane = L.plane;
@@ -323,7 +372,10 @@ __global__ __launch_bounds__(NT) void k_cheb_step(Lev<V, K> L, Tiling t, const V
             const V diff = PM == 0 ? V(0) : PM == 1 ? up : up - xp[o];
             const V v = cheb_step_val(up, diff, b[o], ax, d, PM == 0 ? V(0) : c1, c2);
             out[o] = v;
-            if (DOTR) dot = fmaT(r64[o], (double)v, dot);
+            if (DOTR) {
+                dot = fmaT(r64[o], (double)v, dot);
+                if (q64) dotq = fmaT(q64[o], (double)v, dotq);
+            }
             ub = up;
             up = ut;
             kb = kt;
@@ -332,6 +384,10 @@ __global__ __launch_bounds__(NT) void k_cheb_step(Lev<V, K> L, Tiling t, const V
     if (DOTR) {
         const double s = block_sum<NT>(dot);
         if (threadIdx.x == 0) partial[blockIdx.x] = s;
+        if (q64) {  // flexible CG: second partial array q.z after the first
+            const double sq = block_sum<NT>(dotq);
+            if (threadIdx.x == 0) partial[gridDim.x + blockIdx.x] = sq;
+        }
     }
 }
 
@@ -531,9 +587,7 @@ __device__ void p_cheb_first(const LevBuf<V, K> &lb, V *out, V c) {
         int i, j, k;
         vertex_of<V, K>(L.n, u, i, j, k);
         const long long o = (long long)k * L.plane + (long long)j * L.pitch + i;
-        Nbr<V, K> q;
-        load_k(L, o, q);
-        out[o] = cheb_first_val(lb.b[o], diag7(q.kw, q.ke, q.ks, q.kn, q.kb, q.kt, L.s), c);
+        out[o] = cheb_first_val(lb.b[o], L.dinv[o], c);
     }
     __syncthreads();
 }
@@ -654,7 +708,7 @@ struct PcgState {
     int done;       // 1: stop (converged, breakdown or max_it); every loop kernel skips
     int status;     // 0 running/converged, 6 not converged, 7 breakdown
     int restart;    // 1: next p-update uses beta = 0
-    int pad;
+    int x_pending;  // 1: this iteration's x += alpha p is still to be applied
 };
 
 // The PCG vector kernels sweep only the interior rows (j, k in 1..n-2) of
@@ -687,28 +741,63 @@ struct Vec2<float> {
                        q_ = lane_;                                                                   \
              q_ < (R).half_w; q_ += tpr)
 
-// x += alpha p ; r -= alpha q ; partial = sum r^2
-__global__ __launch_bounds__(NT_FLAT) void k_update_xr(Rows R, double *__restrict__ x, double *__restrict__ r,
-                                                       const double *__restrict__ p, const double *__restrict__ q,
-                                                       const PcgState *__restrict__ st, double *__restrict__ partial) {
+// r -= alpha q ; partial = sum r^2 ; MIXED: also b32 = (float) r, the
+// right-hand side of the next V-cycle's finest level.
+template <typename B>
+__global__ __launch_bounds__(NT_FLAT) void k_update_r(Rows R, double *__restrict__ r, const double *__restrict__ q,
+                                                      B *__restrict__ b32, const PcgState *__restrict__ st,
+                                                      double *__restrict__ partial) {
     if (st->done) return;
     const double a = st->alpha;
+    typedef typename Vec2<B>::type B2;
     double acc = 0.0;
     ROW_LOOP(R) {
         const long long e = base_ + 2 * q_;
-        double2 xv = *(const double2 *)(x + e), rv = *(const double2 *)(r + e);
-        const double2 pv = *(const double2 *)(p + e), qv = *(const double2 *)(q + e);
-        xv.x = fmaT(a, pv.x, xv.x);
-        xv.y = fmaT(a, pv.y, xv.y);
+        double2 rv = *(const double2 *)(r + e);
+        const double2 qv = *(const double2 *)(q + e);
         rv.x = fmaT(-a, qv.x, rv.x);
         rv.y = fmaT(-a, qv.y, rv.y);
-        *(double2 *)(x + e) = xv;
         *(double2 *)(r + e) = rv;
+        if (b32) {
+            B2 bv;
+            bv.x = (B)rv.x;
+            bv.y = (B)rv.y;
+            *(B2 *)(b32 + e) = bv;
+        }
         acc = fmaT(rv.x, rv.x, acc);
         acc = fmaT(rv.y, rv.y, acc);
     }
     const double s = block_sum<NT_FLAT>(acc);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// x += alpha p_old ; p = z + beta p_old (skipped once the loop has stopped,
+// when z is stale).  Runs only while this iteration's x update is pending,
+// so iterations enqueued after the stop change nothing.
+template <typename Z>
+__global__ __launch_bounds__(NT_FLAT) void k_update_xp(Rows R, double *__restrict__ x, double *__restrict__ p,
+                                                       const Z *__restrict__ z, const PcgState *__restrict__ st) {
+    if (!st->x_pending) return;
+    const double a = st->alpha;
+    const bool upd_p = !st->done;
+    const double bta = st->beta;
+    typedef typename Vec2<Z>::type Z2;
+    ROW_LOOP(R) {
+        const long long e = base_ + 2 * q_;
+        const double2 pv = *(const double2 *)(p + e);
+        double2 xv = *(const double2 *)(x + e);
+        xv.x = fmaT(a, pv.x, xv.x);
+        xv.y = fmaT(a, pv.y, xv.y);
+        *(double2 *)(x + e) = xv;
+        if (upd_p) {
+            const Z2 zv = *(const Z2 *)(z + e);
+            *(double2 *)(p + e) = make_double2(fmaT(bta, pv.x, (double)zv.x), fmaT(bta, pv.y, (double)zv.y));
+        }
+    }
+}
+
+__global__ void k_clear_pending(PcgState *st) {
+    if (threadIdx.x == 0) st->x_pending = 0;
 }
 
 // p = z + beta p   (z FP64 or FP32)
@@ -758,17 +847,135 @@ __global__ __launch_bounds__(256) void k_copy(long long n16, const uint4 *__rest
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n16; e += stride) dst[e] = src[e];
 }
 
-enum Stage { ST_BB = 0, ST_RR0 = 1, ST_RHO0 = 2, ST_ALPHA = 3, ST_RR = 4, ST_BETA = 5, ST_TT = 6 };
+// ---------------------------------------------------------------- inexact coarse CG
+// Jacobi-preconditioned CG on the coarsest level of a truncated hierarchy:
+// V-precision vectors, FP64 sums, scalars in a PcgState of its own.  Two
+// partial arrays (gridDim.x each) carry pairs of sums.
+__global__ void k_cg_begin(PcgState *cst, const int *outer_done, double rtol2, int max_it) {
+    if (threadIdx.x != 0) return;
+    cst->its = 0;
+    cst->rtol2 = rtol2;
+    cst->max_it = max_it;
+    cst->status = 0;
+    cst->done = outer_done ? *outer_done : 0;
+}
+// x = 0, r = b, p = D^-1 r; sums b.b and r.D^-1 r
+template <typename V>
+__global__ __launch_bounds__(NT_FLAT) void k_cg_start(Rows R, const V *__restrict__ b, V *__restrict__ x,
+                                                      V *__restrict__ r, V *__restrict__ p,
+                                                      const V *__restrict__ dinv, double *__restrict__ partial,
+                                                      const int *__restrict__ skip) {
+    if (skip && *skip) return;
+    double bb = 0.0, rz = 0.0;
+    ROW_LOOP(R) {
+        for (int t = 0; t < 2; ++t) {
+            const long long e = base_ + 2 * q_ + t;
+            const V bv = b[e];
+            const V z = bv * dinv[e];
+            x[e] = V(0);
+            r[e] = bv;
+            p[e] = z;
+            bb = fmaT((double)bv, (double)bv, bb);
+            rz = fmaT((double)bv, (double)z, rz);
+        }
+    }
+    const double s1 = block_sum<NT_FLAT>(bb);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s1;
+    const double s2 = block_sum<NT_FLAT>(rz);
+    if (threadIdx.x == 0) partial[gridDim.x + blockIdx.x] = s2;
+}
+// x += alpha p, r -= alpha q; sums r.r and r.D^-1 r
+template <typename V>
+__global__ __launch_bounds__(NT_FLAT) void k_cg_update(Rows R, V *__restrict__ x, V *__restrict__ r,
+                                                       const V *__restrict__ p, const V *__restrict__ q,
+                                                       const V *__restrict__ dinv, const PcgState *__restrict__ st,
+                                                       double *__restrict__ partial) {
+    if (st->done) return;
+    const V a = (V)st->alpha;
+    double rr = 0.0, rz = 0.0;
+    ROW_LOOP(R) {
+        for (int t = 0; t < 2; ++t) {
+            const long long e = base_ + 2 * q_ + t;
+            x[e] = fmaT(a, p[e], x[e]);
+            const V rv = fmaT(-a, q[e], r[e]);
+            r[e] = rv;
+            rr = fmaT((double)rv, (double)rv, rr);
+            rz = fmaT((double)rv, (double)(rv * dinv[e]), rz);
+        }
+    }
+    const double s1 = block_sum<NT_FLAT>(rr);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s1;
+    const double s2 = block_sum<NT_FLAT>(rz);
+    if (threadIdx.x == 0) partial[gridDim.x + blockIdx.x] = s2;
+}
+// p = D^-1 r + beta p
+template <typename V>
+__global__ __launch_bounds__(NT_FLAT) void k_cg_p(Rows R, const V *__restrict__ r, V *__restrict__ p,
+                                                  const V *__restrict__ dinv, const PcgState *__restrict__ st) {
+    if (st->done) return;
+    const V bta = (V)st->beta;
+    ROW_LOOP(R) {
+        for (int t = 0; t < 2; ++t) {
+            const long long e = base_ + 2 * q_ + t;
+            p[e] = fmaT(bta, p[e], r[e] * dinv[e]);
+        }
+    }
+}
+
+enum Stage {
+    ST_BB = 0, ST_RR0 = 1, ST_RHO0 = 2, ST_ALPHA = 3, ST_RR = 4, ST_BETA = 5, ST_TT = 6,
+    ST_BETA_FLEX = 7,  // outer Polak-Ribiere: sums (r.z, q.z)
+    ST_C_INIT = 8,     // coarse CG: sums (b.b, r.D^-1 r)
+    ST_C_ALPHA = 9,    // coarse CG: p.Ap
+    ST_C_RR = 10       // coarse CG: sums (r.r, r.D^-1 r)
+};
 
 // Sum `count` partials in a fixed order and advance the PCG state.
 __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ partial, int count, int stage,
                                                   PcgState *__restrict__ st) {
-    if ((stage == ST_ALPHA || stage == ST_RR || stage == ST_BETA) && st->done) return;
+    if ((stage == ST_ALPHA || stage == ST_RR || stage == ST_BETA || stage == ST_BETA_FLEX || stage == ST_C_INIT ||
+         stage == ST_C_ALPHA || stage == ST_C_RR) &&
+        st->done)
+        return;
+    const bool two = stage == ST_BETA_FLEX || stage == ST_C_INIT || stage == ST_C_RR;
     double acc = 0.0;
     for (int w = threadIdx.x; w < count; w += 256) acc += partial[w];
     const double sum = block_sum<256>(acc);
+    double sum2 = 0.0;
+    if (two) {
+        double acc2 = 0.0;
+        for (int w = threadIdx.x; w < count; w += 256) acc2 += partial[count + w];
+        sum2 = block_sum<256>(acc2);
+    }
     if (threadIdx.x != 0) return;
     switch (stage) {
+    case ST_BETA_FLEX:  // beta = z_{k+1}.(r_{k+1} - r_k) / rho_k = -alpha (q.z) / rho
+        st->beta = -st->alpha * sum2 / st->rho;
+        st->rho = sum;
+        break;
+    case ST_C_INIT:
+        st->bb = sum;
+        st->rho = sum2;
+        if (!(sum > 0.0)) st->done = 1;
+        break;
+    case ST_C_ALPHA:
+        if (!(sum > 0.0) || sum > 1.7e308) {
+            st->status = 7;
+            st->done = 1;
+        } else {
+            st->alpha = st->rho / sum;
+        }
+        break;
+    case ST_C_RR:
+        st->rr = sum;
+        st->its += 1;
+        if (!(sum <= st->rtol2 * st->bb) && st->its < st->max_it && sum == sum) {
+            st->beta = sum2 / st->rho;
+            st->rho = sum2;
+        } else {
+            st->done = 1;
+        }
+        break;
     case ST_BB:
         st->bb = sum;
         break;
@@ -791,6 +998,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ par
             st->done = 1;
         } else {
             st->alpha = st->rho / sum;
+            st->x_pending = 1;
         }
         break;
     case ST_RR:

@@ -29,17 +29,20 @@ class Options(ctypes.Structure):
                 ("cheb_lo", ctypes.c_double), ("cheb_hi", ctypes.c_double), ("switch_n", ctypes.c_int32),
                 ("persistent_wgs", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("coarse_rule", ctypes.c_int32), ("coeff_is_log", ctypes.c_int32),
-                ("check_every", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("coarse_solver", ctypes.c_int32),
+                ("coarse_rtol", ctypes.c_double), ("coarse_max_it", ctypes.c_int32),
+                ("flexible", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("restarts", ctypes.c_int32), ("rel_res", ctypes.c_double),
-                ("rel_res_true", ctypes.c_double), ("setup_ms", ctypes.c_double), ("solve_ms", ctypes.c_double)]
+                ("rel_res_true", ctypes.c_double), ("setup_ms", ctypes.c_double), ("solve_ms", ctypes.c_double),
+                ("coarse_iterations", ctypes.c_int32)]
 
     def as_dict(self, status: int):
         return {"status": STATUS.get(status, str(status)), "iterations": self.iterations,
                 "restarts": self.restarts, "rel_res": self.rel_res, "rel_res_true": self.rel_res_true,
-                "setup_ms": self.setup_ms, "solve_ms": self.solve_ms}
+                "setup_ms": self.setup_ms, "solve_ms": self.solve_ms, "coarse_iterations": self.coarse_iterations}
 
 
 class GmgError(RuntimeError):
@@ -138,7 +141,7 @@ class Solver:
 
     def __init__(self, kx, ky, kz, *, levels=None, precision="fp64", switch_n=0, coarse_rule="arithmetic",
                  cheb_degree=2, cheb_lo=0.25, cheb_hi=2.0, coeff_is_log=False, check_every=0,
-                 persistent_wgs=1):
+                 persistent_wgs=1, coarse_solver="exact", coarse_rtol=1e-4, coarse_max_it=500, flexible=False):
         L = lib()
         n = int(kx.shape[0])
         self.n = n
@@ -155,6 +158,11 @@ class Solver:
                          if isinstance(coarse_rule, str) else int(coarse_rule))
         o.coeff_is_log = 1 if coeff_is_log else 0
         o.check_every = int(check_every)
+        o.coarse_solver = ({"exact": 0, "cg": 1}[coarse_solver] if isinstance(coarse_solver, str)
+                           else int(coarse_solver))
+        o.coarse_rtol = float(coarse_rtol)
+        o.coarse_max_it = int(coarse_max_it)
+        o.flexible = 1 if flexible else 0
         self.options = o
         self.levels = o.levels
         self._h = ctypes.c_void_p()
@@ -307,9 +315,9 @@ class Solver:
         return kx, ky, kz
 
 
-KERNEL_CLASSES = ["apply_dot", "residual", "update_xr", "update_p", "cheb_first", "cheb_step", "cheb_step_prev",
+KERNEL_CLASSES = ["apply_dot", "residual", "update_r", "update_p", "cheb_first", "cheb_step", "cheb_step_prev",
                   "cheb_step_dot", "level_residual", "prolong", "persistent", "coarse_solve", "face_gradient",
-                  "restrict"]
+                  "restrict", "update_xp", "cheb_pre2"]
 
 
 class Profile:

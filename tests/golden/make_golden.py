@@ -1,0 +1,100 @@
+"""Write the stored oracle results the full-size GPU parity tests compare with.
+
+Every value written here comes from the FP64 CPU oracle (`oracle/`) run on the
+seeded synthetic inputs of `paper_1604_07163_amd/inputs.py`; nothing comes from
+the GPU path.  Usage:
+
+    python tests/golden/make_golden.py lognormal257 adjoint129 [inclusions513]
+
+(inclusions513 takes ~25 minutes on 8 cores and ~20 GB of RAM.)
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from paper_1604_07163_amd import inputs  # noqa: E402
+
+NSAMPLE = 4096
+
+
+def sample_points(n, seed=123):
+    g = np.random.default_rng(seed)
+    m = n - 2
+    flat = g.choice(m ** 3, size=NSAMPLE, replace=False)
+    i = 1 + flat % m
+    j = 1 + (flat // m) % m
+    k = 1 + flat // (m * m)
+    return np.stack([k, j, i], axis=1)
+
+
+def forward(name, n, levels, k, f, rtol=1e-8, max_it=2000):
+    t = time.time()
+    H = oracle.Hierarchy(*k, levels=levels)
+    x, info = H.solve(f, rtol=rtol, max_it=max_it)
+    pts = sample_points(n)
+    vals = x[pts[:, 0], pts[:, 1], pts[:, 2]]
+    out = {"workload": name, "n": n, "levels": levels, "rtol": rtol, "iterations": info["iterations"],
+           "status": info["status"], "rel_res_true": info["rel_res_true"],
+           "norm2": float(np.linalg.norm(x)), "sample_points": pts.tolist(), "sample_values": vals.tolist(),
+           "seconds": time.time() - t}
+    print(name, info, f"{time.time() - t:.1f}s", flush=True)
+    return out, x, H
+
+
+def lognormal257():
+    w = inputs.WORKLOADS["lognormal257"]
+    n, levels = w["n"], w["levels"]
+    k = inputs.lognormal_k(n, w["k_seed"])
+    f = inputs.uniform_rhs(n, w["f_seed"])
+    out, _, _ = forward("lognormal257", n, levels, k, f)
+    return out
+
+
+def inclusions513():
+    w = inputs.WORKLOADS["inclusions513"]
+    n, levels = w["n"], w["levels"]
+    kx, ky, kz, _ = inputs.inclusion_k(n, w["k_seed"])
+    f = inputs.uniform_rhs(n, w["f_seed"])
+    out, _, _ = forward("inclusions513", n, levels, (kx, ky, kz), f)
+    return out
+
+
+def adjoint129():
+    w = inputs.WORKLOADS["adjoint129"]
+    n, levels = w["n"], w["levels"]
+    theta_field = inputs.lognormal_k(n, w["k_seed"])
+    kobs = inputs.lognormal_k(n, w["kobs_seed"])
+    f = inputs.uniform_rhs(n, w["f_seed"])
+    Hobs = oracle.Hierarchy(*kobs, levels=levels)
+    phi_obs, _ = Hobs.solve(f, rtol=1e-13, max_it=500)
+    H = oracle.Hierarchy(*theta_field, levels=levels)
+    phi, info = H.solve(f, rtol=1e-13, max_it=500)
+    gx, gy, gz, lam, ainfo = H.adjoint_gradient(phi, phi - phi_obs, rtol=1e-13, max_it=500)
+    g = (gx, gy, gz)
+    faces = inputs.sample_faces(n, 50, w["face_seed"])
+    vals = [float(g[ax][kk, jj, ii]) for ax, kk, jj, ii in faces]
+    out = {"workload": "adjoint129", "n": n, "levels": levels, "faces": [list(map(int, f_)) for f_ in faces],
+           "gradient": vals, "gmax": float(max(np.abs(a).max() for a in g)),
+           "gsum": float(gx.sum() + gy.sum() + gz.sum()),
+           "loss": float(0.5 * np.sum((phi - phi_obs) ** 2)),
+           "forward_iterations": info["iterations"], "adjoint_iterations": ainfo["iterations"]}
+    print("adjoint129", out["forward_iterations"], out["adjoint_iterations"], out["gmax"], flush=True)
+    return out
+
+
+if __name__ == "__main__":
+    which = sys.argv[1:] or ["lognormal257", "adjoint129"]
+    for name in which:
+        res = globals()[name]()
+        with open(os.path.join(HERE, f"oracle_{name}.json"), "w") as fh:
+            json.dump(res, fh)

@@ -1,0 +1,204 @@
+"""Full-size workloads on the GPU against stored oracle results (tests/golden/).
+
+The stored values were written by tests/golden/make_golden.py, which runs only
+the CPU oracle.  Solutions are compared on 4096 seeded sample points; the
+adjoint on 50 seeded links, plus a cancellation-free finite-difference check
+that uses only GPU solves.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1604_07163_amd import gmg, inputs
+from paper_1604_07163_amd.autograd import diffusion_solve
+from tests.gpu_util import say, to_gpu, to_np
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def golden(name):
+    p = os.path.join(GOLDEN, f"oracle_{name}.json")
+    if not os.path.exists(p):
+        pytest.skip(f"{p} not generated")
+    return json.load(open(p))
+
+
+def sampled(x, g):
+    pts = np.asarray(g["sample_points"])
+    return to_np(x)[pts[:, 0], pts[:, 1], pts[:, 2]]
+
+
+def sample_rel(x, g):
+    ref = np.asarray(g["sample_values"])
+    v = sampled(x, g)
+    return float(np.linalg.norm(v - ref) / np.linalg.norm(ref))
+
+
+@pytest.mark.parametrize("switch_n", [0, 17])
+def test_lognormal257_fp64(switch_n):
+    g = golden("lognormal257")
+    w = inputs.WORKLOADS["lognormal257"]
+    n, levels = w["n"], w["levels"]
+    k = inputs.lognormal_k(n, w["k_seed"])
+    f = to_gpu(inputs.uniform_rhs(n, w["f_seed"]))
+    s = gmg.Solver(*[to_gpu(a) for a in k], levels=levels, switch_n=switch_n)
+    x, info = s.solve(f, rtol=1e-8)
+    say(f"  257^3 switch={switch_n}: its {info['iterations']} (oracle {g['iterations']}), "
+        f"true {info['rel_res_true']:.2e}, {info['solve_ms']:.1f} ms")
+    assert info["status"] == "GMG_OK" and abs(info["iterations"] - g["iterations"]) <= 1
+    assert info["rel_res_true"] <= 1e-8
+    xf, inf2 = s.solve(f, rtol=0.0, max_it=g["iterations"])
+    d = sample_rel(xf, g)
+    say(f"    forced {g['iterations']} its: sampled rel diff {d:.2e}; norm {float(xf.norm()):.12e} vs {g['norm2']:.12e}")
+    assert d <= 1e-10
+    assert abs(float(xf.norm()) - g["norm2"]) <= 1e-10 * g["norm2"]
+
+
+def test_lognormal257_switch_sweep_identical():
+    """Switch level is a performance knob only: identical iterates for every switch."""
+    w = inputs.WORKLOADS["lognormal257"]
+    n, levels = w["n"], w["levels"]
+    kg = [to_gpu(a) for a in inputs.lognormal_k(n, w["k_seed"])]
+    f = to_gpu(inputs.uniform_rhs(n, w["f_seed"]))
+    base = None
+    for sw in [0, 65, 33, 17, 9]:
+        s = gmg.Solver(*kg, levels=levels, switch_n=sw)
+        x, info = s.solve(f, rtol=1e-8)
+        say(f"  switch {sw}: its {info['iterations']} {info['solve_ms']:.1f} ms")
+        if base is None:
+            base = (x, info["iterations"])
+        else:
+            assert info["iterations"] == base[1]
+            assert float((x - base[0]).abs().max()) <= 1e-14 * float(base[0].abs().max())
+        s.close()
+
+
+def test_lognormal257_mixed():
+    g = golden("lognormal257")
+    w = inputs.WORKLOADS["lognormal257"]
+    n, levels = w["n"], w["levels"]
+    kg = [to_gpu(a) for a in inputs.lognormal_k(n, w["k_seed"])]
+    f = to_gpu(inputs.uniform_rhs(n, w["f_seed"]))
+    s = gmg.Solver(*kg, levels=levels, precision="mixed", switch_n=17)
+    x, info = s.solve(f, rtol=1e-8)
+    d = sample_rel(x, g)
+    say(f"  mixed 257^3: its {info['iterations']} (oracle {g['iterations']}), restarts {info['restarts']}, "
+        f"true {info['rel_res_true']:.2e}, sampled error vs oracle {d:.2e}")
+    assert info["status"] == "GMG_OK" and info["rel_res_true"] <= 1e-8
+    assert info["iterations"] <= g["iterations"] + 2
+    assert d <= 1e-6
+
+
+def test_inclusions513_fp64_and_mixed():
+    g = golden("inclusions513")
+    w = inputs.WORKLOADS["inclusions513"]
+    n, levels = w["n"], w["levels"]
+    kx, ky, kz, _ = inputs.inclusion_k(n, w["k_seed"])
+    kg = [to_gpu(a) for a in (kx, ky, kz)]
+    f = to_gpu(inputs.uniform_rhs(n, w["f_seed"]))
+    s = gmg.Solver(*kg, levels=levels, switch_n=17)
+    x, info = s.solve(f, rtol=1e-8, max_it=2000)
+    say(f"  513^3 fp64: its {info['iterations']} (oracle {g['iterations']}), {info['solve_ms']:.0f} ms")
+    assert info["status"] == "GMG_OK" and abs(info["iterations"] - g["iterations"]) <= 1
+    xf, _ = s.solve(f, rtol=0.0, max_it=g["iterations"])
+    d = sample_rel(xf, g)
+    say(f"    forced: sampled rel diff {d:.2e}")
+    assert d <= 1e-10
+    s.close()
+    del s
+    sm = gmg.Solver(*kg, levels=levels, precision="mixed", switch_n=17)
+    xm, im = sm.solve(f, rtol=1e-8, max_it=2000)
+    dm = sample_rel(xm, g)
+    say(f"  513^3 mixed: its {im['iterations']}, restarts {im['restarts']}, true {im['rel_res_true']:.2e}, "
+        f"{im['solve_ms']:.0f} ms (fp64 {info['solve_ms']:.0f} ms), sampled error vs oracle {dm:.2e}")
+    assert im["status"] == "GMG_OK" and im["rel_res_true"] <= 1e-8
+    assert im["iterations"] <= g["iterations"] + 2 + g["iterations"] // 10
+    assert dm <= 1e-6
+
+
+def test_adjoint129_against_oracle_and_finite_differences():
+    g = golden("adjoint129")
+    w = inputs.WORKLOADS["adjoint129"]
+    n, levels = w["n"], w["levels"]
+    k = inputs.lognormal_k(n, w["k_seed"])
+    kobs = inputs.lognormal_k(n, w["kobs_seed"])
+    f = to_gpu(inputs.uniform_rhs(n, w["f_seed"]))
+    sobs = gmg.Solver(*[to_gpu(a) for a in kobs], levels=levels)
+    phi_obs, _ = sobs.solve(f, rtol=1e-13)
+    sobs.close()
+    theta = [to_gpu(np.log(a)).requires_grad_(True) for a in k]
+    solver = gmg.Solver(*[t.detach() for t in theta], levels=levels, coeff_is_log=True)
+    phi = diffusion_solve(*theta, f, solver, 1e-13, 500)
+    loss = 0.5 * ((phi - phi_obs) ** 2).sum()
+    loss.backward()
+    grads = [t.grad for t in theta]
+    say(f"  loss {float(loss):.10e} (oracle {g['loss']:.10e})")
+    assert abs(float(loss) - g["loss"]) <= 1e-9 * g["loss"]
+    gmax = g["gmax"]
+    for (ax, kk, jj, ii), ref in zip(g["faces"], g["gradient"]):
+        got = float(grads[ax][kk, jj, ii])
+        assert abs(got - ref) / max(abs(ref), 1e-3 * gmax) <= 1e-6, (ax, kk, jj, ii, got, ref)
+    total = float(sum(t.sum() for t in grads))
+    assert abs(total - g["gsum"]) <= 1e-8 * abs(g["gsum"])
+    # sum rule from GPU quantities: sum_f dL/dln k_f = -phi . (phi - phi_obs)
+    rule = -float((phi.detach() * (phi.detach() - phi_obs)).sum())
+    assert abs(total - rule) <= 1e-8 * abs(rule)
+    # cancellation-free central differences with GPU solves (h = 1e-6)
+    eps = 1e-6
+    s2 = (n - 1) ** 2
+    kpm = [to_gpu(a) for a in k]
+    fd = gmg.Solver(*kpm, levels=levels)
+    worst = 0.0
+    for (ax, kk, jj, ii), ref in zip(g["faces"], g["gradient"]):
+        kf = float(kpm[ax][kk, jj, ii])
+        km = [a.clone() for a in kpm]
+        kp = [a.clone() for a in kpm]
+        km[ax][kk, jj, ii] = kf * np.exp(-eps)
+        kp[ax][kk, jj, ii] = kf * np.exp(eps)
+        fd.set_coefficients(*km)
+        phim, _ = fd.solve(f, rtol=1e-13)
+        p = (kk, jj, ii)
+        q = (kk, jj, ii + 1) if ax == 0 else (kk, jj + 1, ii) if ax == 1 else (kk + 1, jj, ii)
+        inner = lambda v: all(1 <= c <= n - 2 for c in v)  # noqa: E731
+        dk = 2.0 * kf * np.sinh(eps)
+        diff = (float(phim[p]) if inner(p) else 0.0) - (float(phim[q]) if inner(q) else 0.0)
+        rhs = torch.zeros_like(f)
+        if inner(p):
+            rhs[p] = -s2 * dk * diff
+        if inner(q):
+            rhs[q] = s2 * dk * diff
+        fd.set_coefficients(*kp)
+        dphi, _ = fd.solve(rhs, rtol=1e-13)
+        dL = 0.5 * float((dphi * (2 * phim + dphi - 2 * phi_obs)).sum())
+        gfd = dL / (2 * eps)
+        got = float(grads[ax][kk, jj, ii])
+        rel = abs(gfd - got) / max(abs(got), 1e-3 * gmax)
+        worst = max(worst, rel)
+        assert rel <= 1e-6, (ax, kk, jj, ii, gfd, got)
+    say(f"  FD check on 50 links: worst relative error {worst:.2e}")
+
+
+def test_autograd_gradcheck_small():
+    n, levels = 9, 3
+    k = inputs.lognormal_k(n, 3, width=2.0)
+    theta = [to_gpu(np.log(a)).requires_grad_(True) for a in k]
+    f = to_gpu(inputs.uniform_rhs(n, 4)).requires_grad_(True)
+    solver = gmg.Solver(*[t.detach() for t in theta], levels=levels, coeff_is_log=True)
+    w = to_gpu(np.random.default_rng(5).standard_normal((n, n, n)))
+
+    def fn(tx, ty, tz, ff):
+        return (diffusion_solve(tx, ty, tz, ff, solver, 1e-14, 200) * w).sum()
+
+    assert torch.autograd.gradcheck(fn, (*theta, f), eps=1e-6, atol=1e-8, rtol=1e-5)
+
+
+def test_gpu_input_generator_matches_host_recipe():
+    n = 65
+    a = inputs.lognormal_log10_field(n, 11, width=8.0, clip=3.0)
+    b = to_np(inputs.lognormal_log10_field_gpu(n, 11, width=8.0, clip=3.0))
+    assert np.abs(a - b).max() <= 1e-12
+    np.testing.assert_array_equal(to_np(inputs.uniform_rhs_gpu(n, 12)), inputs.uniform_rhs(n, 12))

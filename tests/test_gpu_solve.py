@@ -10,7 +10,7 @@ import torch
 
 import oracle
 from paper_1604_07163_amd import gmg, inputs
-from tests.gpu_util import rel_l2, rel_max, say, to_gpu, to_np
+from tests.gpu_util import rand_vec, rel_l2, rel_max, say, to_gpu, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -133,3 +133,26 @@ def test_adjoint_gradient_vs_oracle():
     for a, b in ((gx, gxo), (gy, gyo), (gz, gzo)):
         assert np.abs(to_np(a) - b).max() <= 1e-6 * scale
     assert rel_max(to_np(lam), lamo) <= 1e-9
+
+
+@pytest.mark.parametrize("n,levels", [(65, 3), (129, 4)])
+def test_truncated_hierarchy_flexible_cg(n, levels):
+    """Truncation arm: the hierarchy stops early and the (large) coarsest level
+    is solved by Jacobi-CG to 1e-4; the outer CG is flexible (Polak-Ribiere)."""
+    kx, ky, kz, _ = inputs.inclusion_k(n, 4)
+    f = inputs.uniform_rhs(n, 5)
+    H = oracle.Hierarchy(kx, ky, kz, levels=levels, coarse_solver=1, coarse_rtol=1e-4, coarse_max_it=500)
+    xo, io = H.solve(f, rtol=1e-8, max_it=500, flexible=True)
+    s = gmg.Solver(*[to_gpu(a) for a in (kx, ky, kz)], levels=levels, coarse_solver="cg", coarse_rtol=1e-4,
+                   coarse_max_it=500, flexible=True)
+    fg = to_gpu(f)
+    xg, ig = s.solve(fg, rtol=1e-8, max_it=500)
+    say(f"    truncated n={n} levels={levels}: its gpu {ig['iterations']} oracle {io['iterations']}; "
+        f"coarse its gpu {ig['coarse_iterations']} oracle {io['coarse_iterations']}; {ig['solve_ms']:.1f} ms")
+    assert ig["status"] == "GMG_OK" and abs(ig["iterations"] - io["iterations"]) <= 1
+    assert ig["rel_res_true"] <= 1e-8
+    assert forced_parity(s, fg, xo, io["iterations"]) <= 1e-10
+    # the coarse solve hook against the oracle's coarse CG
+    nc = H.level_n(levels - 1)
+    b = rand_vec(nc, 7)
+    assert rel_max(to_np(s.coarse_solve(to_gpu(b))), H.coarse_solve(b)) <= 1e-10

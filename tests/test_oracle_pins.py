@@ -474,3 +474,56 @@ def test_not_converged_and_zero_rhs(oracle_mod):
     assert info["status"] == "ERR_NOT_CONVERGED" and info["iterations"] == 1
     x, info = H.solve(np.zeros((n, n, n)), rtol=1e-8)
     assert info["status"] == "OK" and info["iterations"] == 0 and np.all(x == 0)
+
+
+# ---------------------------------------------------------------- truncation arm + flexible CG
+def test_truncated_coarse_cg_meets_its_tolerance(oracle_mod):
+    """The inexact coarse solve of a truncated hierarchy is Jacobi-CG: its
+    residual against the dense coarse operator meets the relative target, and
+    with a tiny target it reproduces the dense solve."""
+    n, levels = 17, 2
+    kx, ky, kz = rand_k(n, 81)
+    om = oracle_mod
+    b = rand_vec(9, 4)
+    ks = om.Hierarchy(kx, ky, kz, levels=levels).level_k(1)
+    A = mf.dense_from_links(*ks)
+    for rtol in (1e-4, 1e-12):
+        H = om.Hierarchy(kx, ky, kz, levels=levels, coarse_solver=1, coarse_rtol=rtol, coarse_max_it=2000)
+        x = H.coarse_solve(b)
+        res = np.linalg.norm(mf.interior(b) - A @ mf.interior(x)) / np.linalg.norm(mf.interior(b))
+        assert res <= rtol
+    np.testing.assert_allclose(mf.interior(x), np.linalg.solve(A, mf.interior(b)), rtol=1e-9, atol=1e-12)
+
+
+def test_truncated_vcycle_with_tight_coarse_tolerance_is_exact_vcycle(oracle_mod):
+    n, levels = 17, 3
+    kx, ky, kz = rand_k(n, 82)
+    He = oracle_mod.Hierarchy(kx, ky, kz, levels=levels)
+    Ht = oracle_mod.Hierarchy(kx, ky, kz, levels=levels, coarse_solver=1, coarse_rtol=1e-15, coarse_max_it=5000)
+    r = rand_vec(n, 5)
+    a, b = He.vcycle(r), Ht.vcycle(r)
+    assert np.abs(a - b).max() <= 1e-11 * np.abs(a).max()
+
+
+def test_flexible_cg_equals_cg_for_a_fixed_preconditioner(oracle_mod):
+    """For a fixed SPD preconditioner z_{k+1}.r_k = 0, so the Polak-Ribiere beta
+    equals the standard one and both recurrences give the same iterates."""
+    n = 33
+    H = oracle_mod.Hierarchy(*inputs.lognormal_k(n, 2, width=3.0), levels=5)
+    f = inputs.uniform_rhs(n, 3)
+    x1, i1 = H.solve(f, rtol=1e-10)
+    x2, i2 = H.solve(f, rtol=1e-10, flexible=True)
+    assert i1["iterations"] == i2["iterations"]
+    assert np.abs(x1 - x2).max() <= 1e-9 * np.abs(x1).max()
+
+
+@pytest.mark.parametrize("n,levels", [(9, 2), (17, 2)])
+def test_truncated_flexible_solve_reaches_dense_solution(oracle_mod, n, levels):
+    kx, ky, kz = rand_k(n, 83 + n)
+    f = inputs.uniform_rhs(n, 6)
+    H = oracle_mod.Hierarchy(kx, ky, kz, levels=levels, coarse_solver=1, coarse_rtol=1e-4, coarse_max_it=500)
+    x, info = H.solve(f, rtol=1e-12, flexible=True)
+    A = mf.dense_from_links(kx, ky, kz)
+    ref = np.linalg.solve(A, mf.interior(f))
+    assert info["status"] == "OK" and info["coarse_iterations"] > 0
+    np.testing.assert_allclose(mf.interior(x), ref, rtol=1e-9, atol=1e-10 * np.abs(ref).max())

@@ -132,6 +132,46 @@ def cpu_baseline(w, k, f, its_needed, iters=2):
             "seconds_per_iteration": per_it}
 
 
+def sweep(args):
+    """Switch-level sweep (grid launches vs the persistent coarse kernel) and the
+    truncation arm, forward solves on the chosen workload; prints one JSON line."""
+    import numpy as np
+    import torch
+    from paper_1604_07163_amd import gmg
+    w = WORKLOADS[args.workload]
+    n, levels = w["n"], w["levels"]
+    k_np, _, f_np = make_inputs(w)
+    k = [torch.from_numpy(a).cuda() for a in k_np]
+    f = torch.from_numpy(f_np).cuda()
+    rows = []
+    sizes = [0] + [s for s in (65, 33, 17, 9) if s < n]
+    configs = [dict(precision=p, switch_n=sw) for p in ("fp64", "mixed") for sw in sizes]
+    for lt in args.truncate:
+        configs.append(dict(precision="fp64", levels=lt, coarse_solver="cg", coarse_rtol=1e-4, flexible=True))
+    for cfg in configs:
+        kw = dict(cfg)
+        lv = kw.pop("levels", levels)
+        s = gmg.Solver(*k, levels=lv, **kw)
+        s.solve(f, rtol=args.rtol, max_it=3000)
+        ts, info = [], None
+        for _ in range(max(1, args.steps)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info = s.solve(f, rtol=args.rtol, max_it=3000)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        with gmg.Profile(s) as pr:
+            s.solve(f, rtol=args.rtol, max_it=3000)
+        coarse = pr.result.get("persistent") or pr.result.get("coarse_solve") or {}
+        row = {"levels": lv, **cfg, "iterations": info["iterations"], "coarse_iterations": info["coarse_iterations"],
+               "ms": 1e3 * float(np.median(ts)), "ms_per_iteration": 1e3 * float(np.median(ts)) / info["iterations"],
+               "coarse_kernel_us": 1e3 * coarse.get("avg_ms", 0.0), "rel_res_true": info["rel_res_true"]}
+        log(json.dumps(row))
+        rows.append(row)
+        s.close()
+    print(json.dumps({"workload": args.workload, "n": n, "rtol": args.rtol, "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -143,10 +183,17 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--sweep", action="store_true",
+                    help="switch-level / truncation sweep of forward solves instead of the benchmark step")
+    ap.add_argument("--truncate", type=int, nargs="*", default=[],
+                    help="with --sweep: also time truncated hierarchies with these level counts")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1).", flush=True)
         sys.exit(2)
+    if args.sweep:
+        sweep(args)
+        return
 
     import numpy as np
     import torch

@@ -34,7 +34,8 @@ struct LevelHost {
     double *kx64 = nullptr, *ky64 = nullptr, *kz64 = nullptr;
     bf16 *kx16 = nullptr, *ky16 = nullptr, *kz16 = nullptr;
     void *b = nullptr, *x = nullptr, *t1 = nullptr, *dinv = nullptr;
-    Tiling til{};
+    Tiling til{};    // V-cycle stencil kernels
+    Tiling til64{};  // FP64 outer operator (apply, residual)
     gmg::Rows rows{};
 };
 
@@ -100,18 +101,22 @@ gmg_status fail(gmg_handle *h, gmg_status s, const std::string &msg) {
 int round_up(int a, int b) { return (a + b - 1) / b * b; }
 unsigned blocks_for(long long n, int nt) { return (unsigned)((n + nt - 1) / nt); }
 
-int target_wgs() {
-    const char *e = getenv("GMG_TARGET_WGS");
-    int v = e ? atoi(e) : 0;
-    return v > 0 ? v : 8192;
+// Workgroup-count targets of the z-marching stencil kernels (the z-chunk
+// length follows from them).  Measured on MI355X at 513^3: FP32/BF16 sweeps
+// stream best with one chunk per column (about 1024 workgroups, all resident
+// and advancing through z together); FP64 sweeps with short chunks.
+int env_int(const char *name, int dflt) {
+    const char *e = getenv(name);
+    const int v = e ? atoi(e) : 0;
+    return v > 0 ? v : dflt;
 }
 
-Tiling make_tiling(int n) {
+Tiling make_tiling(int n, int target) {
     Tiling t;
     t.tiles_x = (n - 2) / gmg::TX + 1;  // covers i = 0 .. n-2
     t.tiles_y = (n - 2 + gmg::TY - 1) / gmg::TY;
     const int planes = n - 2;
-    int nch = (target_wgs() + t.tiles_x * t.tiles_y - 1) / (t.tiles_x * t.tiles_y);
+    int nch = (target + t.tiles_x * t.tiles_y - 1) / (t.tiles_x * t.tiles_y);
     if (nch < 1) nch = 1;
     if (nch > planes) nch = planes;
     t.zchunk = (planes + nch - 1) / nch;
@@ -120,15 +125,30 @@ Tiling make_tiling(int n) {
     return t;
 }
 
+// Prolongation grid: one thread per coarse cell (I,J,K), I,J,K in 0..nc-2.
+dim3 prolong_grid(int nc) {
+    return dim3((unsigned)((nc - 1 + gmg::TX - 1) / gmg::TX), (unsigned)((nc - 1 + gmg::TY - 1) / gmg::TY),
+                (unsigned)(nc - 1));
+}
+
 gmg::Rows make_rows(int n, int pitch, long long plane) {
     gmg::Rows r;
     r.n = n;
     r.pitch = pitch;
     r.plane = plane;
     r.half_w = n / 2;  // pairs cover x = 0 .. 2*half_w-1 (>= n-2, <= pitch)
+    const long long nrows = (long long)(n - 2) * (n - 2);
     int l = 0;
     while ((1 << l) < r.half_w && (1 << l) < gmg::NT_FLAT) ++l;
     r.tpr_log2 = l;
+    if (r.half_w >= gmg::NT_FLAT) {
+        r.segs = (r.half_w + gmg::NT_FLAT - 1) / gmg::NT_FLAT;
+        r.nblocks = (int)(nrows * r.segs);
+    } else {
+        r.segs = 0;
+        const int rpb = gmg::NT_FLAT >> l;
+        r.nblocks = (int)((nrows + rpb - 1) / rpb);
+    }
     return r;
 }
 
@@ -309,14 +329,14 @@ gmg_status smooth_grid(gmg_handle *h, int l, bool from_zero, const double *r64_c
         LAUNCHCHK();
     }
     if (dot_r64 && nparts && *nparts == 0) {
-        gmg::k_dot<V><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(lh.rows, dot_r64, bufs[0], h->partial, skip);
+        gmg::k_dot<V><<<lh.rows.nblocks, gmg::NT_FLAT, 0, h->stream>>>(lh.rows, dot_r64, bufs[0], h->partial, skip);
         LAUNCHCHK();
         if (dot_q64) {
-            gmg::k_dot<V><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(lh.rows, dot_q64, bufs[0],
-                                                                         h->partial + gmg::NB_FLAT, skip);
+            gmg::k_dot<V><<<lh.rows.nblocks, gmg::NT_FLAT, 0, h->stream>>>(lh.rows, dot_q64, bufs[0],
+                                                                            h->partial + lh.rows.nblocks, skip);
             LAUNCHCHK();
         }
-        *nparts = gmg::NB_FLAT;
+        *nparts = lh.rows.nblocks;
     }
     return GMG_OK;
 }
@@ -332,21 +352,21 @@ gmg_status coarse_cg(gmg_handle *h, const int *skip) {
     gmg::k_cg_begin<<<1, 64, 0, h->stream>>>(h->cst, skip, h->opt.coarse_rtol * h->opt.coarse_rtol,
                                              h->opt.coarse_max_it);
     LAUNCHCHK();
-    gmg::k_cg_start<V><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(c.rows, (const V *)c.b, (V *)c.x, (V *)c.t1,
-                                                                      (V *)h->cp, (const V *)c.dinv, h->partial, cskip);
+    gmg::k_cg_start<V><<<c.rows.nblocks, gmg::NT_FLAT, 0, h->stream>>>(c.rows, (const V *)c.b, (V *)c.x, (V *)c.t1,
+                                                                        (V *)h->cp, (const V *)c.dinv, h->partial, cskip);
     LAUNCHCHK();
-    STCHK(finalize(h, gmg::NB_FLAT, gmg::ST_C_INIT, h->cst));
+    STCHK(finalize(h, c.rows.nblocks, gmg::ST_C_INIT, h->cst));
     for (int chunk = 0; chunk * 8 < h->opt.coarse_max_it + 8; ++chunk) {
         for (int i = 0; i < 8; ++i) {
             gmg::k_apply<V, K, true><<<c.til.nblocks, gmg::NT, 0, h->stream>>>(view<V, K>(c), c.til, (const V *)h->cp,
                                                                                (V *)h->cq, h->partial, cskip);
             LAUNCHCHK();
             STCHK(finalize(h, c.til.nblocks, gmg::ST_C_ALPHA, h->cst));
-            gmg::k_cg_update<V><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(
+            gmg::k_cg_update<V><<<c.rows.nblocks, gmg::NT_FLAT, 0, h->stream>>>(
                 c.rows, (V *)c.x, (V *)c.t1, (const V *)h->cp, (const V *)h->cq, (const V *)c.dinv, h->cst, h->partial);
             LAUNCHCHK();
-            STCHK(finalize(h, gmg::NB_FLAT, gmg::ST_C_RR, h->cst));
-            gmg::k_cg_p<V><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(c.rows, (const V *)c.t1, (V *)h->cp,
+            STCHK(finalize(h, c.rows.nblocks, gmg::ST_C_RR, h->cst));
+            gmg::k_cg_p<V><<<c.rows.nblocks, gmg::NT_FLAT, 0, h->stream>>>(c.rows, (const V *)c.t1, (V *)h->cp,
                                                                           (const V *)c.dinv, h->cst);
             LAUNCHCHK();
         }
@@ -409,14 +429,15 @@ gmg_status vcycle(gmg_handle *h, const int *skip, bool want_dot, int *nparts, bo
         }
         STCHK((coarse_part<V, K>(h, skip)));
         if (want_dot) {
-            gmg::k_dot<V><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(l0.rows, h->R, (const V *)l0.x, h->partial, skip);
+            gmg::k_dot<V><<<l0.rows.nblocks, gmg::NT_FLAT, 0, h->stream>>>(l0.rows, h->R, (const V *)l0.x, h->partial,
+                                                                            skip);
             LAUNCHCHK();
             if (h->opt.flexible) {
-                gmg::k_dot<V><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(l0.rows, h->Q, (const V *)l0.x,
-                                                                             h->partial + gmg::NB_FLAT, skip);
+                gmg::k_dot<V><<<l0.rows.nblocks, gmg::NT_FLAT, 0, h->stream>>>(l0.rows, h->Q, (const V *)l0.x,
+                                                                                h->partial + l0.rows.nblocks, skip);
                 LAUNCHCHK();
             }
-            *nparts = gmg::NB_FLAT;
+            *nparts = l0.rows.nblocks;
         }
         return GMG_OK;
     }
@@ -431,8 +452,8 @@ gmg_status vcycle(gmg_handle *h, const int *skip, bool want_dot, int *nparts, bo
         LevelHost &f = h->lv[l], &c = h->lv[l + 1];
         {
             Prof pf(h, GMG_K_PROLONG, l == 0);
-            gmg::k_prolong<V><<<f.til.nblocks, gmg::NT, 0, h->stream>>>(f.n, f.pitch, f.plane, f.til, (const V *)c.x,
-                                                                        c.pitch, c.plane, (V *)f.x, skip);
+            gmg::k_prolong<V><<<prolong_grid(c.n), gmg::NT, 0, h->stream>>>(f.pitch, f.plane, c.n, c.pitch, c.plane,
+                                                                            (const V *)c.x, (V *)f.x, skip);
             LAUNCHCHK();
         }
         STCHK((smooth_grid<V, K>(h, l, false, nullptr, (l == 0 && want_dot) ? h->R : nullptr, skip,
@@ -450,15 +471,15 @@ gmg_status vcycle_any(gmg_handle *h, const int *skip, bool want_dot, int *nparts
 }
 
 gmg_status finalize(gmg_handle *h, int count, int stage, PcgState *state) {
-    gmg::k_finalize<<<1, 256, 0, h->stream>>>(h->partial, count, stage, state ? state : h->st);
+    gmg::k_finalize<<<1, gmg::NT_FIN, 0, h->stream>>>(h->partial, count, stage, state ? state : h->st);
     LAUNCHCHK();
     return GMG_OK;
 }
 
 gmg_status dot64(gmg_handle *h, const double *a, const double *b, int stage, const int *skip) {
-    gmg::k_dot<double><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(h->lv[0].rows, a, b, h->partial, skip);
+    gmg::k_dot<double><<<h->lv[0].rows.nblocks, gmg::NT_FLAT, 0, h->stream>>>(h->lv[0].rows, a, b, h->partial, skip);
     LAUNCHCHK();
-    return finalize(h, gmg::NB_FLAT, stage);
+    return finalize(h, h->lv[0].rows.nblocks, stage);
 }
 
 gmg_status read_state(gmg_handle *h) {
@@ -475,10 +496,10 @@ gmg_status pcg_start(gmg_handle *h) {
     STCHK(finalize(h, np, gmg::ST_RHO0));
     Prof pf(h, GMG_K_UPDATE_P, true);
     if (mixed(h))
-        gmg::k_update_p<float><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(h->lv[0].rows, h->P,
+        gmg::k_update_p<float><<<h->lv[0].rows.nblocks, gmg::NT_FLAT, 0, h->stream>>>(h->lv[0].rows, h->P,
                                                                               (const float *)h->lv[0].x, h->st);
     else
-        gmg::k_update_p<double><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(h->lv[0].rows, h->P,
+        gmg::k_update_p<double><<<h->lv[0].rows.nblocks, gmg::NT_FLAT, 0, h->stream>>>(h->lv[0].rows, h->P,
                                                                                (const double *)h->lv[0].x, h->st);
     LAUNCHCHK();
     gmg::k_clear_restart<<<1, 64, 0, h->stream>>>(h->st);
@@ -495,32 +516,32 @@ gmg_status pcg_iteration(gmg_handle *h) {
     const bool mx = mixed(h);
     {
         Prof pf(h, GMG_K_APPLY_DOT, true);
-        gmg::k_apply<double, double, true><<<l0.til.nblocks, gmg::NT, 0, h->stream>>>(view<double, double>(l0), l0.til,
-                                                                                      h->P, h->Q, h->partial, skip);
+        gmg::k_apply<double, double, true><<<l0.til64.nblocks, gmg::NT, 0, h->stream>>>(
+            view<double, double>(l0), l0.til64, h->P, h->Q, h->partial, skip);
         LAUNCHCHK();
     }
-    STCHK(finalize(h, l0.til.nblocks, gmg::ST_ALPHA));
+    STCHK(finalize(h, l0.til64.nblocks, gmg::ST_ALPHA));
     {
         Prof pf(h, GMG_K_UPDATE_R, true);
         if (mx)
-            gmg::k_update_r<float><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(l0.rows, h->R, h->Q, (float *)l0.b,
+            gmg::k_update_r<float><<<l0.rows.nblocks, gmg::NT_FLAT, 0, h->stream>>>(l0.rows, h->R, h->Q, (float *)l0.b,
                                                                                  h->st, h->partial);
         else
-            gmg::k_update_r<double><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(l0.rows, h->R, h->Q, nullptr, h->st,
+            gmg::k_update_r<double><<<l0.rows.nblocks, gmg::NT_FLAT, 0, h->stream>>>(l0.rows, h->R, h->Q, nullptr, h->st,
                                                                                   h->partial);
         LAUNCHCHK();
     }
-    STCHK(finalize(h, gmg::NB_FLAT, gmg::ST_RR));
+    STCHK(finalize(h, l0.rows.nblocks, gmg::ST_RR));
     int np = 0;
     STCHK(vcycle_any(h, skip, true, &np, true));
     STCHK(finalize(h, np, h->opt.flexible ? gmg::ST_BETA_FLEX : gmg::ST_BETA));
     {
         Prof pf(h, GMG_K_UPDATE_XP, true);
         if (mx)
-            gmg::k_update_xp<float><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(l0.rows, h->X, h->P,
+            gmg::k_update_xp<float><<<l0.rows.nblocks, gmg::NT_FLAT, 0, h->stream>>>(l0.rows, h->X, h->P,
                                                                                   (const float *)l0.x, h->st);
         else
-            gmg::k_update_xp<double><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(l0.rows, h->X, h->P,
+            gmg::k_update_xp<double><<<l0.rows.nblocks, gmg::NT_FLAT, 0, h->stream>>>(l0.rows, h->X, h->P,
                                                                                    (const double *)l0.x, h->st);
         LAUNCHCHK();
     }
@@ -562,8 +583,9 @@ gmg_status solve_core(gmg_handle *h, const double *f, const double *x0, double r
         gmg::k_to_padded<double><<<blocks_for(nv, 256), 256, 0, h->stream>>>(l0.n, l0.pitch, x0, h->X);
         LAUNCHCHK();
         Prof pf(h, GMG_K_RESIDUAL, true);
-        gmg::k_residual<double, double><<<l0.til.nblocks, gmg::NT, 0, h->stream>>>(view<double, double>(l0), l0.til,
-                                                                                   h->F, h->X, h->R, nullptr);
+        gmg::k_residual<double, double><<<l0.til64.nblocks, gmg::NT, 0, h->stream>>>(view<double, double>(l0),
+                                                                                     l0.til64, h->F, h->X, h->R,
+                                                                                     nullptr);
         LAUNCHCHK();
     } else {
         HIPCHK(hipMemsetAsync(h->X, 0, l0.nel * sizeof(double), h->stream));
@@ -589,9 +611,8 @@ gmg_status solve_core(gmg_handle *h, const double *f, const double *x0, double r
             // FP64 true residual
             {
                 Prof pf(h, GMG_K_RESIDUAL, true);
-                gmg::k_residual<double, double><<<l0.til.nblocks, gmg::NT, 0, h->stream>>>(view<double, double>(l0),
-                                                                                           l0.til, h->F, h->X, h->Q,
-                                                                                           nullptr);
+                gmg::k_residual<double, double><<<l0.til64.nblocks, gmg::NT, 0, h->stream>>>(
+                    view<double, double>(l0), l0.til64, h->F, h->X, h->Q, nullptr);
                 LAUNCHCHK();
             }
             STCHK(dot64(h, h->Q, h->Q, gmg::ST_TT, nullptr));
@@ -851,7 +872,9 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
         lh.plane = (long long)n * lh.pitch;
         lh.nel = (long long)n * lh.plane;
         lh.s = (double)(n - 1) * (double)(n - 1);
-        lh.til = make_tiling(n);
+        const int t64 = env_int("GMG_TARGET_WGS_64", 16384);
+        lh.til = make_tiling(n, mx ? env_int("GMG_TARGET_WGS_V", 1024) : t64);
+        lh.til64 = make_tiling(n, t64);
         lh.rows = make_rows(n, lh.pitch, lh.plane);
         n = (n - 1) / 2 + 1;
     }
@@ -878,7 +901,7 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
     ALLOC(h->R, l0.nel);
     ALLOC(h->P, l0.nel);
     ALLOC(h->Q, l0.nel);
-    h->npartial = std::max(l0.til.nblocks, gmg::NB_FLAT);
+    h->npartial = std::max(std::max(l0.til.nblocks, l0.til64.nblocks), std::max(l0.rows.nblocks, gmg::NB_FLAT));
     {
         const long long nfaces_blocks = blocks_for((long long)l0.n * l0.n * l0.n, 256);
         if (nfaces_blocks > h->npartial) h->npartial = (int)nfaces_blocks;
@@ -1097,8 +1120,8 @@ gmg_status hook_prolong(gmg_handle *h, int level, const double *e, double *x) {
     LevelHost &f = h->lv[level], &c = h->lv[level + 1];
     STCHK(in_vec<V>(h, c, e, (V *)c.x));
     STCHK(in_vec<V>(h, f, x, (V *)f.x));
-    gmg::k_prolong<V><<<f.til.nblocks, gmg::NT, 0, h->stream>>>(f.n, f.pitch, f.plane, f.til, (const V *)c.x, c.pitch,
-                                                                c.plane, (V *)f.x, nullptr);
+    gmg::k_prolong<V><<<prolong_grid(c.n), gmg::NT, 0, h->stream>>>(f.pitch, f.plane, c.n, c.pitch, c.plane,
+                                                                    (const V *)c.x, (V *)f.x, nullptr);
     LAUNCHCHK();
     return out_vec<V>(h, f, (const V *)f.x, x);
 }
@@ -1136,8 +1159,8 @@ gmg_status gmg_apply_operator(gmg_handle *h, int32_t level, int32_t use_fp64, co
         if (level != 0) return fail(h, GMG_ERR_ARG, "the FP64 outer operator exists on level 0 only");
         LevelHost &l0 = h->lv[0];
         STCHK(in_vec<double>(h, l0, x, h->P));
-        gmg::k_apply<double, double, false><<<l0.til.nblocks, gmg::NT, 0, h->stream>>>(view<double, double>(l0), l0.til,
-                                                                                       h->P, h->Q, nullptr, nullptr);
+        gmg::k_apply<double, double, false><<<l0.til64.nblocks, gmg::NT, 0, h->stream>>>(
+            view<double, double>(l0), l0.til64, h->P, h->Q, nullptr, nullptr);
         LAUNCHCHK();
         return out_vec<double>(h, l0, h->Q, y);
     }

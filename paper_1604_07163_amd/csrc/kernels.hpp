@@ -39,6 +39,40 @@ __device__ __forceinline__ double fmaT(double a, double b, double c) { return __
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __fmaf_rn(a, b, c); }
 __device__ __forceinline__ double kval(double v) { return v; }
 __device__ __forceinline__ float kval(bf16 v) { return __uint_as_float(((uint32_t)v) << 16); }
+// Streaming (nontemporal) loads and stores for data a kernel touches once.
+template <typename T>
+__device__ __forceinline__ T ldnt(const T *p) { return __builtin_nontemporal_load(p); }
+template <typename T>
+__device__ __forceinline__ void stnt(T v, T *p) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ float2 ldnt(const float2 *p) {
+    const float *q = (const float *)p;
+    return make_float2(__builtin_nontemporal_load(q), __builtin_nontemporal_load(q + 1));
+}
+__device__ __forceinline__ double2 ldnt(const double2 *p) {
+    const double *q = (const double *)p;
+    return make_double2(__builtin_nontemporal_load(q), __builtin_nontemporal_load(q + 1));
+}
+__device__ __forceinline__ void stnt(float2 v, float2 *p) {
+    float *q = (float *)p;
+    __builtin_nontemporal_store(v.x, q);
+    __builtin_nontemporal_store(v.y, q + 1);
+}
+__device__ __forceinline__ void stnt(double2 v, double2 *p) {
+    double *q = (double *)p;
+    __builtin_nontemporal_store(v.x, q);
+    __builtin_nontemporal_store(v.y, q + 1);
+}
+template <typename T>
+struct Vec2;
+template <>
+struct Vec2<double> {
+    typedef double2 type;
+};
+template <>
+struct Vec2<float> {
+    typedef float2 type;
+};
+
 
 // FP64 -> BF16, round to nearest even, directly from the double (no double
 // rounding through FP32).  Inputs are positive normal numbers well inside the
@@ -226,10 +260,10 @@ __global__ __launch_bounds__(NT) void k_apply(Lev<V, K> L, Tiling t, const V *__
         for (int k = c.k0; k < c.k1; ++k, o += plane) {
             const V ut = u[o + plane];
             const V uw = u[o - 1], ue = u[o + 1], us = u[o - pitch], un = u[o + pitch];
-            const V kw = kval(L.kx[o - 1]), ke = kval(L.kx[o]), ks = kval(L.ky[o - pitch]),
-                    kn = kval(L.ky[o]), kt = kval(L.kz[o]);
+            const V kw = kval(L.kx[o - 1]), ke = kval(ldnt(&L.kx[o])), ks = kval(L.ky[o - pitch]),
+                    kn = kval(L.ky[o]), kt = kval(ldnt(&L.kz[o]));
             const V r = apply7(up, uw, ue, us, un, ub, ut, kw, ke, ks, kn, kb, kt, L.s);
-            y[o] = r;
+            stnt(r, &y[o]);
             if (DOT) dot = fmaT((double)up, (double)r, dot);
             ub = up;
             up = ut;
@@ -258,9 +292,9 @@ __global__ __launch_bounds__(NT) void k_residual(Lev<V, K> L, Tiling t, const V 
     for (int k = c.k0; k < c.k1; ++k, o += plane) {
         const V ut = u[o + plane];
         const V uw = u[o - 1], ue = u[o + 1], us = u[o - pitch], un = u[o + pitch];
-        const V kw = kval(L.kx[o - 1]), ke = kval(L.kx[o]), ks = kval(L.ky[o - pitch]),
-                kn = kval(L.ky[o]), kt = kval(L.kz[o]);
-        r[o] = b[o] - apply7(up, uw, ue, us, un, ub, ut, kw, ke, ks, kn, kb, kt, L.s);
+        const V kw = kval(L.kx[o - 1]), ke = kval(ldnt(&L.kx[o])), ks = kval(L.ky[o - pitch]),
+                kn = kval(L.ky[o]), kt = kval(ldnt(&L.kz[o]));
+        stnt(ldnt(&b[o]) - apply7(up, uw, ue, us, un, ub, ut, kw, ke, ks, kn, kb, kt, L.s), &r[o]);
         ub = up;
         up = ut;
         kb = kt;
@@ -281,12 +315,12 @@ __global__ __launch_bounds__(NT) void k_cheb_first(Lev<V, K> L, Tiling t, const 
     for (int k = col.k0; k < col.k1; ++k, o += L.plane) {
         V bv;
         if (CVT) {
-            bv = (V)r64[o];
-            b_out[o] = bv;
+            bv = (V)ldnt(&r64[o]);
+            stnt(bv, &b_out[o]);
         } else {
-            bv = b[o];
+            bv = ldnt(&b[o]);
         }
-        x_out[o] = cheb_first_val(bv, L.dinv[o], c);
+        stnt(cheb_first_val(bv, ldnt(&L.dinv[o]), c), &x_out[o]);
     }
 }
 
@@ -316,12 +350,12 @@ __global__ __launch_bounds__(NT) void k_cheb_pre2(Lev<V, K> L, Tiling t, const V
         const V uw = cheb_first_val(b[o - 1], dv[o - 1], c0), ue = cheb_first_val(b[o + 1], dv[o + 1], c0);
         const V us = cheb_first_val(b[o - pitch], dv[o - pitch], c0),
                 un = cheb_first_val(b[o + pitch], dv[o + pitch], c0);
-        const V kw = kval(L.kx[o - 1]), ke = kval(L.kx[o]), ks = kval(L.ky[o - pitch]), kn = kval(L.ky[o]),
-                kt = kval(L.kz[o]);
+        const V kw = kval(L.kx[o - 1]), ke = kval(ldnt(&L.kx[o])), ks = kval(L.ky[o - pitch]), kn = kval(L.ky[o]),
+                kt = kval(ldnt(&L.kz[o]));
         const V ax = apply7(up, uw, ue, us, un, ub, ut, kw, ke, ks, kn, kb, kt, L.s);
         const V d = diag7(kw, ke, ks, kn, kb, kt, L.s);
-        out[o] = cheb_step_val(up, up, bp, ax, d, c1, c2);
-        if (WX1) x1out[o] = up;
+        stnt(cheb_step_val(up, up, bp, ax, d, c1, c2), &out[o]);
+        if (WX1) stnt(up, &x1out[o]);
         ub = up;
         up = ut;
         bp = bt;
@@ -365,16 +399,16 @@ __global__ __launch_bounds__(NT) void k_cheb_step(Lev<V, K> L, Tiling t, const V
         for (int k = col.k0; k < col.k1; ++k, o += plane) {
             const V ut = x[o + plane];
             const V uw = x[o - 1], ue = x[o + 1], us = x[o - pitch], un = x[o + pitch];
-            const V kw = kval(L.kx[o - 1]), ke = kval(L.kx[o]), ks = kval(L.ky[o - pitch]),
-                    kn = kval(L.ky[o]), kt = kval(L.kz[o]);
+            const V kw = kval(L.kx[o - 1]), ke = kval(ldnt(&L.kx[o])), ks = kval(L.ky[o - pitch]),
+                    kn = kval(L.ky[o]), kt = kval(ldnt(&L.kz[o]));
             const V ax = apply7(up, uw, ue, us, un, ub, ut, kw, ke, ks, kn, kb, kt, L.s);
             const V d = diag7(kw, ke, ks, kn, kb, kt, L.s);
-            const V diff = PM == 0 ? V(0) : PM == 1 ? up : up - xp[o];
-            const V v = cheb_step_val(up, diff, b[o], ax, d, PM == 0 ? V(0) : c1, c2);
-            out[o] = v;
+            const V diff = PM == 0 ? V(0) : PM == 1 ? up : up - ldnt(&xp[o]);
+            const V v = cheb_step_val(up, diff, ldnt(&b[o]), ax, d, PM == 0 ? V(0) : c1, c2);
+            stnt(v, &out[o]);
             if (DOTR) {
-                dot = fmaT(r64[o], (double)v, dot);
-                if (q64) dotq = fmaT(q64[o], (double)v, dotq);
+                dot = fmaT(ldnt(&r64[o]), (double)v, dot);
+                if (q64) dotq = fmaT(ldnt(&q64[o]), (double)v, dotq);
             }
             ub = up;
             up = ut;
@@ -482,46 +516,58 @@ __global__ __launch_bounds__(NT) void k_restrict(int nc, int pc, long long plc, 
     }
 }
 
-// x += P e marching fine columns in z; the x-y interpolation of a coarse
-// plane is computed once and reused by the (up to) three fine planes that
-// need it.  Summation order as in prolong_at.
-template <typename V>
-__device__ __forceinline__ V plane_interp(const V *e, long long kbase, int pc, int i, int j) {
-    const int i0 = i >> 1, i1 = (i + 1) >> 1, j0 = j >> 1, j1 = (j + 1) >> 1;
-    const V wi = (i & 1) ? V(0.5) : V(1), wj = (j & 1) ? V(0.5) : V(1);
-    const V *r0 = e + kbase + (long long)j0 * pc;
-    V accx = fmaT(wi, r0[i0], V(0));
-    if (i & 1) accx = fmaT(wi, r0[i1], accx);
-    V accy = fmaT(wj, accx, V(0));
-    if (j & 1) {
-        const V *r1 = e + kbase + (long long)j1 * pc;
-        V ax = fmaT(wi, r1[i0], V(0));
-        if (i & 1) ax = fmaT(wi, r1[i1], ax);
-        accy = fmaT(wj, ax, accy);
+// x += P e by coarse cells: the thread of cell (I,J,K) reads its 8 corner
+// values and updates the 8 fine vertices (2I+a, 2J+b, 2K+c), a,b,c in {0,1}.
+// Each value is summed in the order of prolong_at (z outer, then y, then x,
+// lower coarse index first), so both paths round identically.  Fine vertices
+// on the boundary receive combinations of coarse boundary zeros and stay 0.
+template <int A, int B, int C, typename V>
+__device__ __forceinline__ V cell_val(const V (&e)[2][2][2]) {
+    const V wi = A ? V(0.5) : V(1), wj = B ? V(0.5) : V(1), wk = C ? V(0.5) : V(1);
+    V accz = V(0);
+#pragma unroll
+    for (int c = 0; c <= C; ++c) {
+        V accy = V(0);
+#pragma unroll
+        for (int bb = 0; bb <= B; ++bb) {
+            V accx = V(0);
+#pragma unroll
+            for (int a = 0; a <= A; ++a) accx = fmaT(wi, e[c][bb][a], accx);
+            accy = fmaT(wj, accx, accy);
+        }
+        accz = fmaT(wk, accy, accz);
     }
-    return accy;
+    return accz;
+}
+template <int B, int C, typename V>
+__device__ __forceinline__ void cell_row(V *x, long long o, const V (&e)[2][2][2]) {
+    typedef typename Vec2<V>::type V2;
+    V2 v = ldnt((const V2 *)(x + o));
+    v.x = v.x + cell_val<0, B, C>(e);
+    v.y = v.y + cell_val<1, B, C>(e);
+    stnt(v, (V2 *)(x + o));
 }
 template <typename V>
-__global__ __launch_bounds__(NT) void k_prolong(int n, int pitch, long long plane, Tiling t, const V *__restrict__ e,
-                                                int pc, long long plc, V *__restrict__ x,
+__global__ __launch_bounds__(NT) void k_prolong(int pitch, long long plane, int nc, int pc, long long plc,
+                                                const V *__restrict__ e, V *__restrict__ x,
                                                 const int *__restrict__ skip) {
     if (skip && *skip) return;
-    const Column c = tile_column(n, t);
-    if (!c.active) return;
-    int Klo = c.k0 >> 1;
-    V elo = plane_interp(e, (long long)Klo * plc, pc, c.i, c.j);
-    V ehi = plane_interp(e, (long long)(Klo + 1) * plc, pc, c.i, c.j);
-    long long o = (long long)c.k0 * plane + (long long)c.j * pitch + c.i;
-    for (int k = c.k0; k < c.k1; ++k, o += plane) {
-        const int K = k >> 1;
-        if (K != Klo) {
-            Klo = K;
-            elo = ehi;
-            ehi = plane_interp(e, (long long)(K + 1) * plc, pc, c.i, c.j);
-        }
-        const V v = (k & 1) ? fmaT(V(0.5), ehi, fmaT(V(0.5), elo, V(0))) : fmaT(V(1), elo, V(0));
-        x[o] = x[o] + v;
-    }
+    const int I = blockIdx.x * TX + (threadIdx.x & (TX - 1));
+    const int J = blockIdx.y * TY + (threadIdx.x >> 6);
+    const int K_ = blockIdx.z;
+    if (I > nc - 2 || J > nc - 2) return;
+    V ev[2][2][2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) ev[c][bb][a] = e[(long long)(K_ + c) * plc + (long long)(J + bb) * pc + I + a];
+    const long long o = (long long)(2 * K_) * plane + (long long)(2 * J) * pitch + 2 * I;
+    cell_row<0, 0>(x, o, ev);
+    cell_row<1, 0>(x, o + pitch, ev);
+    cell_row<0, 1>(x, o + plane, ev);
+    cell_row<1, 1>(x, o + plane + pitch, ev);
 }
 
 // ---------------------------------------------------------------- coarsest solve
@@ -711,35 +757,31 @@ struct PcgState {
     int x_pending;  // 1: this iteration's x += alpha p is still to be applied
 };
 
-// The PCG vector kernels sweep only the interior rows (j, k in 1..n-2) of
-// the padded arrays, x index 0 .. 2*half_w-1 in pairs (index 0 and the tail
-// are boundary zeros, so a pair never straddles live and stale data).  A row
-// is handled by 2^tpr_log2 threads; a workgroup covers 256 >> tpr_log2 rows at
-// a time and strides over the rows by the whole grid.
+// The PCG vector kernels cover only the interior rows (j, k in 1..n-2) of the
+// padded arrays, x index 0 .. 2*half_w-1 in pairs (index 0 and the tail are
+// boundary zeros).  No loops: one 16-byte pair per thread, a row split into
+// `segs` workgroups of 256 pairs (half_w >= 256), or 256 >> tpr_log2 rows per
+// workgroup (short rows).  The workgroup count is fixed by N, so the partial
+// sums, and their order, are deterministic.
 struct Rows {
-    int n, pitch, half_w, tpr_log2;
+    int n, pitch, half_w, tpr_log2, segs, nblocks;
     long long plane;
 };
-template <typename T>
-struct Vec2;
-template <>
-struct Vec2<double> {
-    typedef double2 type;
-};
-template <>
-struct Vec2<float> {
-    typedef float2 type;
-};
-
-#define ROW_LOOP(R)                                                                                  \
-    const int tpr = 1 << (R).tpr_log2, rpb = NT_FLAT >> (R).tpr_log2;                               \
-    const int lane_ = threadIdx.x & (tpr - 1);                                                       \
-    const long long nrows = (long long)((R).n - 2) * ((R).n - 2);                                   \
-    for (long long row = (long long)blockIdx.x * rpb + (threadIdx.x >> (R).tpr_log2); row < nrows;   \
-         row += (long long)gridDim.x * rpb)                                                          \
-        for (long long base_ = (1 + row / ((R).n - 2)) * (R).plane + (1 + row % ((R).n - 2)) * (long long)(R).pitch, \
-                       q_ = lane_;                                                                   \
-             q_ < (R).half_w; q_ += tpr)
+__device__ __forceinline__ bool row_item(const Rows &R, long long &e) {
+    const long long nrows = (long long)(R.n - 2) * (R.n - 2);
+    long long row;
+    int q;
+    if (R.segs > 0) {
+        row = blockIdx.x / R.segs;
+        q = (int)(blockIdx.x % R.segs) * NT_FLAT + (int)threadIdx.x;
+    } else {
+        row = (long long)blockIdx.x * (NT_FLAT >> R.tpr_log2) + (threadIdx.x >> R.tpr_log2);
+        q = threadIdx.x & ((1 << R.tpr_log2) - 1);
+    }
+    if (row >= nrows || q >= R.half_w) return false;
+    e = (1 + row / (R.n - 2)) * R.plane + (1 + row % (R.n - 2)) * (long long)R.pitch + 2 * q;
+    return true;
+}
 
 // r -= alpha q ; partial = sum r^2 ; MIXED: also b32 = (float) r, the
 // right-hand side of the next V-cycle's finest level.
@@ -751,8 +793,8 @@ __global__ __launch_bounds__(NT_FLAT) void k_update_r(Rows R, double *__restrict
     const double a = st->alpha;
     typedef typename Vec2<B>::type B2;
     double acc = 0.0;
-    ROW_LOOP(R) {
-        const long long e = base_ + 2 * q_;
+    long long e;
+    if (row_item(R, e)) {
         double2 rv = *(const double2 *)(r + e);
         const double2 qv = *(const double2 *)(q + e);
         rv.x = fmaT(-a, qv.x, rv.x);
@@ -782,8 +824,8 @@ __global__ __launch_bounds__(NT_FLAT) void k_update_xp(Rows R, double *__restric
     const bool upd_p = !st->done;
     const double bta = st->beta;
     typedef typename Vec2<Z>::type Z2;
-    ROW_LOOP(R) {
-        const long long e = base_ + 2 * q_;
+    long long e;
+    if (row_item(R, e)) {
         const double2 pv = *(const double2 *)(p + e);
         double2 xv = *(const double2 *)(x + e);
         xv.x = fmaT(a, pv.x, xv.x);
@@ -808,14 +850,14 @@ __global__ __launch_bounds__(NT_FLAT) void k_update_p(Rows R, double *__restrict
     const double bta = st->restart ? 0.0 : st->beta;
     typedef typename Vec2<Z>::type Z2;
     if (bta == 0.0) {
-        ROW_LOOP(R) {
-            const long long e = base_ + 2 * q_;
+        long long e;
+        if (row_item(R, e)) {
             const Z2 zv = *(const Z2 *)(z + e);
             *(double2 *)(p + e) = make_double2((double)zv.x, (double)zv.y);
         }
     } else {
-        ROW_LOOP(R) {
-            const long long e = base_ + 2 * q_;
+        long long e;
+        if (row_item(R, e)) {
             const Z2 zv = *(const Z2 *)(z + e);
             const double2 pv = *(const double2 *)(p + e);
             *(double2 *)(p + e) = make_double2(fmaT(bta, pv.x, (double)zv.x), fmaT(bta, pv.y, (double)zv.y));
@@ -830,8 +872,8 @@ __global__ __launch_bounds__(NT_FLAT) void k_dot(Rows R, const double *__restric
     if (skip && *skip) return;
     typedef typename Vec2<Z>::type Z2;
     double acc = 0.0;
-    ROW_LOOP(R) {
-        const long long e = base_ + 2 * q_;
+    long long e;
+    if (row_item(R, e)) {
         const double2 av = *(const double2 *)(a + e);
         const Z2 bv = *(const Z2 *)(b + e);
         acc = fmaT(av.x, (double)bv.x, acc);
@@ -867,9 +909,10 @@ __global__ __launch_bounds__(NT_FLAT) void k_cg_start(Rows R, const V *__restric
                                                       const int *__restrict__ skip) {
     if (skip && *skip) return;
     double bb = 0.0, rz = 0.0;
-    ROW_LOOP(R) {
+    long long e0;
+    if (row_item(R, e0)) {
         for (int t = 0; t < 2; ++t) {
-            const long long e = base_ + 2 * q_ + t;
+            const long long e = e0 + t;
             const V bv = b[e];
             const V z = bv * dinv[e];
             x[e] = V(0);
@@ -893,9 +936,10 @@ __global__ __launch_bounds__(NT_FLAT) void k_cg_update(Rows R, V *__restrict__ x
     if (st->done) return;
     const V a = (V)st->alpha;
     double rr = 0.0, rz = 0.0;
-    ROW_LOOP(R) {
+    long long e0;
+    if (row_item(R, e0)) {
         for (int t = 0; t < 2; ++t) {
-            const long long e = base_ + 2 * q_ + t;
+            const long long e = e0 + t;
             x[e] = fmaT(a, p[e], x[e]);
             const V rv = fmaT(-a, q[e], r[e]);
             r[e] = rv;
@@ -914,9 +958,10 @@ __global__ __launch_bounds__(NT_FLAT) void k_cg_p(Rows R, const V *__restrict__ 
                                                   const V *__restrict__ dinv, const PcgState *__restrict__ st) {
     if (st->done) return;
     const V bta = (V)st->beta;
-    ROW_LOOP(R) {
+    long long e0;
+    if (row_item(R, e0)) {
         for (int t = 0; t < 2; ++t) {
-            const long long e = base_ + 2 * q_ + t;
+            const long long e = e0 + t;
             p[e] = fmaT(bta, p[e], r[e] * dinv[e]);
         }
     }
@@ -931,21 +976,22 @@ enum Stage {
 };
 
 // Sum `count` partials in a fixed order and advance the PCG state.
-__global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ partial, int count, int stage,
-                                                  PcgState *__restrict__ st) {
+constexpr int NT_FIN = 1024;
+__global__ __launch_bounds__(NT_FIN) void k_finalize(const double *__restrict__ partial, int count, int stage,
+                                                     PcgState *__restrict__ st) {
     if ((stage == ST_ALPHA || stage == ST_RR || stage == ST_BETA || stage == ST_BETA_FLEX || stage == ST_C_INIT ||
          stage == ST_C_ALPHA || stage == ST_C_RR) &&
         st->done)
         return;
     const bool two = stage == ST_BETA_FLEX || stage == ST_C_INIT || stage == ST_C_RR;
     double acc = 0.0;
-    for (int w = threadIdx.x; w < count; w += 256) acc += partial[w];
-    const double sum = block_sum<256>(acc);
+    for (int w = threadIdx.x; w < count; w += NT_FIN) acc += partial[w];
+    const double sum = block_sum<NT_FIN>(acc);
     double sum2 = 0.0;
     if (two) {
         double acc2 = 0.0;
-        for (int w = threadIdx.x; w < count; w += 256) acc2 += partial[count + w];
-        sum2 = block_sum<256>(acc2);
+        for (int w = threadIdx.x; w < count; w += NT_FIN) acc2 += partial[count + w];
+        sum2 = block_sum<NT_FIN>(acc2);
     }
     if (threadIdx.x != 0) return;
     switch (stage) {

@@ -66,6 +66,12 @@ def lib():
         L.or_create.restype = I
         L.or_create2.argtypes = [I, I, I, D, D, I, I, D, I, P, P, P, ctypes.POINTER(P)]
         L.or_create2.restype = I
+        L.or_create3.argtypes = [I, I, I, D, D, I, I, D, I, I, P, P, P, ctypes.POINTER(P)]
+        L.or_create3.restype = I
+        L.or_apply27_raw.argtypes = [I, P, P, P]
+        L.or_galerkin_raw.argtypes = [I, P, P, P, P, I, P]
+        L.or_get_a27.argtypes = [P, I, P]
+        L.or_get_a27.restype = I
         L.or_pcg2.argtypes = [P, P, P, D, I, I, ctypes.POINTER(I), ctypes.POINTER(D), ctypes.POINTER(D),
                               ctypes.POINTER(ctypes.c_long)]
         L.or_pcg2.restype = I
@@ -161,6 +167,26 @@ def cheb(kx, ky, kz, b, x0=None, degree=2, lo=0.25, hi=2.0):
     return x
 
 
+def apply27(a27, u):
+    """(A u) for a 27-point stencil a27 of shape (N,N,N,27)."""
+    u = _f64(u)
+    a27 = _f64(a27)
+    out = np.empty_like(u)
+    lib().or_apply27_raw(u.shape[0], _p(a27), _p(u), _p(out))
+    return out
+
+
+def galerkin(kx, ky, kz, a27=None):
+    """R A P (27-point, (Nc,Nc,Nc,27)) of the fine operator given by links or by a27."""
+    kx, ky, kz = _f64(kx), _f64(ky), _f64(kz)
+    n = kx.shape[0]
+    nc = (n - 1) // 2 + 1
+    out = np.empty((nc, nc, nc, 27))
+    a = None if a27 is None else _f64(a27)
+    lib().or_galerkin_raw(n, _p(kx), _p(ky), _p(kz), None if a is None else _p(a), nc, _p(out))
+    return out
+
+
 def assemble_dense(kx, ky, kz):
     kx, ky, kz = _f64(kx), _f64(ky), _f64(kz)
     n = kx.shape[0]
@@ -199,15 +225,17 @@ class Hierarchy:
 
     def __init__(self, kx, ky, kz, levels: int, degree: int = 2, lo: float = 0.25, hi: float = 2.0,
                  rule: int = RULE_ARITHMETIC, coarse_solver: int = 0, coarse_rtol: float = 1e-4,
-                 coarse_max_it: int = 500):
+                 coarse_max_it: int = 500, galerkin: int = 0):
         """coarse_solver 0: exact Cholesky on the coarsest level; 1: truncated
-        hierarchy whose coarsest level is solved by Jacobi-CG to coarse_rtol."""
+        hierarchy whose coarsest level is solved by Jacobi-CG to coarse_rtol.
+        galerkin g > 0: levels l >= g use R A P (True = 1: all coarse levels);
+        levels below g keep re-discretized link coefficients."""
         self._kx, self._ky, self._kz = _f64(kx), _f64(ky), _f64(kz)
         self.n = self._kx.shape[0]
         self.levels = levels
         h = ctypes.c_void_p()
-        st = lib().or_create2(self.n, levels, degree, lo, hi, rule, coarse_solver, coarse_rtol, coarse_max_it,
-                              _p(self._kx), _p(self._ky), _p(self._kz), ctypes.byref(h))
+        st = lib().or_create3(self.n, levels, degree, lo, hi, rule, coarse_solver, coarse_rtol, coarse_max_it,
+                              int(galerkin), _p(self._kx), _p(self._ky), _p(self._kz), ctypes.byref(h))
         if st != 0:
             raise OracleError(st)
         self._h = h
@@ -232,6 +260,14 @@ class Hierarchy:
         kx, ky, kz = np.empty(sx), np.empty(sy), np.empty(sz)
         lib().or_get_k(self._h, l, _p(kx), _p(ky), _p(kz))
         return kx, ky, kz
+
+    def level_a27(self, l):
+        """27-point Galerkin operator of level l as an (N,N,N,27) array (index (dz+1)*9+(dy+1)*3+(dx+1))."""
+        n = self.level_n(l)
+        out = np.empty((n, n, n, 27))
+        if lib().or_get_a27(self._h, l, _p(out)) != 0:
+            raise OracleError(1)
+        return out
 
     def apply(self, l, u):
         u = _f64(u)

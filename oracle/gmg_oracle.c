@@ -233,6 +233,136 @@ void or_prolong_add_raw(int nc, const double *e, int n, double *x)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Galerkin coarse operators (the other coarse-operator construction of     */
+/* Sec. 3.3.2 and Sec. 4.2): A_c = R A P with trilinear P and R = P^T / 8.  */
+/* With a 7-point (or 27-point) fine operator A_c couples each coarse       */
+/* vertex to its 3x3x3 neighbourhood, so it is stored as 27 coefficients    */
+/* per vertex: a27[p*27 + (dz+1)*9 + (dy+1)*3 + (dx+1)] multiplies          */
+/* u[p + (dx,dy,dz)].  Rows and columns of boundary vertices are absent.    */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int n;
+    const double *kx, *ky, *kz; /* 7-point link form (a27 == NULL) */
+    const double *a27;          /* or a 27-point stencil per vertex */
+} or_op;
+
+static int d27(int dx, int dy, int dz) { return (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1); }
+
+void or_apply27_raw(int n, const double *a27, const double *u, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < n; k++)
+        for (int j = 0; j < n; j++)
+            for (int i = 0; i < n; i++) {
+                if (!interior(n, i, j, k)) {
+                    out[vid(n, i, j, k)] = 0.0;
+                    continue;
+                }
+                double acc = 0.0;
+                for (int dz = -1; dz <= 1; dz++)
+                    for (int dy = -1; dy <= 1; dy++)
+                        for (int dx = -1; dx <= 1; dx++)
+                            acc += a27[vid(n, i, j, k) * 27 + d27(dx, dy, dz)] *
+                                   val(n, u, i + dx, j + dy, k + dz);
+                out[vid(n, i, j, k)] = acc;
+            }
+}
+
+static void op_apply(const or_op *A, const double *u, double *out)
+{
+    if (A->a27)
+        or_apply27_raw(A->n, A->a27, u, out);
+    else
+        or_apply_raw(A->n, A->kx, A->ky, A->kz, u, out);
+}
+
+static void op_diag(const or_op *A, double *d)
+{
+    if (!A->a27) {
+        or_diag_raw(A->n, A->kx, A->ky, A->kz, d);
+        return;
+    }
+    int n = A->n;
+    for (int k = 0; k < n; k++)
+        for (int j = 0; j < n; j++)
+            for (int i = 0; i < n; i++)
+                d[vid(n, i, j, k)] = interior(n, i, j, k) ? A->a27[vid(n, i, j, k) * 27 + d27(0, 0, 0)] : 0.0;
+}
+
+/* entry A[p][q] of a fine operator for interior p and any q (0 unless q is an
+ * interior stencil neighbour of p) */
+static double op_entry(const or_op *A, int pi, int pj, int pk, int qi, int qj, int qk)
+{
+    int n = A->n;
+    int dx = qi - pi, dy = qj - pj, dz = qk - pk;
+    if (dx < -1 || dx > 1 || dy < -1 || dy > 1 || dz < -1 || dz > 1 || !interior(n, qi, qj, qk))
+        return 0.0;
+    if (A->a27)
+        return A->a27[vid(n, pi, pj, pk) * 27 + d27(dx, dy, dz)];
+    double s = (double)(n - 1) * (double)(n - 1);
+    int nz = (dx != 0) + (dy != 0) + (dz != 0);
+    if (nz == 0)
+        return s * (A->kx[xid(n, pi - 1, pj, pk)] + A->kx[xid(n, pi, pj, pk)] + A->ky[yid(n, pi, pj - 1, pk)] +
+                    A->ky[yid(n, pi, pj, pk)] + A->kz[zid(n, pi, pj, pk - 1)] + A->kz[zid(n, pi, pj, pk)]);
+    if (nz > 1)
+        return 0.0;
+    if (dx)
+        return -s * A->kx[xid(n, dx < 0 ? pi - 1 : pi, pj, pk)];
+    if (dy)
+        return -s * A->ky[yid(n, pi, dy < 0 ? pj - 1 : pj, pk)];
+    return -s * A->kz[zid(n, pi, pj, dz < 0 ? pk - 1 : pk)];
+}
+
+/* 1D trilinear weight of coarse index J at fine index q */
+static double pw(int q, int J)
+{
+    int d = q - 2 * J;
+    return d == 0 ? 1.0 : (d == 1 || d == -1) ? 0.5 : 0.0;
+}
+
+/* a27c = R A P on the coarse grid of A's grid, from the definitions of R, A, P:
+ * (R A P)[I][J] = sum_p sum_q R[I][p] A[p][q] P[q][J] with R[I][p] = P[p][I]/8. */
+void or_galerkin_op(const or_op *A, int nc, double *a27c)
+{
+    int n = A->n;
+    memset(a27c, 0, sizeof(double) * nvert(nc) * 27);
+#pragma omp parallel for schedule(dynamic)
+    for (int K = 1; K <= nc - 2; K++)
+        for (int J = 1; J <= nc - 2; J++)
+            for (int I = 1; I <= nc - 2; I++)
+                for (int pk = 2 * K - 1; pk <= 2 * K + 1; pk++)
+                    for (int pj = 2 * J - 1; pj <= 2 * J + 1; pj++)
+                        for (int pi = 2 * I - 1; pi <= 2 * I + 1; pi++) {
+                            double r = pw(pi, I) * pw(pj, J) * pw(pk, K) / 8.0;
+                            for (int qk = pk - 1; qk <= pk + 1; qk++)
+                                for (int qj = pj - 1; qj <= pj + 1; qj++)
+                                    for (int qi = pi - 1; qi <= pi + 1; qi++) {
+                                        double a = op_entry(A, pi, pj, pk, qi, qj, qk);
+                                        if (a == 0.0)
+                                            continue;
+                                        for (int Ck = qk / 2 - 1; Ck <= qk / 2 + 1; Ck++)
+                                            for (int Cj = qj / 2 - 1; Cj <= qj / 2 + 1; Cj++)
+                                                for (int Ci = qi / 2 - 1; Ci <= qi / 2 + 1; Ci++) {
+                                                    if (!interior(nc, Ci, Cj, Ck))
+                                                        continue;
+                                                    double w = pw(qi, Ci) * pw(qj, Cj) * pw(qk, Ck);
+                                                    if (w == 0.0)
+                                                        continue;
+                                                    a27c[vid(nc, I, J, K) * 27 + d27(Ci - I, Cj - J, Ck - K)] +=
+                                                        r * a * w;
+                                                }
+                                    }
+                        }
+}
+
+void or_galerkin_raw(int n, const double *kx, const double *ky, const double *kz, const double *a27, int nc,
+                     double *a27c)
+{
+    or_op A = {n, kx, ky, kz, a27};
+    or_galerkin_op(&A, nc, a27c);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Chebyshev smoother preconditioned by Jacobi (the smoother of Sec. 4.3 and */
 /* of the PETSc option examples in Sec. 3.3).  Chebyshev acceleration on    */
 /* D^-1 A over the interval [lo, hi], following the published three-term    */
@@ -246,19 +376,20 @@ void or_prolong_add_raw(int nc, const double *e, int n, double *x)
 /* degree steps in total; x0 = 0 when x0_zero is set (r0 = b, no matvec).   */
 /* work must hold 4 vertex vectors.                                         */
 /* ------------------------------------------------------------------------ */
-void or_cheb_raw(int n, const double *kx, const double *ky, const double *kz, int degree,
-                 double lo, double hi, const double *b, double *x, int x0_zero, double *work)
+static void cheb_op(const or_op *A, int degree, double lo, double hi, const double *b, double *x, int x0_zero,
+                    double *work)
 {
+    int n = A->n;
     size_t nv = nvert(n);
     double *r = work, *d = work + nv, *t = work + 2 * nv, *dg = work + 3 * nv;
     double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
-    or_diag_raw(n, kx, ky, kz, dg);
+    op_diag(A, dg);
     if (x0_zero) {
         memset(x, 0, sizeof(double) * nv);
         for (size_t p = 0; p < nv; p++)
             r[p] = b[p];
     } else {
-        or_apply_raw(n, kx, ky, kz, x, t);
+        op_apply(A, x, t);
         for (size_t p = 0; p < nv; p++)
             r[p] = b[p] - t[p];
     }
@@ -269,7 +400,7 @@ void or_cheb_raw(int n, const double *kx, const double *ky, const double *kz, in
         for (size_t p = 0; p < nv; p++)
             x[p] += d[p];
         if (j + 1 < degree) {
-            or_apply_raw(n, kx, ky, kz, d, t);
+            op_apply(A, d, t);
             for (size_t p = 0; p < nv; p++)
                 r[p] -= t[p];
             double rho_new = 1.0 / (2.0 * sigma - rho);
@@ -284,6 +415,13 @@ void or_cheb_raw(int n, const double *kx, const double *ky, const double *kz, in
             for (int i = 0; i < n; i++)
                 if (!interior(n, i, j, k))
                     x[vid(n, i, j, k)] = 0.0;
+}
+
+void or_cheb_raw(int n, const double *kx, const double *ky, const double *kz, int degree, double lo, double hi,
+                 const double *b, double *x, int x0_zero, double *work)
+{
+    or_op A = {n, kx, ky, kz, NULL};
+    cheb_op(&A, degree, lo, hi, b, x, x0_zero, work);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -314,6 +452,26 @@ void or_assemble_dense_raw(int n, const double *kx, const double *ky, const doub
                         A[(size_t)p * m + unk(n, nb[f][0], nb[f][1], nb[f][2])] -= s * kf[f];
                 }
             }
+}
+
+static void assemble_dense_op(const or_op *A, double *M)
+{
+    if (!A->a27) {
+        or_assemble_dense_raw(A->n, A->kx, A->ky, A->kz, M);
+        return;
+    }
+    int n = A->n;
+    int m = (n - 2) * (n - 2) * (n - 2);
+    memset(M, 0, sizeof(double) * (size_t)m * m);
+    for (int k = 1; k <= n - 2; k++)
+        for (int j = 1; j <= n - 2; j++)
+            for (int i = 1; i <= n - 2; i++)
+                for (int dz = -1; dz <= 1; dz++)
+                    for (int dy = -1; dy <= 1; dy++)
+                        for (int dx = -1; dx <= 1; dx++)
+                            if (interior(n, i + dx, j + dy, k + dz))
+                                M[(size_t)unk(n, i, j, k) * m + unk(n, i + dx, j + dy, k + dz)] +=
+                                    A->a27[vid(n, i, j, k) * 27 + d27(dx, dy, dz)];
 }
 
 /* In-place Cholesky: on return the lower triangle of A holds L.  Returns 0, */
@@ -363,8 +521,15 @@ void or_chol_solve_raw(int m, const double *L, double *y)
 typedef struct {
     int n;
     double *kx, *ky, *kz;
+    double *a27;              /* Galerkin coarse operator (NULL: the 7-point link form) */
     double *x, *b, *r, *work; /* work: 4 vectors for the smoother */
 } or_level;
+
+static or_op level_op(const or_level *L)
+{
+    or_op A = {L->n, L->kx, L->ky, L->kz, L->a27};
+    return A;
+}
 
 typedef struct {
     int levels, degree, rule;
@@ -373,6 +538,9 @@ typedef struct {
     int m;       /* unknowns on the coarsest level */
     double *chol; /* m x m, lower triangle = L (exact coarse solve only) */
     int coarse_solver;     /* 0: exact Cholesky; 1: truncated hierarchy, inexact coarse CG */
+    int galerkin;          /* g > 0: levels l >= g take R A P, levels below g are re-discretized
+                              (g = 1: Galerkin throughout, Sec. 3.3.2; g > 1: the hybrid
+                              construction of Sec. 3.3.3); 0: re-discretized throughout */
     double coarse_rtol;    /* coarse CG relative residual target */
     int coarse_max_it;
     long coarse_its;       /* coarse CG iterations since the last reset */
@@ -390,6 +558,7 @@ void or_destroy(void *hp)
         free(H->lv[l].kx);
         free(H->lv[l].ky);
         free(H->lv[l].kz);
+        free(H->lv[l].a27);
         free(H->lv[l].x);
         free(H->lv[l].b);
         free(H->lv[l].r);
@@ -399,13 +568,25 @@ void or_destroy(void *hp)
     free(H);
 }
 
+int or_create3(int n, int levels, int degree, double lo, double hi, int rule, int coarse_solver,
+               double coarse_rtol, int coarse_max_it, int galerkin, const double *kx, const double *ky,
+               const double *kz, void **out);
+
 int or_create2(int n, int levels, int degree, double lo, double hi, int rule, int coarse_solver,
                double coarse_rtol, int coarse_max_it, const double *kx, const double *ky, const double *kz,
                void **out)
 {
+    return or_create3(n, levels, degree, lo, hi, rule, coarse_solver, coarse_rtol, coarse_max_it, 0, kx, ky, kz,
+                      out);
+}
+
+int or_create3(int n, int levels, int degree, double lo, double hi, int rule, int coarse_solver,
+               double coarse_rtol, int coarse_max_it, int galerkin, const double *kx, const double *ky,
+               const double *kz, void **out)
+{
     *out = NULL;
     if (n < 3 || levels < 1 || levels > OR_MAX_LEVELS || degree < 1 || !(lo > 0.0) || !(hi > lo) ||
-        rule < 0 || rule > 1 || coarse_solver < 0 || coarse_solver > 1 ||
+        rule < 0 || rule > 1 || coarse_solver < 0 || coarse_solver > 1 || galerkin < 0 ||
         (coarse_solver == 1 && (!(coarse_rtol > 0.0) || coarse_max_it < 1)))
         return OR_ERR_ARG;
     if ((n - 1) % (1 << (levels - 1)) != 0)
@@ -434,6 +615,7 @@ int or_create2(int n, int levels, int degree, double lo, double hi, int rule, in
     H->degree = degree;
     H->rule = rule;
     H->coarse_solver = coarse_solver;
+    H->galerkin = galerkin;
     H->coarse_rtol = coarse_rtol;
     H->coarse_max_it = coarse_max_it;
     H->lo = lo;
@@ -462,6 +644,16 @@ int or_create2(int n, int levels, int degree, double lo, double hi, int rule, in
         } else {
             or_level *F = &H->lv[l - 1];
             or_coarsen_k_raw(F->n, F->kx, F->ky, F->kz, nl, L->kx, L->ky, L->kz, rule);
+            if (H->galerkin && l >= H->galerkin) {
+                L->a27 = (double *)calloc(nv * 27, sizeof(double));
+                if (!L->a27) {
+                    H->levels = l + 1;
+                    or_destroy(H);
+                    return OR_ERR_NOMEM;
+                }
+                or_op Fo = level_op(F);
+                or_galerkin_op(&Fo, nl, L->a27);
+            }
         }
         nl = (nl - 1) / 2 + 1;
     }
@@ -476,7 +668,10 @@ int or_create2(int n, int levels, int degree, double lo, double hi, int rule, in
         or_destroy(H);
         return OR_ERR_NOMEM;
     }
-    or_assemble_dense_raw(C->n, C->kx, C->ky, C->kz, H->chol);
+    {
+        or_op Co = level_op(C);
+        assemble_dense_op(&Co, H->chol);
+    }
     if (or_cholesky_raw(m, H->chol) != 0) {
         or_destroy(H);
         return OR_ERR_COEFF;
@@ -525,7 +720,8 @@ static int coarse_cg(or_hier *H, const double *b, double *x)
     double *z = (double *)calloc(nv, sizeof(double));
     if (!z)
         return OR_ERR_NOMEM;
-    or_diag_raw(n, C->kx, C->ky, C->kz, dg);
+    or_op Ao = level_op(C);
+    op_diag(&Ao, dg);
     for (size_t i = 0; i < nv; i++) {
         x[i] = 0.0;
         r[i] = b[i];
@@ -539,7 +735,7 @@ static int coarse_cg(or_hier *H, const double *b, double *x)
         return OR_OK;
     }
     for (int it = 0; it < H->coarse_max_it; it++) {
-        or_apply_raw(n, C->kx, C->ky, C->kz, p, q);
+        op_apply(&Ao, p, q);
         double pq = dot_int(n, p, q);
         if (!(pq > 0.0))
             break;
@@ -602,8 +798,9 @@ static int vcycle_level(or_hier *H, int l)
     if (l == H->levels - 1)
         return or_coarse_solve(H, L->b, L->x);
     or_level *C = &H->lv[l + 1];
-    or_cheb_raw(L->n, L->kx, L->ky, L->kz, H->degree, H->lo, H->hi, L->b, L->x, 1, L->work);
-    or_apply_raw(L->n, L->kx, L->ky, L->kz, L->x, L->r);
+    or_op A = level_op(L);
+    cheb_op(&A, H->degree, H->lo, H->hi, L->b, L->x, 1, L->work);
+    op_apply(&A, L->x, L->r);
     size_t nv = nvert(L->n);
     for (size_t p = 0; p < nv; p++)
         L->r[p] = L->b[p] - L->r[p];
@@ -612,7 +809,7 @@ static int vcycle_level(or_hier *H, int l)
     if (st != OR_OK)
         return st;
     or_prolong_add_raw(C->n, C->x, L->n, L->x);
-    or_cheb_raw(L->n, L->kx, L->ky, L->kz, H->degree, H->lo, H->hi, L->b, L->x, 0, L->work);
+    cheb_op(&A, H->degree, H->lo, H->hi, L->b, L->x, 0, L->work);
     return OR_OK;
 }
 
@@ -638,7 +835,8 @@ int or_smooth(void *hp, int l, const double *b, double *x, int x0_zero)
     if (l < 0 || l >= H->levels)
         return OR_ERR_ARG;
     or_level *L = &H->lv[l];
-    or_cheb_raw(L->n, L->kx, L->ky, L->kz, H->degree, H->lo, H->hi, b, x, x0_zero, L->work);
+    or_op A = level_op(L);
+    cheb_op(&A, H->degree, H->lo, H->hi, b, x, x0_zero, L->work);
     return OR_OK;
 }
 
@@ -648,7 +846,8 @@ int or_apply(void *hp, int l, const double *u, double *out)
     if (l < 0 || l >= H->levels)
         return OR_ERR_ARG;
     or_level *L = &H->lv[l];
-    or_apply_raw(L->n, L->kx, L->ky, L->kz, u, out);
+    or_op A = level_op(L);
+    op_apply(&A, u, out);
     return OR_OK;
 }
 
@@ -839,4 +1038,14 @@ int or_adjoint_gradient(void *hp, const double *phi, const double *dl_dphi, doub
         memcpy(lambda, lam, sizeof(double) * nvert(n));
     free(lam);
     return st;
+}
+
+/* Copy the 27-point coarse operator of level l (Galerkin hierarchies). */
+int or_get_a27(void *hp, int l, double *out)
+{
+    or_hier *H = (or_hier *)hp;
+    if (l < 0 || l >= H->levels || !H->lv[l].a27)
+        return OR_ERR_ARG;
+    memcpy(out, H->lv[l].a27, sizeof(double) * nvert(H->lv[l].n) * 27);
+    return OR_OK;
 }

@@ -527,3 +527,109 @@ def test_truncated_flexible_solve_reaches_dense_solution(oracle_mod, n, levels):
     ref = np.linalg.solve(A, mf.interior(f))
     assert info["status"] == "OK" and info["coarse_iterations"] > 0
     np.testing.assert_allclose(mf.interior(x), ref, rtol=1e-9, atol=1e-10 * np.abs(ref).max())
+
+
+# ---------------------------------------------------------------- Galerkin coarse operators
+def a27_to_dense(a27):
+    n = a27.shape[0]
+    m = (n - 2) ** 3
+    M = np.zeros((m, m))
+    for k in range(1, n - 1):
+        for j in range(1, n - 1):
+            for i in range(1, n - 1):
+                p = mf.unknown_index(n, (k, j, i))
+                for dz in (-1, 0, 1):
+                    for dy in (-1, 0, 1):
+                        for dx in (-1, 0, 1):
+                            q = mf.unknown_index(n, (k + dz, j + dy, i + dx))
+                            if q is not None:
+                                M[p, q] = a27[k, j, i, (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)]
+    return M
+
+
+@pytest.mark.parametrize("n", [9, 17])
+def test_galerkin_operator_is_dense_rap(oracle_mod, n):
+    """A_c = P^T A P / 8 from dense matrices (link-assembled A, Kronecker P), two levels deep."""
+    kx, ky, kz = rand_k(n, 90 + n)
+    A = mf.dense_from_links(kx, ky, kz)
+    P = mf.prolongation_matrix(n)
+    Ac_ref = P.T @ A @ P / 8.0
+    a27 = oracle_mod.galerkin(kx, ky, kz)
+    Ac = a27_to_dense(a27)
+    assert np.abs(Ac - Ac_ref).max() <= 1e-12 * np.abs(Ac_ref).max()
+    assert np.abs(Ac - Ac.T).max() <= 1e-12 * np.abs(Ac).max()
+    # second level from the 27-point operator
+    nc = (n - 1) // 2 + 1
+    P2 = mf.prolongation_matrix(nc)
+    Acc_ref = P2.T @ Ac_ref @ P2 / 8.0
+    a27c = oracle_mod.galerkin(*inputs.const_k(nc), a27=a27)
+    assert np.abs(a27_to_dense(a27c) - Acc_ref).max() <= 1e-12 * np.abs(Acc_ref).max()
+    # the hierarchy stores the same operators, and its apply is the 27-point product
+    H = oracle_mod.Hierarchy(kx, ky, kz, levels=3, galerkin=True)
+    np.testing.assert_allclose(H.level_a27(1), a27, rtol=1e-13, atol=1e-12 * np.abs(a27).max())
+    u = rand_vec(nc, 3)
+    np.testing.assert_allclose(mf.interior(H.apply(1, u)), Ac_ref @ mf.interior(u), rtol=1e-11,
+                               atol=1e-11 * np.abs(Ac_ref).max())
+
+
+def dense_vcycle_galerkin(A0, n, levels, m=DEG, lo=LO, hi=HI, first=1, rediscretized=None):
+    """Dense V-cycle whose levels l >= first are P^T A P / 8; levels 0 < l < first
+    take the dense matrices in `rediscretized[l]` (hybrid construction)."""
+    As, ns = [A0], [n]
+    for l in range(1, levels):
+        P = mf.prolongation_matrix(ns[-1])
+        As.append(P.T @ As[-1] @ P / 8.0 if l >= first else rediscretized[l])
+        ns.append((ns[-1] - 1) // 2 + 1)
+
+    def B(l):
+        A = As[l]
+        if l == levels - 1:
+            return np.linalg.inv(A)
+        P = mf.prolongation_matrix(ns[l])
+        K = np.diag(1.0 / np.diag(A)) @ A
+        pK = mf.cheb_poly_matrix(K, m, lo, hi)
+        I = np.eye(A.shape[0])
+        E = pK @ (I - P @ B(l + 1) @ (P.T / 8.0) @ A) @ pK
+        return (I - E) @ np.linalg.inv(A)
+    return B(0)
+
+
+@pytest.mark.parametrize("n,levels", [(9, 2), (9, 3), (17, 3)])
+def test_galerkin_vcycle_matches_dense_composition(oracle_mod, n, levels):
+    kx, ky, kz = rand_k(n, 95 + n + levels)
+    H = oracle_mod.Hierarchy(kx, ky, kz, levels=levels, galerkin=True)
+    Bd = dense_vcycle_galerkin(mf.dense_from_links(kx, ky, kz), n, levels)
+    r = rand_vec(n, 9)
+    ref = Bd @ mf.interior(r)
+    np.testing.assert_allclose(mf.interior(H.vcycle(r)), ref, rtol=1e-10, atol=1e-11 * np.abs(ref).max())
+
+
+def test_galerkin_solve_reaches_dense_solution(oracle_mod):
+    n = 17
+    kx, ky, kz, _ = inputs.inclusion_k(n, 4, rmin_cells=1.0, rmax_cells=3.0)
+    f = inputs.uniform_rhs(n, 5)
+    H = oracle_mod.Hierarchy(kx, ky, kz, levels=4, galerkin=True)
+    x, info = H.solve(f, rtol=1e-12)
+    ref = np.linalg.solve(mf.dense_from_links(kx, ky, kz), mf.interior(f))
+    assert info["status"] == "OK"
+    np.testing.assert_allclose(mf.interior(x), ref, rtol=1e-9, atol=1e-10 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("n,levels,first", [(17, 3, 2), (17, 4, 2), (17, 4, 3)])
+def test_hybrid_galerkin_vcycle_matches_dense_composition(oracle_mod, n, levels, first):
+    """Hybrid coarse operators (Sec. 3.3.3): re-discretized links on levels below
+    `first` (dense-assembled from the coarsened links, the rule pinned above),
+    R A P from there on, each from the operator of the level above it."""
+    kx, ky, kz = rand_k(n, 97 + n + levels + first)
+    H = oracle_mod.Hierarchy(kx, ky, kz, levels=levels, galerkin=first)
+    redisc = {}
+    k = (kx, ky, kz)
+    for l in range(1, first):
+        k = oracle_mod.coarsen_k(*k)
+        redisc[l] = mf.dense_from_links(*k)
+    Bd = dense_vcycle_galerkin(mf.dense_from_links(kx, ky, kz), n, levels, first=first, rediscretized=redisc)
+    r = rand_vec(n, 11)
+    ref = Bd @ mf.interior(r)
+    np.testing.assert_allclose(mf.interior(H.vcycle(r)), ref, rtol=1e-10, atol=1e-11 * np.abs(ref).max())
+    with pytest.raises(Exception):
+        H.level_a27(first - 1)

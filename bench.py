@@ -145,9 +145,16 @@ def sweep(args):
     f = torch.from_numpy(f_np).cuda()
     rows = []
     sizes = [0] + [s for s in (65, 33, 17, 9) if s < n]
-    configs = [dict(precision=p, switch_n=sw) for p in ("fp64", "mixed") for sw in sizes]
+    configs = [dict(precision=p, switch_n=sw, persistent_wgs=1) for p in ("fp64", "mixed") for sw in sizes]
+    configs += [dict(precision=p, switch_n=sw, persistent_wgs=t) for p in ("fp64", "mixed")
+                for sw in sizes if sw > 0 for t in args.teams]
+    for t in args.teams:  # two-stage: team on the middle levels, one workgroup from 9^3 down
+        for sw in [s for s in sizes if s > 17]:
+            configs.append(dict(precision="mixed", switch_n=sw, persistent_wgs=t, switch2_n=9))
     for lt in args.truncate:
         configs.append(dict(precision="fp64", levels=lt, coarse_solver="cg", coarse_rtol=1e-4, flexible=True))
+    for g in args.galerkin:  # Galerkin (g = 1) or hybrid (g > 1) coarse operators
+        configs += [dict(precision=p, switch_n=sw, galerkin=g) for p in ("fp64", "mixed") for sw in (0, 17)]
     for cfg in configs:
         kw = dict(cfg)
         lv = kw.pop("levels", levels)
@@ -165,11 +172,56 @@ def sweep(args):
         coarse = pr.result.get("persistent") or pr.result.get("coarse_solve") or {}
         row = {"levels": lv, **cfg, "iterations": info["iterations"], "coarse_iterations": info["coarse_iterations"],
                "ms": 1e3 * float(np.median(ts)), "ms_per_iteration": 1e3 * float(np.median(ts)) / info["iterations"],
-               "coarse_kernel_us": 1e3 * coarse.get("avg_ms", 0.0), "rel_res_true": info["rel_res_true"]}
+               "coarse_kernel_us": 1e3 * coarse.get("avg_ms", 0.0), "rel_res_true": info["rel_res_true"],
+               "setup_ms": info["setup_ms"]}
         log(json.dumps(row))
         rows.append(row)
         s.close()
     print(json.dumps({"workload": args.workload, "n": n, "rtol": args.rtol, "rows": rows}), flush=True)
+
+
+def profile_summary(d, top=25):
+    """Markdown summary of a rocprofv3 output folder (CSV format): per kernel and
+    grid size the dispatch count and average duration from the kernel trace, and
+    the per-dispatch averages of any collected counters.  Host-only."""
+    import csv
+    import glob
+    from collections import defaultdict
+
+    def short(name):
+        name = name.split("(")[0]
+        return name.replace("void ", "").replace("gmg::", "").replace("unsigned short", "bf16")
+
+    out = []
+    for path in sorted(glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True)):
+        agg = defaultdict(lambda: [0, 0.0])
+        for r in csv.DictReader(open(path)):
+            key = (short(r["Kernel_Name"]), int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"]))
+            a = agg[key]
+            a[0] += 1
+            a[1] += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
+        total = sum(v[1] for v in agg.values())
+        out.append(f"kernel trace: {os.path.relpath(path, d)}  (total kernel time {total / 1e3:.1f} ms)\n")
+        out.append("| kernel | grid (threads) | calls | avg us | total ms | share |")
+        out.append("|---|---:|---:|---:|---:|---:|")
+        for (nm, g), (c, t) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:top]:
+            out.append(f"| `{nm}` | {g} | {c} | {t / c:.1f} | {t / 1e3:.2f} | {100 * t / total:.1f}% |")
+        out.append("")
+    for path in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
+        agg = defaultdict(lambda: [0, 0.0])
+        for r in csv.DictReader(open(path)):
+            grid = r.get("Grid_Size") or r.get("Grid_Size_X") or "0"
+            key = (short(r["Kernel_Name"]), int(float(grid)), r["Counter_Name"])
+            a = agg[key]
+            a[0] += 1
+            a[1] += float(r["Counter_Value"])
+        out.append(f"counters: {os.path.relpath(path, d)}\n")
+        out.append("| kernel | grid (threads) | counter | dispatches | avg per dispatch |")
+        out.append("|---|---:|---|---:|---:|")
+        for (nm, g, cn), (c, v) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:top]:
+            out.append(f"| `{nm}` | {g} | {cn} | {c} | {v / c:.1f} |")
+        out.append("")
+    print("\n".join(out))
 
 
 def main():
@@ -185,9 +237,18 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=2)
     ap.add_argument("--sweep", action="store_true",
                     help="switch-level / truncation sweep of forward solves instead of the benchmark step")
+    ap.add_argument("--teams", type=int, nargs="*", default=[],
+                    help="with --sweep: also time persistent teams of these workgroup counts")
     ap.add_argument("--truncate", type=int, nargs="*", default=[],
                     help="with --sweep: also time truncated hierarchies with these level counts")
+    ap.add_argument("--profile-summary", metavar="DIR",
+                    help="print a markdown summary of a rocprofv3 CSV output folder and exit (host only)")
+    ap.add_argument("--galerkin", type=int, nargs="*", default=[],
+                    help="with --sweep: also time Galerkin coarse operators from these first levels")
     args = ap.parse_args()
+    if args.profile_summary:
+        profile_summary(args.profile_summary)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1).", flush=True)
         sys.exit(2)

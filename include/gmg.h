@@ -72,7 +72,10 @@ typedef struct {
     double cheb_hi;
     int32_t switch_n;       /* 0: grid launches on every level.  Else levels with
                                N_l <= switch_n run inside one persistent kernel */
-    int32_t persistent_wgs; /* workgroups of the persistent kernel (1) */
+    int32_t persistent_wgs; /* workgroups of the persistent kernel, 1..32 (default 1).  More
+                               than one: a co-resident team (cooperative launch) packed
+                               onto one XCD when it fits, with a device-wide barrier
+                               between sweeps; results are identical for any team size */
     int32_t precision;      /* gmg_precision.  MIXED: V-cycle in FP32 with BF16 link
                                coefficients (round-to-nearest-even from FP64), outer
                                PCG, dot products and coarsest Cholesky in FP64 */
@@ -89,6 +92,14 @@ typedef struct {
     int32_t coarse_max_it;  /* coarse CG iteration cap (default 500) */
     int32_t flexible;       /* 1: Polak-Ribiere beta in the outer CG, for preconditioners
                                that change between iterations (inexact coarse solves) */
+    int32_t switch2_n;      /* with persistent_wgs > 1: levels with N_l <= switch2_n leave
+                               the team for a single workgroup (multi-stage agglomeration,
+                               the two-stage repartitioning of Sec. 4.2, Tab. 3); 0 = off */
+    int32_t galerkin;       /* g > 0: levels l >= g use the Galerkin operator R A P (trilinear P,
+                               R = P^T / 8; 27 coefficients per vertex), each from the level
+                               above it; levels below g keep re-discretized links.  g = 1 is
+                               Galerkin throughout (Sec. 3.3.2), g > 1 the hybrid construction
+                               of Sec. 3.3.3.  0 = re-discretized throughout (default). */
 } gmg_options;
 
 typedef struct {
@@ -158,6 +169,13 @@ gmg_status gmg_debug_coarse_solve(gmg_handle *h, const double *b, double *x);
 gmg_status gmg_debug_vcycle(gmg_handle *h, const double *r, double *z);
 /* Copy level coefficients out in face shapes (MIXED: the BF16 values). */
 gmg_status gmg_get_level_coefficients(gmg_handle *h, int32_t level, double *kx, double *ky, double *kz);
+
+/* Galerkin operator of `level` (>= the handle's galerkin level; GMG_ERR_ARG
+ * otherwise) in FP64, written to the device array a27 of N_l^3 * 27 doubles in
+ * natural order: a27[((k*N + j)*N + i)*27 + (dz+1)*9 + (dy+1)*3 + (dx+1)] is
+ * the coefficient of u(i+dx, j+dy, k+dz) in row (i, j, k); boundary rows and
+ * couplings to boundary vertices are 0.  Synchronizes the stream. */
+gmg_status gmg_get_level_stencil(gmg_handle *h, int32_t level, double *a27);
 
 /* ---- kernel timing.  While profiling is on, every launch of a class on the
  * FINEST level (plus the coarse-level classes) is bracketed by HIP events on

@@ -34,6 +34,9 @@ struct LevelHost {
     double *kx64 = nullptr, *ky64 = nullptr, *kz64 = nullptr;
     bf16 *kx16 = nullptr, *ky16 = nullptr, *kz16 = nullptr;
     void *b = nullptr, *x = nullptr, *t1 = nullptr, *dinv = nullptr;
+    bool g27 = false;           // Galerkin level: 27-point operator instead of links
+    double *a64 = nullptr;      // its 27 coefficient arrays (FP64, padded layout)
+    void *av = nullptr;         // the same in the V-cycle type (== a64 in FP64 mode)
     Tiling til{};    // V-cycle stencil kernels
     Tiling til64{};  // FP64 outer operator (apply, residual)
     gmg::Rows rows{};
@@ -61,6 +64,9 @@ struct gmg_handle {
     void *dev_levels = nullptr;   // LevBuf<V,K>[L] on the device
     int s_persist = 0;            // first level run by the persistent kernel (L-1 if none)
     bool persist = false;
+    int persist_spread = 1;       // team packing stride (8 = one XCD) for persistent_wgs > 1
+    int s2_persist = 0;           // first level on a single workgroup below a team (L-1: none)
+    gmg::GridBar *bar = nullptr;  // device barrier of the persistent team
     ChebCoef<double> cheb64{};
     ChebCoef<float> cheb32{};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -195,6 +201,8 @@ Lev<V, K> view(const LevelHost &l) {
     v.ky = KSel<K>::y(l);
     v.kz = KSel<K>::z(l);
     v.dinv = (const V *)l.dinv;
+    v.a27 = l.g27 ? (const V *)l.av : nullptr;
+    v.nel = l.nel;
     return v;
 }
 
@@ -239,6 +247,54 @@ struct Prof {
 gmg_status finalize(gmg_handle *h, int count, int stage, PcgState *state = nullptr);
 
 // ------------------------------------------------------------------ smoothing
+// Chebyshev-Jacobi smoothing on a Galerkin level: the recurrence and buffer
+// rotation of smooth_grid with the 27-point operator, whose centre
+// coefficient is the Jacobi diagonal.
+template <typename V, typename K>
+gmg_status smooth27(gmg_handle *h, int l, bool from_zero, const int *skip) {
+    LevelHost &lh = h->lv[l];
+    const ChebCoef<V> &cc = cheb<V>(h);
+    V *bufs[2] = {(V *)lh.x, (V *)lh.t1};
+    V *b = (V *)lh.b;
+    const V *a = (const V *)lh.av;
+    const dim3 grid(lh.til.nblocks), blk(gmg::NT);
+    int cur, prev;
+    if (from_zero) {
+        V *dst = cc.m == 1 ? bufs[0] : bufs[1];
+        gmg::k_cheb_first<V, K, false><<<grid, blk, 0, h->stream>>>(view<V, K>(lh), lh.til, b, nullptr, nullptr, dst,
+                                                                     cc.cfirst, skip);
+        LAUNCHCHK();
+        if (cc.m == 1) return GMG_OK;
+        cur = 1;
+        prev = -1;
+    } else {
+        gmg::k_sweep27<V, 2, 0><<<grid, blk, 0, h->stream>>>(lh.n, lh.pitch, lh.plane, lh.til, a, lh.nel, b, bufs[0],
+                                                              nullptr, bufs[1], V(0), cc.cfirst, skip);
+        LAUNCHCHK();
+        cur = 1;
+        prev = 0;
+    }
+    for (int j = 1; j < cc.m; ++j) {
+        const int dst = 1 - cur;
+        if (prev < 0)
+            gmg::k_sweep27<V, 2, 1><<<grid, blk, 0, h->stream>>>(lh.n, lh.pitch, lh.plane, lh.til, a, lh.nel, b,
+                                                                  bufs[cur], nullptr, bufs[dst], cc.c1[j], cc.c2[j],
+                                                                  skip);
+        else
+            gmg::k_sweep27<V, 2, 2><<<grid, blk, 0, h->stream>>>(lh.n, lh.pitch, lh.plane, lh.til, a, lh.nel, b,
+                                                                  bufs[cur], bufs[prev], bufs[dst], cc.c1[j],
+                                                                  cc.c2[j], skip);
+        LAUNCHCHK();
+        prev = cur;
+        cur = dst;
+    }
+    if (cur != 0) {
+        gmg::k_cast<V, V><<<gmg::NB_FLAT, gmg::NT_FLAT, 0, h->stream>>>(lh.nel, bufs[1], bufs[0], skip);
+        LAUNCHCHK();
+    }
+    return GMG_OK;
+}
+
 // Chebyshev-Jacobi smoothing of A_l x = b_l on the grid path.  The iterate
 // alternates between x and t1 (x_{j+1} overwrites the buffer of x_{j-1});
 // odd degrees end with a copy into x.  `dot_r64` (finest level, post-smoothing
@@ -248,6 +304,10 @@ template <typename V, typename K>
 gmg_status smooth_grid(gmg_handle *h, int l, bool from_zero, const double *r64_cvt, const double *dot_r64,
                        const int *skip, int *nparts, const double *dot_q64 = nullptr) {
     LevelHost &lh = h->lv[l];
+    if (lh.g27) {  // never the finest level: no conversion, no fused dot
+        if (nparts) *nparts = 0;
+        return smooth27<V, K>(h, l, from_zero, skip);
+    }
     const Lev<V, K> L = view<V, K>(lh);
     const ChebCoef<V> &cc = cheb<V>(h);
     V *bufs[2] = {(V *)lh.x, (V *)lh.t1};
@@ -358,8 +418,13 @@ gmg_status coarse_cg(gmg_handle *h, const int *skip) {
     STCHK(finalize(h, c.rows.nblocks, gmg::ST_C_INIT, h->cst));
     for (int chunk = 0; chunk * 8 < h->opt.coarse_max_it + 8; ++chunk) {
         for (int i = 0; i < 8; ++i) {
-            gmg::k_apply<V, K, true><<<c.til.nblocks, gmg::NT, 0, h->stream>>>(view<V, K>(c), c.til, (const V *)h->cp,
-                                                                               (V *)h->cq, h->partial, cskip);
+            if (c.g27)
+                gmg::k_sweep27<V, 0, 0, true><<<c.til.nblocks, gmg::NT, 0, h->stream>>>(
+                    c.n, c.pitch, c.plane, c.til, (const V *)c.av, c.nel, nullptr, (const V *)h->cp, nullptr,
+                    (V *)h->cq, V(0), V(0), cskip, h->partial);
+            else
+                gmg::k_apply<V, K, true><<<c.til.nblocks, gmg::NT, 0, h->stream>>>(
+                    view<V, K>(c), c.til, (const V *)h->cp, (V *)h->cq, h->partial, cskip);
             LAUNCHCHK();
             STCHK(finalize(h, c.til.nblocks, gmg::ST_C_ALPHA, h->cst));
             gmg::k_cg_update<V><<<c.rows.nblocks, gmg::NT_FLAT, 0, h->stream>>>(
@@ -385,8 +450,13 @@ gmg_status residual_restrict(gmg_handle *h, int l, const int *skip) {
     LevelHost &f = h->lv[l], &c = h->lv[l + 1];
     {
         Prof pf(h, GMG_K_LEVEL_RESIDUAL, l == 0);
-        gmg::k_residual<V, K><<<f.til.nblocks, gmg::NT, 0, h->stream>>>(view<V, K>(f), f.til, (const V *)f.b,
-                                                                        (const V *)f.x, (V *)f.t1, skip);
+        if (f.g27)
+            gmg::k_sweep27<V, 1, 0><<<f.til.nblocks, gmg::NT, 0, h->stream>>>(
+                f.n, f.pitch, f.plane, f.til, (const V *)f.av, f.nel, (const V *)f.b, (const V *)f.x, nullptr,
+                (V *)f.t1, V(0), V(0), skip);
+        else
+            gmg::k_residual<V, K><<<f.til.nblocks, gmg::NT, 0, h->stream>>>(view<V, K>(f), f.til, (const V *)f.b,
+                                                                            (const V *)f.x, (V *)f.t1, skip);
         LAUNCHCHK();
     }
     Prof pf(h, GMG_K_RESTRICT, l == 0);
@@ -401,9 +471,32 @@ gmg_status coarse_part(gmg_handle *h, const int *skip) {
     const int last = h->L - 1;
     if (h->opt.coarse_solver == 1) return coarse_cg<V, K>(h, skip);
     Prof pf(h, h->persist ? GMG_K_PERSISTENT : GMG_K_COARSE_SOLVE, true);
-    if (h->persist) {
-        gmg::k_persistent<V, K><<<1, gmg::NT_PERSIST, 0, h->stream>>>(
-            (const LevBuf<V, K> *)h->dev_levels, h->s_persist, last, cheb<V>(h), h->chol, h->m, skip);
+    if (h->persist && h->opt.persistent_wgs == 1) {
+        gmg::k_persistent<V, K><<<1, gmg::NT_PERSIST, 0, h->stream>>>((const LevBuf<V, K> *)h->dev_levels,
+                                                                       h->s_persist, last, cheb<V>(h), h->chol, h->m,
+                                                                       skip, nullptr, 1, 1, 0);
+    } else if (h->persist) {
+        // A team of co-resident workgroups (cooperative launch: an error, never
+        // a hang, if they cannot all be resident).  With a second switch level the
+        // team runs the middle levels and one workgroup the ones below it.
+        const LevBuf<V, K> *lv = (const LevBuf<V, K> *)h->dev_levels;
+        const int s2 = h->s2_persist;
+        int s0 = h->s_persist, la = s2 < last ? s2 : last, m = h->m, na = h->opt.persistent_wgs,
+            sp = h->persist_spread, ph = s2 < last ? 1 : 0;
+        ChebCoef<V> cc = cheb<V>(h);
+        const double *lf = h->chol;
+        gmg::GridBar *bar = h->bar;
+        void *args[] = {&lv, &s0, &la, &cc, &lf, &m, &skip, &bar, &na, &sp, &ph};
+        HIPCHK(hipLaunchCooperativeKernel((const void *)gmg::k_persistent<V, K>, dim3(na * sp), dim3(gmg::NT_PERSIST),
+                                          args, 0, h->stream));
+        if (s2 < last) {
+            gmg::k_persistent<V, K><<<1, gmg::NT_PERSIST, 0, h->stream>>>(lv, s2, last, cc, h->chol, h->m, skip,
+                                                                           nullptr, 1, 1, 0);
+            LAUNCHCHK();
+            ph = 2;
+            HIPCHK(hipLaunchCooperativeKernel((const void *)gmg::k_persistent<V, K>, dim3(na * sp),
+                                              dim3(gmg::NT_PERSIST), args, 0, h->stream));
+        }
     } else {
         const LevelHost &c = h->lv[last];
         gmg::k_coarse_solve<V><<<1, 256, 0, h->stream>>>(c.n, c.pitch, c.plane, h->m, h->chol, (const V *)c.b,
@@ -571,6 +664,8 @@ gmg_status solve_core(gmg_handle *h, const double *f, const double *x0, double r
     LevelHost &l0 = h->lv[0];
     const long long nv = (long long)l0.n * l0.n * l0.n;
     h->coarse_its = 0;
+    if (h->persist && h->opt.persistent_wgs > 1)  // a clean team barrier for this solve
+        HIPCHK(hipMemsetAsync(h->bar, 0, sizeof(gmg::GridBar), h->stream));
     HIPCHK(hipEventRecord(h->ev0, h->stream));
     gmg::k_to_padded<double><<<blocks_for(nv, 256), 256, 0, h->stream>>>(l0.n, l0.pitch, f, h->F);
     LAUNCHCHK();
@@ -641,6 +736,11 @@ gmg_status solve_core(gmg_handle *h, const double *f, const double *x0, double r
     HIPCHK(hipEventSynchronize(h->ev1));
     float ms = 0;
     HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+    if (h->persist && h->opt.persistent_wgs > 1) {
+        gmg::GridBar gb{};
+        HIPCHK(hipMemcpy(&gb, h->bar, sizeof(gb), hipMemcpyDeviceToHost));
+        if (gb.err) return fail(h, GMG_ERR_HIP, "persistent team barrier timed out");
+    }
     if (info) {
         const PcgState &so = *h->st_out;
         info->iterations = so.its;
@@ -662,16 +762,33 @@ gmg_status solve_core(gmg_handle *h, const double *f, const double *x0, double r
 gmg_status factor_coarsest(gmg_handle *h) {
     LevelHost &c = h->lv[h->L - 1];
     const int n = c.n, nn = n - 2, m = nn * nn * nn;
-    std::vector<double> kx(c.nel), ky(c.nel), kz(c.nel);
-    HIPCHK(hipMemcpyAsync(kx.data(), c.kx64, c.nel * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(hipMemcpyAsync(ky.data(), c.ky64, c.nel * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(hipMemcpyAsync(kz.data(), c.kz64, c.nel * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(hipStreamSynchronize(h->stream));
     std::vector<double> A((size_t)m * m, 0.0);
     auto off = [&](int i, int j, int k) { return (long long)k * c.plane + (long long)j * c.pitch + i; };
     auto unk = [&](int i, int j, int k) { return ((k - 1) * nn + (j - 1)) * nn + (i - 1); };
     auto in = [&](int i, int j, int k) { return i >= 1 && j >= 1 && k >= 1 && i <= n - 2 && j <= n - 2 && k <= n - 2; };
-    for (int k = 1; k <= n - 2; ++k)
+    std::vector<double> kx, ky, kz, a27;
+    if (c.g27) {
+        a27.resize(27 * c.nel);
+        HIPCHK(hipMemcpyAsync(a27.data(), c.a64, 27 * c.nel * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        for (int k = 1; k <= n - 2; ++k)
+            for (int j = 1; j <= n - 2; ++j)
+                for (int i = 1; i <= n - 2; ++i)
+                    for (int d = 0; d < 27; ++d) {
+                        const int di = d % 3 - 1, dj = (d / 3) % 3 - 1, dk = d / 9 - 1;
+                        if (in(i + di, j + dj, k + dk))
+                            A[(size_t)unk(i, j, k) * m + unk(i + di, j + dj, k + dk)] = a27[d * c.nel + off(i, j, k)];
+                    }
+    } else {
+        kx.resize(c.nel);
+        ky.resize(c.nel);
+        kz.resize(c.nel);
+        HIPCHK(hipMemcpyAsync(kx.data(), c.kx64, c.nel * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipMemcpyAsync(ky.data(), c.ky64, c.nel * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipMemcpyAsync(kz.data(), c.kz64, c.nel * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+    }
+    for (int k = 1; k <= n - 2 && !c.g27; ++k)
         for (int j = 1; j <= n - 2; ++j)
             for (int i = 1; i <= n - 2; ++i) {
                 const int p = unk(i, j, k);
@@ -738,6 +855,23 @@ gmg_status load_coefficients(gmg_handle *h, const double *kx, const double *ky, 
             h->opt.coarse_rule);
         LAUNCHCHK();
     }
+    // Galerkin levels: R A P from the level above (links on its first level)
+    for (int l = 1; l < h->L; ++l) {
+        LevelHost &f = h->lv[l - 1], &c = h->lv[l];
+        if (!c.g27) continue;
+        const long long m3 = (long long)(c.n - 2) * (c.n - 2) * (c.n - 2);
+        if (f.g27)
+            gmg::k_galerkin<false><<<blocks_for(m3, 128), 128, 0, h->stream>>>(
+                f.n, f.pitch, f.plane, nullptr, nullptr, nullptr, f.a64, f.nel, c.n, c.pitch, c.plane, c.a64, c.nel);
+        else
+            gmg::k_galerkin<true><<<blocks_for(m3, 128), 128, 0, h->stream>>>(
+                f.n, f.pitch, f.plane, f.kx64, f.ky64, f.kz64, nullptr, f.nel, c.n, c.pitch, c.plane, c.a64, c.nel);
+        LAUNCHCHK();
+        if (mixed(h)) {
+            gmg::k_cast27<float><<<gmg::NB_FLAT, 256, 0, h->stream>>>(27 * c.nel, c.a64, (float *)c.av);
+            LAUNCHCHK();
+        }
+    }
     if (mixed(h)) {
         for (int l = 0; l < h->L; ++l) {
             LevelHost &c = h->lv[l];
@@ -749,7 +883,13 @@ gmg_status load_coefficients(gmg_handle *h, const double *kx, const double *ky, 
     }
     for (int l = 0; l < h->L; ++l) {
         LevelHost &c = h->lv[l];
-        if (mixed(h))
+        if (c.g27 && mixed(h))
+            gmg::k_dinv27<float><<<c.til.nblocks, gmg::NT, 0, h->stream>>>(c.n, c.pitch, c.plane, c.til,
+                                                                          (const float *)c.av, c.nel, (float *)c.dinv);
+        else if (c.g27)
+            gmg::k_dinv27<double><<<c.til.nblocks, gmg::NT, 0, h->stream>>>(c.n, c.pitch, c.plane, c.til, c.a64, c.nel,
+                                                                           (double *)c.dinv);
+        else if (mixed(h))
             gmg::k_dinv<float, bf16><<<c.til.nblocks, gmg::NT, 0, h->stream>>>(view<float, bf16>(c), c.til,
                                                                                 (float *)c.dinv);
         else
@@ -792,6 +932,8 @@ void gmg_default_options(gmg_options *o, int32_t n) {
     o->coarse_rtol = 1e-4;
     o->coarse_max_it = 500;
     o->flexible = 0;
+    o->switch2_n = 0;
+    o->galerkin = 0;
 }
 
 const char *gmg_status_string(gmg_status s) {
@@ -834,9 +976,10 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
     if (o.cheb_degree < 1 || o.cheb_degree > gmg::MAX_DEGREE || !(o.cheb_lo > 0.0) || !(o.cheb_hi > o.cheb_lo) ||
         (o.precision != GMG_FP64 && o.precision != GMG_MIXED) ||
         (o.coarse_rule != GMG_COARSE_ARITHMETIC && o.coarse_rule != GMG_COARSE_HARMONIC) || o.switch_n < 0 ||
-        o.persistent_wgs != 1 || o.check_every < 0 || (o.coeff_is_log != 0 && o.coeff_is_log != 1) ||
+        o.persistent_wgs < 1 || o.persistent_wgs > 32 || o.switch2_n < 0 || o.check_every < 0 || (o.coeff_is_log != 0 && o.coeff_is_log != 1) ||
         (o.coarse_solver != 0 && o.coarse_solver != 1) || (o.flexible != 0 && o.flexible != 1) ||
-        (o.coarse_solver == 1 && (!(o.coarse_rtol > 0.0) || o.coarse_max_it < 1 || o.switch_n != 0)))
+        (o.coarse_solver == 1 && (!(o.coarse_rtol > 0.0) || o.coarse_max_it < 1 || o.switch_n != 0)) ||
+        o.galerkin < 0)
         return GMG_ERR_ARG;
     if ((o.n - 1) % (1 << (o.levels - 1)) != 0) return GMG_ERR_DIMS;
     const int nc = (o.n - 1) / (1 << (o.levels - 1)) + 1;
@@ -876,16 +1019,26 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
         lh.til = make_tiling(n, mx ? env_int("GMG_TARGET_WGS_V", 1024) : t64);
         lh.til64 = make_tiling(n, t64);
         lh.rows = make_rows(n, lh.pitch, lh.plane);
+        lh.g27 = o.galerkin > 0 && l >= o.galerkin;
         n = (n - 1) / 2 + 1;
     }
-    // persistent switch: first level l >= 1 with N_l <= switch_n
+    // persistent switch: first level l >= 1 with N_l <= switch_n; with a team,
+    // the first level with N_l <= switch2_n moves on to a single workgroup
     h->s_persist = h->L - 1;
+    h->s2_persist = h->L - 1;
     h->persist = false;
     if (o.switch_n > 0 && h->L > 1) {
         for (int l = 1; l < h->L; ++l)
             if (h->lv[l].n <= o.switch_n) {
                 h->s_persist = l;
                 h->persist = true;
+                break;
+            }
+    }
+    if (h->persist && o.persistent_wgs > 1 && o.switch2_n > 0) {
+        for (int l = h->s_persist + 1; l < h->L - 1; ++l)
+            if (h->lv[l].n <= o.switch2_n) {
+                h->s2_persist = l;
                 break;
             }
     }
@@ -909,11 +1062,22 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
     ALLOC(h->partial, 2LL * h->npartial);  // two partial arrays for paired sums
     ALLOC(h->st, 1LL);
     ALLOC(h->cst, 1LL);
+    ALLOC(h->bar, 1LL);
     for (int l = 0; l < h->L; ++l) {
         LevelHost &lh = h->lv[l];
         ALLOC(lh.kx64, lh.nel);
         ALLOC(lh.ky64, lh.nel);
         ALLOC(lh.kz64, lh.nel);
+        if (lh.g27) {
+            ALLOC(lh.a64, 27 * lh.nel);
+            if (mx) {
+                float *a;
+                ALLOC(a, 27 * lh.nel);
+                lh.av = a;
+            } else {
+                lh.av = lh.a64;
+            }
+        }
         if (mx) {
             ALLOC(lh.kx16, lh.nel);
             ALLOC(lh.ky16, lh.nel);
@@ -966,6 +1130,23 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
         h->dev_levels = dl;
     }
 #undef ALLOC
+    // persistent team placement: 8 = one workgroup in eight launched, so the
+    // active ones share an XCD; 1 if the packed launch would not fit
+    if (h->persist && o.persistent_wgs > 1) {
+        int dev = 0, coop = 0, ncu = 0, occ = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev);
+        (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        if (!coop) return (h->err = "cooperative launch unsupported", bail(GMG_ERR_HIP));
+        if (mx)
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gmg::k_persistent<float, bf16>, gmg::NT_PERSIST, 0);
+        else
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gmg::k_persistent<double, double>,
+                                                               gmg::NT_PERSIST, 0);
+        const long long cap = (long long)occ * ncu;
+        h->persist_spread = (8LL * o.persistent_wgs <= cap) ? 8 : 1;
+        if ((long long)o.persistent_wgs > cap) return (h->err = "persistent team cannot be co-resident", bail(GMG_ERR_ARG));
+    }
     // Chebyshev coefficients
     {
         const double theta = 0.5 * (o.cheb_hi + o.cheb_lo), delta = 0.5 * (o.cheb_hi - o.cheb_lo);
@@ -1091,8 +1272,15 @@ template <typename V, typename K>
 gmg_status hook_apply(gmg_handle *h, int level, const double *x, double *y) {
     LevelHost &lh = h->lv[level];
     STCHK(in_vec<V>(h, lh, x, (V *)lh.t1));
-    gmg::k_apply<V, K, false><<<lh.til.nblocks, gmg::NT, 0, h->stream>>>(view<V, K>(lh), lh.til, (const V *)lh.t1,
-                                                                        (V *)lh.x, nullptr, nullptr);
+    if (lh.g27)
+        gmg::k_sweep27<V, 0, 0><<<lh.til.nblocks, gmg::NT, 0, h->stream>>>(lh.n, lh.pitch, lh.plane, lh.til,
+                                                                          (const V *)lh.av, lh.nel, nullptr,
+                                                                          (const V *)lh.t1, nullptr, (V *)lh.x, V(0),
+                                                                          V(0), nullptr);
+    else
+        gmg::k_apply<V, K, false><<<lh.til.nblocks, gmg::NT, 0, h->stream>>>(view<V, K>(lh), lh.til,
+                                                                            (const V *)lh.t1, (V *)lh.x, nullptr,
+                                                                            nullptr);
     LAUNCHCHK();
     return out_vec<V>(h, lh, (const V *)lh.x, y);
 }
@@ -1143,6 +1331,7 @@ gmg_status hook_coarse(gmg_handle *h, const double *b, double *x) {
 template <typename V, typename K>
 gmg_status hook_vcycle(gmg_handle *h, const double *r, double *z) {
     LevelHost &l0 = h->lv[0];
+    if (h->persist && h->opt.persistent_wgs > 1) HIPCHK(hipMemsetAsync(h->bar, 0, sizeof(gmg::GridBar), h->stream));
     STCHK(in_vec<double>(h, l0, r, h->R));
     STCHK((vcycle<V, K>(h, nullptr, false, nullptr)));
     return out_vec<V>(h, l0, (const V *)l0.x, z);
@@ -1217,6 +1406,18 @@ gmg_status gmg_get_level_coefficients(gmg_handle *h, int32_t level, double *kx, 
     else
         gmg::k_faces_out<double><<<blocks_for(nv, 256), 256, 0, h->stream>>>(lh.n, lh.pitch, lh.kx64, lh.ky64,
                                                                              lh.kz64, kx, ky, kz);
+    LAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return GMG_OK;
+}
+
+gmg_status gmg_get_level_stencil(gmg_handle *h, int32_t level, double *a27) {
+    STCHK(check_level(h, level));
+    if (!a27) return fail(h, GMG_ERR_ARG, "null array");
+    LevelHost &lh = h->lv[level];
+    if (!lh.g27) return fail(h, GMG_ERR_ARG, "level has no Galerkin operator");
+    const long long nv = (long long)lh.n * lh.n * lh.n;
+    gmg::k_stencil_out<<<blocks_for(nv, 256), 256, 0, h->stream>>>(lh.n, lh.pitch, lh.plane, lh.a64, lh.nel, a27);
     LAUNCHCHK();
     HIPCHK(hipStreamSynchronize(h->stream));
     return GMG_OK;

@@ -109,6 +109,8 @@ struct Lev {
     V s;             // h^-2
     const K *kx, *ky, *kz;
     const V *dinv;   // 1 / diagonal of A at interior vertices, 0 elsewhere
+    const V *a27;    // Galerkin level: 27 coefficient arrays (d27 order), else null
+    long long nel;   // elements per array (n * plane)
 };
 
 // Per-level buffers the V-cycle uses (device-resident array of these).
@@ -155,6 +157,23 @@ __device__ __forceinline__ T cheb_step_val(T xc, T diff, T bv, T ax, T d, T c1, 
     return fmaT(c2, (bv - ax) / d, fmaT(c1, diff, xc));
 }
 
+// Galerkin levels store 27 coefficient arrays; array d27(dx,dy,dz) holds the
+// coefficient of u[p + (dx,dy,dz)] in row p.
+__host__ __device__ constexpr int d27(int dx, int dy, int dz) { return (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1); }
+// (A u)_p of a 27-point level, summed in the fixed order dz, dy, dx.
+template <typename V>
+__device__ __forceinline__ V apply27_at(const V *a, long long nel, const V *u, long long o, int pitch, long long plane) {
+    V acc = V(0);
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx)
+                acc = fmaT(a[(long long)d27(dx, dy, dz) * nel + o], u[o + dz * plane + dy * pitch + dx], acc);
+    return acc;
+}
+
 // The 7 vertex values and 6 link coefficients around offset o, read from memory.
 template <typename V, typename K>
 struct Nbr {
@@ -182,6 +201,7 @@ __device__ __forceinline__ void load_u(const Lev<V, K> &L, const V *u, long long
 }
 template <typename V, typename K>
 __device__ __forceinline__ V apply_at(const Lev<V, K> &L, const V *u, long long o) {
+    if (L.a27) return apply27_at(L.a27, L.nel, u, o, L.pitch, L.plane);
     Nbr<V, K> q;
     load_k(L, o, q);
     load_u(L, u, o, q);
@@ -328,14 +348,20 @@ __global__ __launch_bounds__(NT) void k_cheb_first(Lev<V, K> L, Tiling t, const 
 // evaluated on the fly at the seven stencil points (it is pointwise), and
 //   x2 = x1 + c1 x1 + c2 D^-1 (b - A x1).
 // Same values as k_cheb_first followed by the PM = 1 step.  WX1 also stores
-// x1 (needed as the previous iterate when the degree exceeds 2).
+// x1 (needed as the previous iterate when the degree exceeds 2).  Each lane
+// evaluates x1 of its own column for planes k-1..k+1 and takes its x
+// neighbours from the adjacent lanes; only the two edge lanes of a wave
+// evaluate an outside neighbour.  Lanes outside the interior stay alive
+// (their b and D^-1 are the stored zeros) so the shuffles see every lane.
 template <typename V, typename K, bool WX1>
 __global__ __launch_bounds__(NT) void k_cheb_pre2(Lev<V, K> L, Tiling t, const V *__restrict__ b,
                                                   V *__restrict__ out, V *__restrict__ x1out, V c0, V c1, V c2,
                                                   const int *__restrict__ skip) {
     if (skip && *skip) return;
     const Column col = tile_column(L.n, t);
-    if (!col.active) return;
+    if (col.j > L.n - 2 || col.k0 >= col.k1) return;  // uniform over the wave
+    const bool act = col.i >= 1 && col.i <= L.n - 2;
+    const int lane = threadIdx.x & (TX - 1);
     const int pitch = L.pitch;
     const long long plane = L.plane;
     const V *__restrict__ dv = L.dinv;
@@ -347,15 +373,19 @@ __global__ __launch_bounds__(NT) void k_cheb_pre2(Lev<V, K> L, Tiling t, const V
     for (int k = col.k0; k < col.k1; ++k, o += plane) {
         const V bt = b[o + plane];
         const V ut = cheb_first_val(bt, dv[o + plane], c0);
-        const V uw = cheb_first_val(b[o - 1], dv[o - 1], c0), ue = cheb_first_val(b[o + 1], dv[o + 1], c0);
+        V uw = __shfl_up(up, 1, TX), ue = __shfl_down(up, 1, TX);
+        if (lane == 0) uw = cheb_first_val(b[o - 1], dv[o - 1], c0);
+        if (lane == TX - 1) ue = cheb_first_val(b[o + 1], dv[o + 1], c0);
         const V us = cheb_first_val(b[o - pitch], dv[o - pitch], c0),
                 un = cheb_first_val(b[o + pitch], dv[o + pitch], c0);
         const V kw = kval(L.kx[o - 1]), ke = kval(ldnt(&L.kx[o])), ks = kval(L.ky[o - pitch]), kn = kval(L.ky[o]),
                 kt = kval(ldnt(&L.kz[o]));
-        const V ax = apply7(up, uw, ue, us, un, ub, ut, kw, ke, ks, kn, kb, kt, L.s);
-        const V d = diag7(kw, ke, ks, kn, kb, kt, L.s);
-        stnt(cheb_step_val(up, up, bp, ax, d, c1, c2), &out[o]);
-        if (WX1) stnt(up, &x1out[o]);
+        if (act) {
+            const V ax = apply7(up, uw, ue, us, un, ub, ut, kw, ke, ks, kn, kb, kt, L.s);
+            const V d = diag7(kw, ke, ks, kn, kb, kt, L.s);
+            stnt(cheb_step_val(up, up, bp, ax, d, c1, c2), &out[o]);
+            if (WX1) stnt(up, &x1out[o]);
+        }
         ub = up;
         up = ut;
         bp = bt;
@@ -613,11 +643,60 @@ __global__ __launch_bounds__(256) void k_coarse_solve(int n, int pitch, long lon
 }
 
 // ---------------------------------------------------------------- persistent coarse kernel
-// Levels s..last-1 of the V-cycle plus the coarsest solve, all inside one
-// workgroup: every sweep is a block-strided loop over the level's interior
-// vertices followed by a workgroup barrier.  The per-vertex arithmetic is the
-// same value functions the grid kernels call.
-template <typename V, typename K>
+// Levels s..last-1 of the V-cycle plus the coarsest solve in ONE launch, run
+// by a team of one or a few co-resident workgroups: every sweep is a
+// team-strided loop over the level's interior vertices followed by a team
+// barrier (a workgroup barrier for one workgroup, a device-wide barrier
+// otherwise).  Each vertex is computed by exactly one thread with the value
+// functions the grid kernels call, so the result does not depend on the team
+// size or on the switch level.
+
+// Device-wide barrier of `n` workgroups (cooperative launch guarantees they
+// are co-resident).  Generation counting; the wait is bounded: after ~2^24
+// polls the barrier records an error and stops waiting (every later barrier
+// of the kernel then passes at once), so a kernel always terminates.
+struct GridBar {
+    unsigned count, gen, err, pad;
+};
+__device__ void grid_sync(GridBar *gb, unsigned n) {
+    __threadfence();  // release this thread's global writes at device scope
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (__hip_atomic_load(&gb->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+            const unsigned g = __hip_atomic_load(&gb->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned arrived = __hip_atomic_fetch_add(&gb->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if (arrived == n - 1) {
+                __hip_atomic_store(&gb->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(&gb->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                unsigned polls = 0;
+                while (__hip_atomic_load(&gb->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                    __builtin_amdgcn_s_sleep(1);
+                    if (++polls > (1u << 24)) {
+                        __hip_atomic_store(&gb->err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        break;
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    __threadfence();  // acquire: later loads see the other workgroups' writes
+}
+
+struct Team {
+    int rank, size;  // this workgroup among the active ones
+    GridBar *bar;    // null for a single workgroup
+    __device__ int first() const { return rank * (int)blockDim.x + (int)threadIdx.x; }
+    __device__ int stride() const { return size * (int)blockDim.x; }
+    __device__ void sync() const {
+        if (size == 1)
+            __syncthreads();
+        else
+            grid_sync(bar, (unsigned)size);
+    }
+};
+
 __device__ __forceinline__ void vertex_of(int n, int u, int &i, int &j, int &k) {
     const int nn = n - 2;
     i = 1 + u % nn;
@@ -626,120 +705,285 @@ __device__ __forceinline__ void vertex_of(int n, int u, int &i, int &j, int &k) 
 }
 
 template <typename V, typename K>
-__device__ void p_cheb_first(const LevBuf<V, K> &lb, V *out, V c) {
+__device__ void p_cheb_first(const Team &T, const LevBuf<V, K> &lb, V *out, V c) {
     const Lev<V, K> &L = lb.L;
     const int np = (L.n - 2) * (L.n - 2) * (L.n - 2);
-    for (int u = threadIdx.x; u < np; u += blockDim.x) {
+    for (int u = T.first(); u < np; u += T.stride()) {
         int i, j, k;
-        vertex_of<V, K>(L.n, u, i, j, k);
+        vertex_of(L.n, u, i, j, k);
         const long long o = (long long)k * L.plane + (long long)j * L.pitch + i;
         out[o] = cheb_first_val(lb.b[o], L.dinv[o], c);
     }
-    __syncthreads();
+    T.sync();
 }
 template <typename V, typename K>
-__device__ void p_cheb_step(const LevBuf<V, K> &lb, const V *x, const V *xp, int pm, V *out, V c1, V c2) {
+__device__ void p_cheb_step(const Team &T, const LevBuf<V, K> &lb, const V *x, const V *xp, int pm, V *out, V c1,
+                            V c2) {
     const Lev<V, K> &L = lb.L;
     const int np = (L.n - 2) * (L.n - 2) * (L.n - 2);
-    for (int u = threadIdx.x; u < np; u += blockDim.x) {
+    for (int u = T.first(); u < np; u += T.stride()) {
         int i, j, k;
-        vertex_of<V, K>(L.n, u, i, j, k);
+        vertex_of(L.n, u, i, j, k);
         const long long o = (long long)k * L.plane + (long long)j * L.pitch + i;
-        Nbr<V, K> q;
-        load_k(L, o, q);
-        load_u(L, x, o, q);
-        const V ax = apply7(q.up, q.uw, q.ue, q.us, q.un, q.ub, q.ut, q.kw, q.ke, q.ks, q.kn, q.kb, q.kt, L.s);
-        const V d = diag7(q.kw, q.ke, q.ks, q.kn, q.kb, q.kt, L.s);
-        const V diff = pm == 0 ? V(0) : pm == 1 ? q.up : q.up - xp[o];
-        out[o] = cheb_step_val(q.up, diff, lb.b[o], ax, d, pm == 0 ? V(0) : c1, c2);
+        V ax, d, up;
+        if (L.a27) {  // uniform over the level
+            ax = apply27_at(L.a27, L.nel, x, o, L.pitch, L.plane);
+            d = L.a27[(long long)d27(0, 0, 0) * L.nel + o];
+            up = x[o];
+        } else {
+            Nbr<V, K> q;
+            load_k(L, o, q);
+            load_u(L, x, o, q);
+            ax = apply7(q.up, q.uw, q.ue, q.us, q.un, q.ub, q.ut, q.kw, q.ke, q.ks, q.kn, q.kb, q.kt, L.s);
+            d = diag7(q.kw, q.ke, q.ks, q.kn, q.kb, q.kt, L.s);
+            up = q.up;
+        }
+        const V diff = pm == 0 ? V(0) : pm == 1 ? up : up - xp[o];
+        out[o] = cheb_step_val(up, diff, lb.b[o], ax, d, pm == 0 ? V(0) : c1, c2);
     }
-    __syncthreads();
+    T.sync();
 }
 template <typename V>
-__device__ void p_copy(int n, int pitch, long long plane, const V *src, V *dst) {
+__device__ void p_copy(const Team &T, int n, int pitch, long long plane, const V *src, V *dst) {
     const int np = (n - 2) * (n - 2) * (n - 2);
-    const int nn = n - 2;
-    for (int u = threadIdx.x; u < np; u += blockDim.x) {
-        const int i = 1 + u % nn, j = 1 + (u / nn) % nn, k = 1 + u / (nn * nn);
+    for (int u = T.first(); u < np; u += T.stride()) {
+        int i, j, k;
+        vertex_of(n, u, i, j, k);
         const long long o = (long long)k * plane + (long long)j * pitch + i;
         dst[o] = src[o];
     }
-    __syncthreads();
+    T.sync();
 }
 
 // Smoothing schedule shared by both paths (see the host-side driver): the
 // iterate alternates between x and t1; odd degrees end with a copy into x.
 template <typename V, typename K>
-__device__ void p_smooth(const LevBuf<V, K> &lb, const ChebCoef<V> &cc, bool from_zero) {
+__device__ void p_smooth(const Team &T, const LevBuf<V, K> &lb, const ChebCoef<V> &cc, bool from_zero) {
     const Lev<V, K> &L = lb.L;
     V *bufs[2] = {lb.x, lb.t1};
     int cur;  // index of the buffer holding x_j
     int prev; // buffer holding x_{j-1} (or -1)
     if (from_zero) {
         if (cc.m == 1) {
-            p_cheb_first(lb, lb.x, cc.cfirst);
+            p_cheb_first(T, lb, lb.x, cc.cfirst);
             return;
         }
-        p_cheb_first(lb, lb.t1, cc.cfirst);  // x_1 in t1
+        p_cheb_first(T, lb, lb.t1, cc.cfirst);  // x_1 in t1
         cur = 1;
         prev = -1;  // x_0 = 0
     } else {
-        p_cheb_step(lb, lb.x, (const V *)nullptr, 0, lb.t1, V(0), cc.cfirst);  // x_1 in t1
+        p_cheb_step(T, lb, lb.x, (const V *)nullptr, 0, lb.t1, V(0), cc.cfirst);  // x_1 in t1
         cur = 1;
         prev = 0;
         if (cc.m == 1) {
-            p_copy(L.n, L.pitch, L.plane, lb.t1, lb.x);
+            p_copy(T, L.n, L.pitch, L.plane, lb.t1, lb.x);
             return;
         }
     }
     for (int j = 1; j < cc.m; ++j) {
         const int dst = 1 - cur;  // the buffer of x_{j-1} (or the free one)
         if (prev < 0)
-            p_cheb_step(lb, bufs[cur], (const V *)nullptr, 1, bufs[dst], cc.c1[j], cc.c2[j]);
+            p_cheb_step(T, lb, bufs[cur], (const V *)nullptr, 1, bufs[dst], cc.c1[j], cc.c2[j]);
         else
-            p_cheb_step(lb, bufs[cur], bufs[prev], 2, bufs[dst], cc.c1[j], cc.c2[j]);
+            p_cheb_step(T, lb, bufs[cur], bufs[prev], 2, bufs[dst], cc.c1[j], cc.c2[j]);
         prev = cur;
         cur = dst;
     }
-    if (cur != 0) p_copy(L.n, L.pitch, L.plane, lb.t1, lb.x);
+    if (cur != 0) p_copy(T, L.n, L.pitch, L.plane, lb.t1, lb.x);
 }
 
+// `spread` > 1 packs the team onto one XCD: the launch has nactive*spread
+// workgroups and only those with blockIdx % spread == 0 work (dispatch is
+// round-robin over the XCDs); the others return at once.
+// phase 0: levels s..last-1 down, the coarsest solve on level `last`, and
+//          back up (a whole V-cycle below s);
+// phase 1: only the down sweep of levels s..last-1 (right-hand side of `last`);
+// phase 2: only the up sweep of levels last-1..s (correction from `last`).
+// Phases 1 and 2 let a team run the middle levels while a single workgroup
+// runs the ones below (multi-stage agglomeration).
 template <typename V, typename K>
 __global__ __launch_bounds__(NT_PERSIST) void k_persistent(const LevBuf<V, K> *__restrict__ lv, int s, int last,
                                                            ChebCoef<V> cc, const double *__restrict__ Lf, int m,
-                                                           const int *__restrict__ skip) {
+                                                           const int *__restrict__ skip, GridBar *bar, int nactive,
+                                                           int spread, int phase) {
     if (skip && *skip) return;
+    if ((int)blockIdx.x % spread != 0) return;
+    const Team T{(int)blockIdx.x / spread, nactive, bar};
     __shared__ double y[MAX_COARSE];
-    for (int l = s; l < last; ++l) {
+    for (int l = s; l < last && phase != 2; ++l) {
         const LevBuf<V, K> F = lv[l];
         const LevBuf<V, K> C = lv[l + 1];
-        p_smooth(F, cc, true);
+        p_smooth(T, F, cc, true);
         const int nc = C.L.n, mc = nc - 2;
         const int np = mc * mc * mc;
-        for (int u = threadIdx.x; u < np; u += blockDim.x) {
+        for (int u = T.first(); u < np; u += T.stride()) {
             const int I = 1 + u % mc, J = 1 + (u / mc) % mc, K_ = 1 + u / (mc * mc);
             C.b[(long long)K_ * C.L.plane + (long long)J * C.L.pitch + I] =
                 restrict_resid_at(F.L, F.b, F.x, I, J, K_);
         }
-        __syncthreads();
+        T.sync();
     }
-    {
-        const LevBuf<V, K> C = lv[last];
-        chol_solve_block(C.L.n, C.L.pitch, C.L.plane, m, Lf, C.b, C.x, y);
+    if (phase == 1) return;
+    if (phase == 0) {
+        if (T.rank == 0) {
+            const LevBuf<V, K> C = lv[last];
+            chol_solve_block(C.L.n, C.L.pitch, C.L.plane, m, Lf, C.b, C.x, y);
+        }
+        T.sync();
     }
     for (int l = last - 1; l >= s; --l) {
         const LevBuf<V, K> F = lv[l];
         const LevBuf<V, K> C = lv[l + 1];
         const int mf = F.L.n - 2;
         const int np = mf * mf * mf;
-        for (int u = threadIdx.x; u < np; u += blockDim.x) {
+        for (int u = T.first(); u < np; u += T.stride()) {
             const int i = 1 + u % mf, j = 1 + (u / mf) % mf, k = 1 + u / (mf * mf);
             const long long o = (long long)k * F.L.plane + (long long)j * F.L.pitch + i;
             F.x[o] = F.x[o] + prolong_at(C.x, C.L.pitch, C.L.plane, i, j, k);
         }
-        __syncthreads();
-        p_smooth(F, cc, false);
+        T.sync();
+        p_smooth(T, F, cc, false);
     }
+}
+
+// ================================================================ Galerkin coarse operators
+// A_c = R A P with trilinear P and R = P^T / 8 (27 coefficients per coarse
+// vertex).  Storage: 27 arrays in the level's padded layout, array
+// d = (dz+1)*9 + (dy+1)*3 + (dx+1) holds the coefficient of u[p + (dx,dy,dz)];
+// boundary vertices and padding hold 0.
+
+// 1D trilinear weight of coarse index offset `c` at fine offset `q` (both
+// relative to the coarse vertex, fine offset counted on the fine grid).
+__host__ __device__ constexpr double pw1(int q, int c) {
+    return (q - 2 * c) == 0 ? 1.0 : ((q - 2 * c) == 1 || (q - 2 * c) == -1) ? 0.5 : 0.0;
+}
+
+// One thread per coarse interior vertex I: for every fine point p = 2I + dp
+// (dp in -1..1 per axis), every fine neighbour q = p + dq of the fine stencil,
+// and every coarse vertex J = I + D, add R[I][p] A[p][q] P[q][J] to a[D].  The
+// p and q loops run at run time; the 27 D terms are unrolled so that the sums
+// stay in registers (weights that vanish contribute exact zeros).  Fine values
+// at boundary q and coarse values at boundary J are excluded (zero Dirichlet
+// data).
+template <bool LINKS>
+__global__ __launch_bounds__(128) void k_galerkin(int n, int pitch, long long plane, const double *__restrict__ kx,
+                                                  const double *__restrict__ ky, const double *__restrict__ kz,
+                                                  const double *__restrict__ af, long long nel_f, int nc, int pc,
+                                                  long long plc, double *__restrict__ ac, long long nel_c) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = nc - 2;
+    if (idx >= (long long)m * m * m) return;
+    const int I = 1 + (int)(idx % m), J = 1 + (int)((idx / m) % m), K_ = 1 + (int)(idx / ((long long)m * m));
+    const double s = (double)(n - 1) * (double)(n - 1);
+    double acc[27];
+#pragma unroll
+    for (int d = 0; d < 27; ++d) acc[d] = 0.0;
+    // coarse vertices off the boundary, per axis and offset -1, 0, 1
+    const double ci[3] = {I > 1 ? 1.0 : 0.0, 1.0, I < nc - 2 ? 1.0 : 0.0};
+    const double cj[3] = {J > 1 ? 1.0 : 0.0, 1.0, J < nc - 2 ? 1.0 : 0.0};
+    const double ck[3] = {K_ > 1 ? 1.0 : 0.0, 1.0, K_ < nc - 2 ? 1.0 : 0.0};
+    for (int dp = 0; dp < 27; ++dp) {
+        const int px = dp % 3 - 1, py = (dp / 3) % 3 - 1, pz = dp / 9 - 1;
+        const int pi = 2 * I + px, pj = 2 * J + py, pk = 2 * K_ + pz;
+        const double r = pw1(px, 0) * pw1(py, 0) * pw1(pz, 0) / 8.0;
+        const long long po = (long long)pk * plane + (long long)pj * pitch + pi;
+        for (int dq = 0; dq < 27; ++dq) {
+            const int qx = dq % 3 - 1, qy = (dq / 3) % 3 - 1, qz = dq / 9 - 1;
+            const int nz = (qx != 0) + (qy != 0) + (qz != 0);
+            if (LINKS && nz > 1) continue;
+            const int qi = pi + qx, qj = pj + qy, qk = pk + qz;
+            if (qi < 1 || qj < 1 || qk < 1 || qi > n - 2 || qj > n - 2 || qk > n - 2) continue;
+            double a;
+            if (LINKS) {
+                if (nz == 0)
+                    a = s * (((kx[po - 1] + kx[po]) + (ky[po - pitch] + ky[po])) + (kz[po - plane] + kz[po]));
+                else if (qx)
+                    a = -s * kx[qx < 0 ? po - 1 : po];
+                else if (qy)
+                    a = -s * ky[qy < 0 ? po - pitch : po];
+                else
+                    a = -s * kz[qz < 0 ? po - plane : po];
+            } else {
+                a = af[(long long)dq * nel_f + po];
+            }
+            const double ra = r * a;
+            // fine offset of q from 2I on each axis, in -2..2
+            const int fx = px + qx, fy = py + qy, fz = pz + qz;
+#pragma unroll
+            for (int Dz = -1; Dz <= 1; ++Dz)
+#pragma unroll
+                for (int Dy = -1; Dy <= 1; ++Dy)
+#pragma unroll
+                    for (int Dx = -1; Dx <= 1; ++Dx) {
+                        const double w = pw1(fx, Dx) * pw1(fy, Dy) * pw1(fz, Dz) * ci[Dx + 1] * cj[Dy + 1] *
+                                         ck[Dz + 1];
+                        acc[d27(Dx, Dy, Dz)] = fmaT(ra, w, acc[d27(Dx, Dy, Dz)]);
+                    }
+        }
+    }
+    const long long oc = (long long)K_ * plc + (long long)J * pc + I;
+#pragma unroll
+    for (int d = 0; d < 27; ++d) ac[(long long)d * nel_c + oc] = acc[d];
+}
+
+template <typename V>
+__global__ __launch_bounds__(256) void k_cast27(long long n, const double *__restrict__ src, V *__restrict__ dst) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) dst[e] = (V)src[e];
+}
+
+// D^-1 of a 27-point level: 1 / centre coefficient at interior vertices.
+template <typename V>
+__global__ __launch_bounds__(NT) void k_dinv27(int n, int pitch, long long plane, Tiling t, const V *__restrict__ a,
+                                               long long nel, V *__restrict__ dinv) {
+    const Column col = tile_column(n, t);
+    if (!col.active) return;
+    long long o = (long long)col.k0 * plane + (long long)col.j * pitch + col.i;
+    for (int k = col.k0; k < col.k1; ++k, o += plane) dinv[o] = V(1) / a[(long long)d27(0, 0, 0) * nel + o];
+}
+
+// 27-point sweeps on Galerkin levels.  MODE 0: y = A u (DOT: partial[wg] =
+// sum u.y, the coarse CG's p.Ap);  1: y = b - A u;  2: Chebyshev step (PM as in
+// k_cheb_step; the diagonal is the centre coefficient).  out may alias xp.
+template <typename V, int MODE, int PM, bool DOT = false>
+__global__ __launch_bounds__(NT) void k_sweep27(int n, int pitch, long long plane, Tiling t, const V *__restrict__ a,
+                                                long long nel, const V *__restrict__ b, const V *__restrict__ u,
+                                                const V *xp, V *out, V c1, V c2, const int *__restrict__ skip,
+                                                double *__restrict__ partial = nullptr) {
+    if (skip && *skip) return;
+    const Column col = tile_column(n, t);
+    double dot = 0.0;
+    if (col.active) {
+        long long o = (long long)col.k0 * plane + (long long)col.j * pitch + col.i;
+        for (int k = col.k0; k < col.k1; ++k, o += plane) {
+            const V au = apply27_at(a, nel, u, o, pitch, plane);
+            if (MODE == 0) {
+                out[o] = au;
+                if (DOT) dot = fmaT((double)u[o], (double)au, dot);
+            } else if (MODE == 1) {
+                out[o] = b[o] - au;
+            } else {
+                const V up = u[o];
+                const V d = a[(long long)d27(0, 0, 0) * nel + o];
+                const V diff = PM == 0 ? V(0) : PM == 1 ? up : up - xp[o];
+                out[o] = cheb_step_val(up, diff, b[o], au, d, PM == 0 ? V(0) : c1, c2);
+            }
+        }
+    }
+    if (DOT) {
+        const double s = block_sum<NT>(dot);
+        if (threadIdx.x == 0) partial[blockIdx.x] = s;
+    }
+}
+
+// Natural-layout copy of a Galerkin level's stencil: out[v*27 + d], v = (k*n + j)*n + i.
+__global__ __launch_bounds__(256) void k_stencil_out(int n, int pitch, long long plane, const double *__restrict__ a,
+                                                     long long nel, double *__restrict__ out) {
+    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= (long long)n * n * n) return;
+    const int i = (int)(v % n), j = (int)((v / n) % n), k = (int)(v / ((long long)n * n));
+    const long long o = (long long)k * plane + (long long)j * pitch + i;
+    for (int d = 0; d < 27; ++d) out[v * 27 + d] = a[(long long)d * nel + o];
 }
 
 // ================================================================ PCG vector kernels (FP64)

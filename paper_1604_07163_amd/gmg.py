@@ -31,7 +31,8 @@ class Options(ctypes.Structure):
                 ("coarse_rule", ctypes.c_int32), ("coeff_is_log", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("coarse_solver", ctypes.c_int32),
                 ("coarse_rtol", ctypes.c_double), ("coarse_max_it", ctypes.c_int32),
-                ("flexible", ctypes.c_int32)]
+                ("flexible", ctypes.c_int32), ("switch2_n", ctypes.c_int32),
+                ("galerkin", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -98,6 +99,8 @@ def lib():
     L.gmg_debug_vcycle.restype = st
     L.gmg_get_level_coefficients.argtypes = [P, I32, P, P, P]
     L.gmg_get_level_coefficients.restype = st
+    L.gmg_get_level_stencil.argtypes = [P, I32, P]
+    L.gmg_get_level_stencil.restype = st
     L.gmg_profile_start.argtypes = [P]
     L.gmg_profile_start.restype = st
     L.gmg_profile_stop.argtypes = [P]
@@ -141,7 +144,8 @@ class Solver:
 
     def __init__(self, kx, ky, kz, *, levels=None, precision="fp64", switch_n=0, coarse_rule="arithmetic",
                  cheb_degree=2, cheb_lo=0.25, cheb_hi=2.0, coeff_is_log=False, check_every=0,
-                 persistent_wgs=1, coarse_solver="exact", coarse_rtol=1e-4, coarse_max_it=500, flexible=False):
+                 persistent_wgs=1, coarse_solver="exact", coarse_rtol=1e-4, coarse_max_it=500, flexible=False,
+                 switch2_n=0, galerkin=0):
         L = lib()
         n = int(kx.shape[0])
         self.n = n
@@ -163,6 +167,8 @@ class Solver:
         o.coarse_rtol = float(coarse_rtol)
         o.coarse_max_it = int(coarse_max_it)
         o.flexible = 1 if flexible else 0
+        o.switch2_n = int(switch2_n)
+        o.galerkin = int(galerkin)
         self.options = o
         self.levels = o.levels
         self._h = ctypes.c_void_p()
@@ -313,6 +319,17 @@ class Solver:
         if s != OK:
             self._err(s, "gmg_get_level_coefficients")
         return kx, ky, kz
+
+    def level_stencil(self, level):
+        """FP64 Galerkin operator of `level` as an (N, N, N, 27) tensor, entry
+        (dz+1)*9 + (dy+1)*3 + (dx+1) the coefficient of u(i+dx, j+dy, k+dz)."""
+        self._sync_stream()
+        n = self.level_n(level)
+        out = torch.empty((n, n, n, 27), dtype=torch.float64, device="cuda")
+        s = lib().gmg_get_level_stencil(self._h, level, _dev(out, "a27"))
+        if s != OK:
+            self._err(s, "gmg_get_level_stencil")
+        return out
 
 
 KERNEL_CLASSES = ["apply_dot", "residual", "update_r", "update_p", "cheb_first", "cheb_step", "cheb_step_prev",

@@ -94,11 +94,20 @@ def test_vcycle_and_switch_invariance(n, levels):
     assert rel_max(base, ref) <= 1e-12, rel_max(base, ref)
     sizes = sorted({H.level_n(l) for l in range(1, levels)})
     for sw in sizes:
-        sp = gmg.Solver(*[to_gpu(a) for a in k], levels=levels, switch_n=sw)
+        for wgs in (1, 4, 8):
+            sp = gmg.Solver(*[to_gpu(a) for a in k], levels=levels, switch_n=sw, persistent_wgs=wgs)
+            z = to_np(sp.vcycle(to_gpu(r)))
+            d = rel_max(z, base)
+            say(f"    switch {sw} team {wgs}: max rel diff vs grid path {d:.3e} (bitwise: {np.array_equal(z, base)})")
+            assert np.array_equal(z, base)
+            sp.close()
+    # multi-stage: a team on the middle levels, one workgroup below switch2
+    if len(sizes) >= 3:
+        sp = gmg.Solver(*[to_gpu(a) for a in k], levels=levels, switch_n=sizes[-1], persistent_wgs=4,
+                        switch2_n=sizes[1])
         z = to_np(sp.vcycle(to_gpu(r)))
-        d = rel_max(z, base)
-        say(f"    switch {sw}: max rel diff vs grid path {d:.3e} (bitwise: {np.array_equal(z, base)})")
-        assert d <= 1e-14
+        say(f"    multi-stage switch {sizes[-1]} -> team 4 -> {sizes[1]} -> 1 wg: bitwise {np.array_equal(z, base)}")
+        assert np.array_equal(z, base)
 
 
 def test_bf16_coefficients_round_to_nearest_even():

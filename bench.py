@@ -37,7 +37,7 @@ BYTES_PER_POINT = {
     "fp64": {"apply_dot": 40, "residual": 48, "update_r": 24, "update_xp": 40, "update_p": 16, "cheb_first": 24, "cheb_pre2": 48,
              "cheb_step": 48, "cheb_step_prev": 56, "cheb_step_dot": 56, "level_residual": 48,
              "restrict": 9, "prolong": 17, "face_gradient": 64},
-    "mixed": {"apply_dot": 40, "residual": 48, "update_r": 28, "update_xp": 36, "update_p": 12, "cheb_first": 12, "cheb_pre2": 18,
+    "mixed": {"apply_dot": 36, "residual": 48, "update_r": 28, "update_xp": 28, "update_p": 8, "cheb_first": 20, "cheb_pre2": 18,
               "cheb_step": 18, "cheb_step_prev": 22, "cheb_step_dot": 30, "level_residual": 18,
               "restrict": 4.5, "prolong": 8.5, "face_gradient": 64},
 }
@@ -224,6 +224,98 @@ def profile_summary(d, top=25):
     print("\n".join(out))
 
 
+# Finest-level kernel of each class in the MIXED step, as rocprofv3 names it.
+CLASS_KERNELS = {
+    "apply_dot": "k_apply_x2<true, float>",
+    "update_r": "k_update_r<float>",
+    "update_xp": "k_update_xp<float, float>",
+    "cheb_pre2": "k_cheb_pre2<float, bf16, false>",
+    "cheb_step": "k_cheb_step<float, bf16, 0, false>",
+    "cheb_step_dot": "k_cheb_step<float, bf16, 2, true>",
+    "level_residual": "k_residual<float, bf16>",
+    "restrict": "k_restrict<float>",
+    "prolong": "k_prolong<float>",
+}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_inclusions513.md")
+COPY_BYTES = 2 << 30  # copy_bandwidth(): bytes read (and written) per calibration copy
+
+
+def source_digest():
+    """sha256 of the kernel and driver sources: counter figures hold for this build only."""
+    import hashlib
+    hsh = hashlib.sha256()
+    for rel in ("paper_1604_07163_amd/csrc/kernels.hpp", "paper_1604_07163_amd/csrc/gmg.hip"):
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            hsh.update(fh.read())
+    return hsh.hexdigest()[:16]
+
+
+def _short(name):
+    return name.split("(")[0].replace("void ", "").replace("gmg::", "").replace("unsigned short", "bf16")
+
+
+def pmc_traffic(fetch_dir, write_dir, n=513):
+    """HBM bytes per finest-level launch from rocprofv3 FETCH_SIZE and WRITE_SIZE
+    runs (KiB per dispatch), each scaled so that the plain calibration copy reads
+    and writes exactly COPY_BYTES.  Only level-0 dispatches count: within one
+    kernel name, those with at least half the largest reading.  Host only;
+    prints a markdown report that `traffic_for` reads back."""
+    import csv
+    import glob
+    from collections import defaultdict
+    n_unk = (n - 2) ** 3
+    vals = {}
+    for d, counter in ((fetch_dir, "FETCH_SIZE"), (write_dir, "WRITE_SIZE")):
+        per = defaultdict(list)
+        for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(path)):
+                if r["Counter_Name"] == counter:
+                    per[_short(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+        vals[counter] = per
+    scale = {}
+    for c in ("FETCH_SIZE", "WRITE_SIZE"):
+        cp = vals[c]["k_copy_flat"]
+        scale[c] = COPY_BYTES / (1024.0 * sum(cp) / len(cp))
+    lines = [f"source_digest: {source_digest()}",
+             f"calibration: k_copy_flat of {COPY_BYTES} bytes; FETCH_SIZE x {scale['FETCH_SIZE']:.4f}, "
+             f"WRITE_SIZE x {scale['WRITE_SIZE']:.4f}", "",
+             "| class | kernel | level-0 dispatches | read GB | written GB | traffic GB | algorithmic GB | ratio |",
+             "|---|---|---:|---:|---:|---:|---:|---:|"]
+    figures = []
+    for cls, name in CLASS_KERNELS.items():
+        out = []
+        for c in ("FETCH_SIZE", "WRITE_SIZE"):
+            v = vals[c].get(name, [])
+            if not v:
+                break
+            top = max(v)
+            sel = [x for x in v if x >= 0.5 * top]
+            out.append((len(sel), 1024.0 * scale[c] * sum(sel) / len(sel)))
+        if len(out) != 2:
+            continue
+        rd, wr = out[0][1], out[1][1]
+        alg = BYTES_PER_POINT["mixed"][cls] * n_unk
+        lines.append(f"| {cls} | `{name}` | {out[0][0]} | {rd / 1e9:.3f} | {wr / 1e9:.3f} | {(rd + wr) / 1e9:.3f} | "
+                     f"{alg / 1e9:.3f} | {(rd + wr) / alg:.3f} |")
+        figures.append(f"traffic_bytes {cls}: {rd + wr:.6e}")
+    print("\n".join(lines + [""] + figures))
+
+
+def traffic_for(cls):
+    """Counter-measured HBM bytes per launch of `cls`, or None when no figure was
+    taken or the sources have changed since it was."""
+    try:
+        txt = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    if f"source_digest: {source_digest()}" not in txt:
+        return None
+    for line in txt.splitlines():
+        if line.startswith(f"traffic_bytes {cls}:"):
+            return float(line.split(":")[1])
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -243,11 +335,17 @@ def main():
                     help="with --sweep: also time truncated hierarchies with these level counts")
     ap.add_argument("--profile-summary", metavar="DIR",
                     help="print a markdown summary of a rocprofv3 CSV output folder and exit (host only)")
+    ap.add_argument("--pmc-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="print HBM traffic per finest-level launch from rocprofv3 FETCH_SIZE / WRITE_SIZE "
+                         "folders and exit (host only)")
     ap.add_argument("--galerkin", type=int, nargs="*", default=[],
                     help="with --sweep: also time Galerkin coarse operators from these first levels")
     args = ap.parse_args()
     if args.profile_summary:
         profile_summary(args.profile_summary)
+        return
+    if args.pmc_traffic:
+        pmc_traffic(*args.pmc_traffic)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1).", flush=True)
@@ -329,7 +427,7 @@ def main():
                    "unknowns": n_unk, "switch_n": args.switch_n, "rtol": args.rtol,
                    "step": "setup + mixed PCG solve + adjoint gradient"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(dom),
                      "bytes_per_launch": bytes_per_launch, "avg_ms": cands[dom]["avg_ms"],
                      "copy_GBs": copy_gbs},
         "forward": {"iterations": mixed["forward"]["iterations"], "rel_res_true": mixed["forward"]["rel_res_true"],

@@ -205,8 +205,9 @@ gmg_status gmg_profile_stop(gmg_handle *h);   /* stop recording, wait for the st
 gmg_status gmg_profile_get(gmg_handle *h, int32_t kclass, int32_t *launches, double *total_ms);
 const char *gmg_kernel_class_name(int32_t kclass);
 
-/* Plain device-to-device copy of `bytes` (a multiple of 16) with a simple
- * streaming kernel on `stream`; returns after it completes.  Used to calibrate
+/* Plain device-to-device copy of `bytes` (a multiple of 16, at most 2^35) with a
+ * streaming kernel (one 16-byte element per thread) on `stream`; returns after
+ * it completes; GMG_ERR_ARG for null pointers or an invalid size.  Used to calibrate
  * the profiler's HBM byte counters and to measure achievable copy bandwidth. */
 gmg_status gmg_calibration_copy(void *dst, const void *src, uint64_t bytes, void *stream);
 

@@ -38,7 +38,8 @@ struct LevelHost {
     double *a64 = nullptr;      // its 27 coefficient arrays (FP64, padded layout)
     void *av = nullptr;         // the same in the V-cycle type (== a64 in FP64 mode)
     Tiling til{};    // V-cycle stencil kernels
-    Tiling til64{};  // FP64 outer operator (apply, residual)
+    Tiling til64{};  // FP64 outer operator (residual)
+    Tiling til2{};   // FP64 outer apply, two points per lane
     gmg::Rows rows{};
 };
 
@@ -50,6 +51,7 @@ struct gmg_handle {
     int L = 0;
     LevelHost lv[gmg::MAX_LEVELS];
     double *F = nullptr, *X = nullptr, *R = nullptr, *P = nullptr, *Q = nullptr;
+    float *P32 = nullptr;  // MIXED: the search direction, stored in FP32
     double *partial = nullptr;
     int npartial = 0;
     PcgState *st = nullptr;       // device
@@ -108,23 +110,27 @@ int round_up(int a, int b) { return (a + b - 1) / b * b; }
 unsigned blocks_for(long long n, int nt) { return (unsigned)((n + nt - 1) / nt); }
 
 // Workgroup-count targets of the z-marching stencil kernels (the z-chunk
-// length follows from them).  Measured on MI355X at 513^3: FP32/BF16 sweeps
-// stream best with one chunk per column (about 1024 workgroups, all resident
-// and advancing through z together); FP64 sweeps with short chunks.
+// length follows from them, at least kMinChunk planes).  Measured on MI355X at
+// 513^3: FP32/BF16 sweeps stream as well with one chunk per column (about 1024
+// workgroups, all resident and advancing through z together) as with 8-plane
+// chunks; FP64 sweeps best with 8-plane chunks.
 int env_int(const char *name, int dflt) {
     const char *e = getenv(name);
     const int v = e ? atoi(e) : 0;
     return v > 0 ? v : dflt;
 }
 
-Tiling make_tiling(int n, int target) {
+constexpr int kMinChunk = 8;
+
+// width: x extent of a tile (TX, or TX2 for the two-points-per-lane apply)
+Tiling make_tiling(int n, int target, int width = gmg::TX) {
     Tiling t;
-    t.tiles_x = (n - 2) / gmg::TX + 1;  // covers i = 0 .. n-2
+    t.tiles_x = (n - 2) / width + 1;  // covers i = 0 .. n-2
     t.tiles_y = (n - 2 + gmg::TY - 1) / gmg::TY;
     const int planes = n - 2;
     int nch = (target + t.tiles_x * t.tiles_y - 1) / (t.tiles_x * t.tiles_y);
+    if (nch > planes / kMinChunk) nch = planes / kMinChunk;
     if (nch < 1) nch = 1;
-    if (nch > planes) nch = planes;
     t.zchunk = (planes + nch - 1) / nch;
     nch = (planes + t.zchunk - 1) / t.zchunk;
     t.nblocks = t.tiles_x * t.tiles_y * nch;
@@ -589,11 +595,11 @@ gmg_status pcg_start(gmg_handle *h) {
     STCHK(finalize(h, np, gmg::ST_RHO0));
     Prof pf(h, GMG_K_UPDATE_P, true);
     if (mixed(h))
-        gmg::k_update_p<float><<<h->lv[0].rows.nblocks, gmg::NT_FLAT, 0, h->stream>>>(h->lv[0].rows, h->P,
-                                                                              (const float *)h->lv[0].x, h->st);
+        gmg::k_update_p<float, float><<<h->lv[0].rows.nblocks, gmg::NT_FLAT, 0, h->stream>>>(
+            h->lv[0].rows, h->P32, (const float *)h->lv[0].x, h->st);
     else
-        gmg::k_update_p<double><<<h->lv[0].rows.nblocks, gmg::NT_FLAT, 0, h->stream>>>(h->lv[0].rows, h->P,
-                                                                               (const double *)h->lv[0].x, h->st);
+        gmg::k_update_p<double, double><<<h->lv[0].rows.nblocks, gmg::NT_FLAT, 0, h->stream>>>(
+            h->lv[0].rows, h->P, (const double *)h->lv[0].x, h->st);
     LAUNCHCHK();
     gmg::k_clear_restart<<<1, 64, 0, h->stream>>>(h->st);
     LAUNCHCHK();
@@ -609,11 +615,15 @@ gmg_status pcg_iteration(gmg_handle *h) {
     const bool mx = mixed(h);
     {
         Prof pf(h, GMG_K_APPLY_DOT, true);
-        gmg::k_apply<double, double, true><<<l0.til64.nblocks, gmg::NT, 0, h->stream>>>(
-            view<double, double>(l0), l0.til64, h->P, h->Q, h->partial, skip);
+        if (mx)
+            gmg::k_apply_x2<true, float><<<l0.til2.nblocks, gmg::NT, 0, h->stream>>>(
+                view<double, double>(l0), l0.til2, h->P32, h->Q, h->partial, skip);
+        else
+            gmg::k_apply_x2<true, double><<<l0.til2.nblocks, gmg::NT, 0, h->stream>>>(
+                view<double, double>(l0), l0.til2, h->P, h->Q, h->partial, skip);
         LAUNCHCHK();
     }
-    STCHK(finalize(h, l0.til64.nblocks, gmg::ST_ALPHA));
+    STCHK(finalize(h, l0.til2.nblocks, gmg::ST_ALPHA));
     {
         Prof pf(h, GMG_K_UPDATE_R, true);
         if (mx)
@@ -631,11 +641,11 @@ gmg_status pcg_iteration(gmg_handle *h) {
     {
         Prof pf(h, GMG_K_UPDATE_XP, true);
         if (mx)
-            gmg::k_update_xp<float><<<l0.rows.nblocks, gmg::NT_FLAT, 0, h->stream>>>(l0.rows, h->X, h->P,
-                                                                                  (const float *)l0.x, h->st);
+            gmg::k_update_xp<float, float><<<l0.rows.nblocks, gmg::NT_FLAT, 0, h->stream>>>(
+                l0.rows, h->X, h->P32, (const float *)l0.x, h->st);
         else
-            gmg::k_update_xp<double><<<l0.rows.nblocks, gmg::NT_FLAT, 0, h->stream>>>(l0.rows, h->X, h->P,
-                                                                                   (const double *)l0.x, h->st);
+            gmg::k_update_xp<double, double><<<l0.rows.nblocks, gmg::NT_FLAT, 0, h->stream>>>(
+                l0.rows, h->X, h->P, (const double *)l0.x, h->st);
         LAUNCHCHK();
     }
     gmg::k_clear_pending<<<1, 64, 0, h->stream>>>(h->st);
@@ -1015,9 +1025,10 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
         lh.plane = (long long)n * lh.pitch;
         lh.nel = (long long)n * lh.plane;
         lh.s = (double)(n - 1) * (double)(n - 1);
-        const int t64 = env_int("GMG_TARGET_WGS_64", 16384);
+        const int t64 = env_int("GMG_TARGET_WGS_64", 1 << 20);
         lh.til = make_tiling(n, mx ? env_int("GMG_TARGET_WGS_V", 1024) : t64);
         lh.til64 = make_tiling(n, t64);
+        lh.til2 = make_tiling(n, t64, gmg::TX2);
         lh.rows = make_rows(n, lh.pitch, lh.plane);
         lh.g27 = o.galerkin > 0 && l >= o.galerkin;
         n = (n - 1) / 2 + 1;
@@ -1052,9 +1063,13 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
     ALLOC(h->F, l0.nel);
     ALLOC(h->X, l0.nel);
     ALLOC(h->R, l0.nel);
-    ALLOC(h->P, l0.nel);
+    if (mx)
+        ALLOC(h->P32, l0.nel);
+    else
+        ALLOC(h->P, l0.nel);
     ALLOC(h->Q, l0.nel);
-    h->npartial = std::max(std::max(l0.til.nblocks, l0.til64.nblocks), std::max(l0.rows.nblocks, gmg::NB_FLAT));
+    h->npartial = std::max(std::max(std::max(l0.til.nblocks, l0.til64.nblocks), l0.til2.nblocks),
+                           std::max(l0.rows.nblocks, gmg::NB_FLAT));
     {
         const long long nfaces_blocks = blocks_for((long long)l0.n * l0.n * l0.n, 256);
         if (nfaces_blocks > h->npartial) h->npartial = (int)nfaces_blocks;
@@ -1347,9 +1362,10 @@ gmg_status gmg_apply_operator(gmg_handle *h, int32_t level, int32_t use_fp64, co
     if (use_fp64) {
         if (level != 0) return fail(h, GMG_ERR_ARG, "the FP64 outer operator exists on level 0 only");
         LevelHost &l0 = h->lv[0];
-        STCHK(in_vec<double>(h, l0, x, h->P));
-        gmg::k_apply<double, double, false><<<l0.til64.nblocks, gmg::NT, 0, h->stream>>>(
-            view<double, double>(l0), l0.til64, h->P, h->Q, nullptr, nullptr);
+        double *u = h->X;  // free between solves (every solve re-initializes it)
+        STCHK(in_vec<double>(h, l0, x, u));
+        gmg::k_apply_x2<false, double><<<l0.til2.nblocks, gmg::NT, 0, h->stream>>>(view<double, double>(l0), l0.til2,
+                                                                                  u, h->Q, nullptr, nullptr);
         LAUNCHCHK();
         return out_vec<double>(h, l0, h->Q, y);
     }
@@ -1470,8 +1486,10 @@ const char *gmg_kernel_class_name(int32_t c) {
 extern "C" gmg_status gmg_calibration_copy(void *dst, const void *src, uint64_t bytes, void *stream) {
     if (!dst || !src || (bytes % 16) != 0) return GMG_ERR_ARG;
     const long long n16 = (long long)(bytes / 16);
-    const int nb = (int)std::min<long long>((n16 + 255) / 256, 1 << 16);
-    gmg::k_copy<<<nb > 0 ? nb : 1, 256, 0, (hipStream_t)stream>>>(n16, (const uint4 *)src, (uint4 *)dst);
+    const long long nb = (n16 + 255) / 256;
+    if (nb > 0x7fffffffLL) return GMG_ERR_ARG;
+    gmg::k_copy_flat<<<(unsigned)(nb > 0 ? nb : 1), 256, 0, (hipStream_t)stream>>>(n16, (const uint4 *)src,
+                                                                                   (uint4 *)dst);
     if (hipGetLastError() != hipSuccess) return GMG_ERR_HIP;
     if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return GMG_ERR_HIP;
     return GMG_OK;

@@ -27,6 +27,7 @@ typedef uint16_t bf16;
 constexpr int TX = 64;          // threads along x in a stencil tile (one wave64 row)
 constexpr int TY = 4;           // rows per tile
 constexpr int NT = TX * TY;     // threads per stencil workgroup
+constexpr int TX2 = 2 * TX;     // x extent of a tile of the two-points-per-lane apply
 constexpr int NT_FLAT = 256;    // threads per workgroup of the flat vector kernels
 constexpr int NB_FLAT = 2048;   // workgroups of the flat vector kernels (fixed => deterministic sums)
 constexpr int NT_PERSIST = 1024;
@@ -229,15 +230,12 @@ __device__ __forceinline__ double block_sum(double v) {
 }
 
 // ---------------------------------------------------------------- tiling
-// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b on XCD
-// b % 8).  Give every XCD a contiguous range of tiles so that neighbouring
-// tiles, which share halo rows, share that XCD's L2.
-__device__ __forceinline__ int xcd_tile(int b, int nb) {
-    const int per = nb >> 3;
-    if (b < (per << 3)) return (b & 7) * per + (b >> 3);
-    return b;
-}
-
+// Workgroup b takes tile b in x-fastest order.  Dispatch is round-robin over
+// the 8 XCDs, so tiles that are neighbours in y (tiles_x apart, a multiple of
+// 8 on the large levels) share an XCD and its L2, and all XCDs stream the same
+// band of planes at any moment.  Giving each XCD a contiguous slab of tiles
+// instead was measured 5-11% slower on MI355X (eight far-apart streams per
+// array).
 struct Column {
     int i, j, k0, k1;
     bool active;
@@ -245,7 +243,7 @@ struct Column {
 // tile -> (x tile, y tile, z chunk), x fastest; a thread owns the column
 // (i, j) for planes k0..k1-1.  x tiles start at i = 0 so rows stay aligned.
 __device__ __forceinline__ Column tile_column(int n, const Tiling &t) {
-    int b = xcd_tile(blockIdx.x, t.nblocks);
+    int b = blockIdx.x;
     const int tx = b % t.tiles_x;
     b /= t.tiles_x;
     const int ty = b % t.tiles_y;
@@ -263,9 +261,11 @@ __device__ __forceinline__ Column tile_column(int n, const Tiling &t) {
 // Each thread marches its column in z, keeping u(k-1), u(k) and the lower
 // z-link in registers; x/y neighbours come through the L1/L2 caches.
 
-// y = A u ;  DOT: partial[wg] = sum u . (A u)   (PCG p.Ap)
-template <typename V, typename K, bool DOT>
-__global__ __launch_bounds__(NT) void k_apply(Lev<V, K> L, Tiling t, const V *__restrict__ u,
+// y = A u ;  DOT: partial[wg] = sum u . (A u)   (PCG p.Ap).  u may be stored
+// narrower than V (the FP32 search direction of the MIXED solve): its values
+// are widened exactly before the arithmetic.
+template <typename V, typename K, bool DOT, typename U = V>
+__global__ __launch_bounds__(NT) void k_apply(Lev<V, K> L, Tiling t, const U *__restrict__ u,
                                               V *__restrict__ y, double *__restrict__ partial,
                                               const int *__restrict__ skip) {
     if (skip && *skip) return;
@@ -275,11 +275,11 @@ __global__ __launch_bounds__(NT) void k_apply(Lev<V, K> L, Tiling t, const V *__
         const int pitch = L.pitch;
         const long long plane = L.plane;
         long long o = (long long)c.k0 * plane + (long long)c.j * pitch + c.i;
-        V ub = u[o - plane], up = u[o];
+        V ub = (V)u[o - plane], up = (V)u[o];
         V kb = kval(L.kz[o - plane]);
         for (int k = c.k0; k < c.k1; ++k, o += plane) {
-            const V ut = u[o + plane];
-            const V uw = u[o - 1], ue = u[o + 1], us = u[o - pitch], un = u[o + pitch];
+            const V ut = (V)u[o + plane];
+            const V uw = (V)u[o - 1], ue = (V)u[o + 1], us = (V)u[o - pitch], un = (V)u[o + pitch];
             const V kw = kval(L.kx[o - 1]), ke = kval(ldnt(&L.kx[o])), ks = kval(L.ky[o - pitch]),
                     kn = kval(L.ky[o]), kt = kval(ldnt(&L.kz[o]));
             const V r = apply7(up, uw, ue, us, un, ub, ut, kw, ke, ks, kn, kb, kt, L.s);
@@ -293,6 +293,64 @@ __global__ __launch_bounds__(NT) void k_apply(Lev<V, K> L, Tiling t, const V *__
     if (DOT) {
         const double s = block_sum<NT>(dot);
         if (threadIdx.x == 0) partial[blockIdx.x] = s;
+    }
+}
+
+// The outer FP64 operator with two x points per lane: a tile is 128 x 4
+// points of a z-chunk, u and the links are read as pairs (8- and 16-byte
+// loads), the west/east values at the pair's ends singly.  Per point the
+// arithmetic is that of k_apply; the dot adds the pair's two terms in x order.
+// Lanes whose two points are both outside the interior load nothing.
+template <bool DOT, typename U>
+__global__ __launch_bounds__(NT) void k_apply_x2(Lev<double, double> L, Tiling t, const U *__restrict__ u,
+                                                 double *__restrict__ y, double *__restrict__ partial,
+                                                 const int *__restrict__ skip) {
+    if (skip && *skip) return;
+    typedef typename Vec2<U>::type U2;
+    int b = blockIdx.x;
+    const int tx = b % t.tiles_x;
+    b /= t.tiles_x;
+    const int ty = b % t.tiles_y;
+    const int cz = b / t.tiles_y;
+    const int i0 = tx * TX2 + 2 * (int)(threadIdx.x & (TX - 1));
+    const int j = 1 + ty * TY + (int)(threadIdx.x >> 6);
+    const int k0 = 1 + cz * t.zchunk, k1 = min(k0 + t.zchunk, L.n - 1);
+    const bool a0 = i0 >= 1 && i0 <= L.n - 2, a1 = i0 + 1 <= L.n - 2;
+    double dot = 0.0;
+    if ((a0 || a1) && j <= L.n - 2 && k0 < k1) {
+        const int pitch = L.pitch;
+        const long long plane = L.plane;
+        const double s = L.s;
+        long long o = (long long)k0 * plane + (long long)j * pitch + i0;
+        U2 ub = *(const U2 *)(u + o - plane), up = *(const U2 *)(u + o);
+        double2 kb = *(const double2 *)(L.kz + o - plane);
+        for (int k = k0; k < k1; ++k, o += plane) {
+            const U2 ut = *(const U2 *)(u + o + plane);
+            const U2 us = *(const U2 *)(u + o - pitch), un = *(const U2 *)(u + o + pitch);
+            const double uw = (double)u[o - 1], ue = (double)u[o + 2];
+            const double kw = L.kx[o - 1];
+            const double2 ke = ldnt((const double2 *)(L.kx + o)), kt = ldnt((const double2 *)(L.kz + o));
+            const double2 ks = *(const double2 *)(L.ky + o - pitch), kn = *(const double2 *)(L.ky + o);
+            const double p0 = (double)up.x, p1 = (double)up.y;
+            double r0 = apply7(p0, uw, p1, (double)us.x, (double)un.x, (double)ub.x, (double)ut.x, kw, ke.x, ks.x,
+                               kn.x, kb.x, kt.x, s);
+            double r1 = apply7(p1, p0, ue, (double)us.y, (double)un.y, (double)ub.y, (double)ut.y, ke.x, ke.y, ks.y,
+                               kn.y, kb.y, kt.y, s);
+            if (!a0) r0 = 0.0;
+            if (!a1) r1 = 0.0;
+            stnt(make_double2(r0, r1), (double2 *)(y + o));
+            if (DOT) {
+                dot = fmaT(p0, r0, dot);
+                dot = fmaT(p1, r1, dot);
+            }
+            ub = up;
+            up = ut;
+            kb = kt;
+        }
+    }
+    if (DOT) {
+        const double sum = block_sum<NT>(dot);
+        if (threadIdx.x == 0) partial[blockIdx.x] = sum;
     }
 }
 
@@ -348,20 +406,14 @@ __global__ __launch_bounds__(NT) void k_cheb_first(Lev<V, K> L, Tiling t, const 
 // evaluated on the fly at the seven stencil points (it is pointwise), and
 //   x2 = x1 + c1 x1 + c2 D^-1 (b - A x1).
 // Same values as k_cheb_first followed by the PM = 1 step.  WX1 also stores
-// x1 (needed as the previous iterate when the degree exceeds 2).  Each lane
-// evaluates x1 of its own column for planes k-1..k+1 and takes its x
-// neighbours from the adjacent lanes; only the two edge lanes of a wave
-// evaluate an outside neighbour.  Lanes outside the interior stay alive
-// (their b and D^-1 are the stored zeros) so the shuffles see every lane.
+// x1 (needed as the previous iterate when the degree exceeds 2).
 template <typename V, typename K, bool WX1>
 __global__ __launch_bounds__(NT) void k_cheb_pre2(Lev<V, K> L, Tiling t, const V *__restrict__ b,
                                                   V *__restrict__ out, V *__restrict__ x1out, V c0, V c1, V c2,
                                                   const int *__restrict__ skip) {
     if (skip && *skip) return;
     const Column col = tile_column(L.n, t);
-    if (col.j > L.n - 2 || col.k0 >= col.k1) return;  // uniform over the wave
-    const bool act = col.i >= 1 && col.i <= L.n - 2;
-    const int lane = threadIdx.x & (TX - 1);
+    if (!col.active) return;
     const int pitch = L.pitch;
     const long long plane = L.plane;
     const V *__restrict__ dv = L.dinv;
@@ -373,19 +425,15 @@ __global__ __launch_bounds__(NT) void k_cheb_pre2(Lev<V, K> L, Tiling t, const V
     for (int k = col.k0; k < col.k1; ++k, o += plane) {
         const V bt = b[o + plane];
         const V ut = cheb_first_val(bt, dv[o + plane], c0);
-        V uw = __shfl_up(up, 1, TX), ue = __shfl_down(up, 1, TX);
-        if (lane == 0) uw = cheb_first_val(b[o - 1], dv[o - 1], c0);
-        if (lane == TX - 1) ue = cheb_first_val(b[o + 1], dv[o + 1], c0);
+        const V uw = cheb_first_val(b[o - 1], dv[o - 1], c0), ue = cheb_first_val(b[o + 1], dv[o + 1], c0);
         const V us = cheb_first_val(b[o - pitch], dv[o - pitch], c0),
                 un = cheb_first_val(b[o + pitch], dv[o + pitch], c0);
         const V kw = kval(L.kx[o - 1]), ke = kval(ldnt(&L.kx[o])), ks = kval(L.ky[o - pitch]), kn = kval(L.ky[o]),
                 kt = kval(ldnt(&L.kz[o]));
-        if (act) {
-            const V ax = apply7(up, uw, ue, us, un, ub, ut, kw, ke, ks, kn, kb, kt, L.s);
-            const V d = diag7(kw, ke, ks, kn, kb, kt, L.s);
-            stnt(cheb_step_val(up, up, bp, ax, d, c1, c2), &out[o]);
-            if (WX1) stnt(up, &x1out[o]);
-        }
+        const V ax = apply7(up, uw, ue, us, un, ub, ut, kw, ke, ks, kn, kb, kt, L.s);
+        const V d = diag7(kw, ke, ks, kn, kb, kt, L.s);
+        stnt(cheb_step_val(up, up, bp, ax, d, c1, c2), &out[o]);
+        if (WX1) stnt(up, &x1out[o]);
         ub = up;
         up = ut;
         bp = bt;
@@ -1059,25 +1107,30 @@ __global__ __launch_bounds__(NT_FLAT) void k_update_r(Rows R, double *__restrict
 
 // x += alpha p_old ; p = z + beta p_old (skipped once the loop has stopped,
 // when z is stale).  Runs only while this iteration's x update is pending,
-// so iterations enqueued after the stop change nothing.
-template <typename Z>
-__global__ __launch_bounds__(NT_FLAT) void k_update_xp(Rows R, double *__restrict__ x, double *__restrict__ p,
+// so iterations enqueued after the stop change nothing.  p is FP64 or (MIXED)
+// FP32: the new direction is formed in FP64 and rounded once.
+template <typename Z, typename PT>
+__global__ __launch_bounds__(NT_FLAT) void k_update_xp(Rows R, double *__restrict__ x, PT *__restrict__ p,
                                                        const Z *__restrict__ z, const PcgState *__restrict__ st) {
     if (!st->x_pending) return;
     const double a = st->alpha;
     const bool upd_p = !st->done;
     const double bta = st->beta;
     typedef typename Vec2<Z>::type Z2;
+    typedef typename Vec2<PT>::type P2;
     long long e;
     if (row_item(R, e)) {
-        const double2 pv = *(const double2 *)(p + e);
+        const P2 pv = *(const P2 *)(p + e);
         double2 xv = *(const double2 *)(x + e);
-        xv.x = fmaT(a, pv.x, xv.x);
-        xv.y = fmaT(a, pv.y, xv.y);
+        xv.x = fmaT(a, (double)pv.x, xv.x);
+        xv.y = fmaT(a, (double)pv.y, xv.y);
         *(double2 *)(x + e) = xv;
         if (upd_p) {
             const Z2 zv = *(const Z2 *)(z + e);
-            *(double2 *)(p + e) = make_double2(fmaT(bta, pv.x, (double)zv.x), fmaT(bta, pv.y, (double)zv.y));
+            P2 pn;
+            pn.x = (PT)fmaT(bta, (double)pv.x, (double)zv.x);
+            pn.y = (PT)fmaT(bta, (double)pv.y, (double)zv.y);
+            *(P2 *)(p + e) = pn;
         }
     }
 }
@@ -1086,27 +1139,27 @@ __global__ void k_clear_pending(PcgState *st) {
     if (threadIdx.x == 0) st->x_pending = 0;
 }
 
-// p = z + beta p   (z FP64 or FP32)
-template <typename Z>
-__global__ __launch_bounds__(NT_FLAT) void k_update_p(Rows R, double *__restrict__ p, const Z *__restrict__ z,
+// p = z + beta p   (z FP64 or FP32; p FP64 or, MIXED, FP32)
+template <typename Z, typename PT>
+__global__ __launch_bounds__(NT_FLAT) void k_update_p(Rows R, PT *__restrict__ p, const Z *__restrict__ z,
                                                       const PcgState *__restrict__ st) {
     if (st->done) return;
     const double bta = st->restart ? 0.0 : st->beta;
     typedef typename Vec2<Z>::type Z2;
+    typedef typename Vec2<PT>::type P2;
+    long long e;
+    if (!row_item(R, e)) return;
+    const Z2 zv = *(const Z2 *)(z + e);
+    P2 pn;
     if (bta == 0.0) {
-        long long e;
-        if (row_item(R, e)) {
-            const Z2 zv = *(const Z2 *)(z + e);
-            *(double2 *)(p + e) = make_double2((double)zv.x, (double)zv.y);
-        }
+        pn.x = (PT)zv.x;
+        pn.y = (PT)zv.y;
     } else {
-        long long e;
-        if (row_item(R, e)) {
-            const Z2 zv = *(const Z2 *)(z + e);
-            const double2 pv = *(const double2 *)(p + e);
-            *(double2 *)(p + e) = make_double2(fmaT(bta, pv.x, (double)zv.x), fmaT(bta, pv.y, (double)zv.y));
-        }
+        const P2 pv = *(const P2 *)(p + e);
+        pn.x = (PT)fmaT(bta, (double)pv.x, (double)zv.x);
+        pn.y = (PT)fmaT(bta, (double)pv.y, (double)zv.y);
     }
+    *(P2 *)(p + e) = pn;
 }
 
 // partial = sum a.b over the interior rows  (b FP64 or FP32)
@@ -1127,10 +1180,11 @@ __global__ __launch_bounds__(NT_FLAT) void k_dot(Rows R, const double *__restric
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-// Plain device copy (bandwidth calibration of the profiler counters).
-__global__ __launch_bounds__(256) void k_copy(long long n16, const uint4 *__restrict__ src, uint4 *__restrict__ dst) {
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n16; e += stride) dst[e] = src[e];
+// Plain streaming copy for counter calibration: one 16-byte element per thread.
+__global__ __launch_bounds__(256) void k_copy_flat(long long n16, const uint4 *__restrict__ src,
+                                                   uint4 *__restrict__ dst) {
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n16) dst[e] = src[e];
 }
 
 // ---------------------------------------------------------------- inexact coarse CG
@@ -1221,6 +1275,20 @@ enum Stage {
 
 // Sum `count` partials in a fixed order and advance the PCG state.
 constexpr int NT_FIN = 1024;
+// This thread's share of count partial sums (elements threadIdx.x + m*NT_FIN),
+// eight loads in flight at a time, added in a fixed order.
+__device__ __forceinline__ double fin_thread_sum(const double *__restrict__ p, int count) {
+    double acc = 0.0;
+    int w = threadIdx.x;
+    for (; w + 7 * NT_FIN < count; w += 8 * NT_FIN) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = p[w + u * NT_FIN];
+        acc += ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+    }
+    for (; w < count; w += NT_FIN) acc += p[w];
+    return acc;
+}
 __global__ __launch_bounds__(NT_FIN) void k_finalize(const double *__restrict__ partial, int count, int stage,
                                                      PcgState *__restrict__ st) {
     if ((stage == ST_ALPHA || stage == ST_RR || stage == ST_BETA || stage == ST_BETA_FLEX || stage == ST_C_INIT ||
@@ -1228,15 +1296,8 @@ __global__ __launch_bounds__(NT_FIN) void k_finalize(const double *__restrict__ 
         st->done)
         return;
     const bool two = stage == ST_BETA_FLEX || stage == ST_C_INIT || stage == ST_C_RR;
-    double acc = 0.0;
-    for (int w = threadIdx.x; w < count; w += NT_FIN) acc += partial[w];
-    const double sum = block_sum<NT_FIN>(acc);
-    double sum2 = 0.0;
-    if (two) {
-        double acc2 = 0.0;
-        for (int w = threadIdx.x; w < count; w += NT_FIN) acc2 += partial[count + w];
-        sum2 = block_sum<NT_FIN>(acc2);
-    }
+    const double sum = block_sum<NT_FIN>(fin_thread_sum(partial, count));
+    const double sum2 = two ? block_sum<NT_FIN>(fin_thread_sum(partial + count, count)) : 0.0;
     if (threadIdx.x != 0) return;
     switch (stage) {
     case ST_BETA_FLEX:  // beta = z_{k+1}.(r_{k+1} - r_k) / rho_k = -alpha (q.z) / rho

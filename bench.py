@@ -59,8 +59,15 @@ def log(*a):
 
 
 def make_inputs(w):
+    """Seeded inputs of a workload: numpy arrays, or (log-normal fields at 1025^3
+    and up, too slow to filter on the host) torch tensors drawn on the GPU by
+    the same recipe."""
     from paper_1604_07163_amd import inputs
     n = w["n"]
+    if w["kind"] != "inclusions" and n >= 1025:
+        k = inputs.lognormal_k_gpu(n, w["k_seed"], clip=w["clip"])
+        kobs = inputs.lognormal_k_gpu(n, w["kobs_seed"], clip=w["clip"])
+        return k, kobs, inputs.uniform_rhs_gpu(n, w["f_seed"])
     if w["kind"] == "inclusions":
         kx, ky, kz, _ = inputs.inclusion_k(n, w["k_seed"])
         kox, koy, koz, _ = inputs.inclusion_k(n, w["kobs_seed"])
@@ -69,6 +76,16 @@ def make_inputs(w):
         kox, koy, koz = inputs.lognormal_k(n, w["kobs_seed"], clip=w["clip"])
     f = inputs.uniform_rhs(n, w["f_seed"])
     return (kx, ky, kz), (kox, koy, koz), f
+
+
+def _dev(a):
+    import torch
+    return a if torch.is_tensor(a) else torch.from_numpy(a).cuda()
+
+
+def _host(a):
+    import torch
+    return a.cpu().numpy() if torch.is_tensor(a) else a
 
 
 def run_steps(solver, k, f, phi_obs, steps, rtol, profile=False):
@@ -140,9 +157,9 @@ def sweep(args):
     from paper_1604_07163_amd import gmg
     w = WORKLOADS[args.workload]
     n, levels = w["n"], w["levels"]
-    k_np, _, f_np = make_inputs(w)
-    k = [torch.from_numpy(a).cuda() for a in k_np]
-    f = torch.from_numpy(f_np).cuda()
+    k_in, _, f_in = make_inputs(w)
+    k = [_dev(a) for a in k_in]
+    f = _dev(f_in)
     rows = []
     sizes = [0] + [s for s in (65, 33, 17, 9) if s < n]
     configs = [dict(precision=p, switch_n=sw, persistent_wgs=1) for p in ("fp64", "mixed") for sw in sizes]
@@ -363,11 +380,12 @@ def main():
     n, levels = w["n"], w["levels"]
     n_unk = (n - 2) ** 3
     t0 = time.perf_counter()
-    k_np, kobs_np, f_np = make_inputs(w)
+    k_in, kobs_in, f_in = make_inputs(w)
     log(f"inputs generated in {time.perf_counter() - t0:.1f}s")
-    k = [torch.from_numpy(a).cuda() for a in k_np]
-    kobs = [torch.from_numpy(a).cuda() for a in kobs_np]
-    f = torch.from_numpy(f_np).cuda()
+    k = [_dev(a) for a in k_in]
+    kobs = [_dev(a) for a in kobs_in]
+    f = _dev(f_in)
+    del kobs_in
 
     copy_gbs = copy_bandwidth()
     log(f"plain copy: {copy_gbs:.0f} GB/s")
@@ -448,7 +466,7 @@ def main():
     if not args.no_cpu_baseline:
         its = legs.get("fp64", mixed)["forward"]["iterations"]
         log("timing the CPU oracle sample ...")
-        out["cpu_baseline"] = cpu_baseline(w, k_np, f_np, its, iters=args.cpu_iters)
+        out["cpu_baseline"] = cpu_baseline(w, [_host(a) for a in k_in], _host(f_in), its, iters=args.cpu_iters)
     print(json.dumps(out), flush=True)
 
 

@@ -253,7 +253,8 @@ CLASS_KERNELS = {
     "restrict": "k_restrict<float>",
     "prolong": "k_prolong<float>",
 }
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_inclusions513.md")
+def traffic_file(workload):
+    return os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
 COPY_BYTES = 2 << 30  # copy_bandwidth(): bytes read (and written) per calibration copy
 
 
@@ -318,11 +319,11 @@ def pmc_traffic(fetch_dir, write_dir, n=513):
     print("\n".join(lines + [""] + figures))
 
 
-def traffic_for(cls):
-    """Counter-measured HBM bytes per launch of `cls`, or None when no figure was
-    taken or the sources have changed since it was."""
+def traffic_for(cls, workload):
+    """Counter-measured HBM bytes per launch of `cls` on `workload`, or None when
+    no figure was taken or the sources have changed since it was."""
     try:
-        txt = open(TRAFFIC_FILE).read()
+        txt = open(traffic_file(workload)).read()
     except OSError:
         return None
     if f"source_digest: {source_digest()}" not in txt:
@@ -445,7 +446,7 @@ def main():
                    "unknowns": n_unk, "switch_n": args.switch_n, "rtol": args.rtol,
                    "step": "setup + mixed PCG solve + adjoint gradient"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(dom),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(dom, args.workload),
                      "bytes_per_launch": bytes_per_launch, "avg_ms": cands[dom]["avg_ms"],
                      "copy_GBs": copy_gbs},
         "forward": {"iterations": mixed["forward"]["iterations"], "rel_res_true": mixed["forward"]["rel_res_true"],

@@ -170,6 +170,13 @@ gmg_status gmg_debug_vcycle(gmg_handle *h, const double *r, double *z);
 /* Copy level coefficients out in face shapes (MIXED: the BF16 values). */
 gmg_status gmg_get_level_coefficients(gmg_handle *h, int32_t level, double *kx, double *ky, double *kz);
 
+/* Chebyshev interval [*lo, *hi] of D^-1 A used by the smoother on `level`
+ * (host pointers).  The option interval on re-discretized levels; on a
+ * smoothed Galerkin level [1.1 lam cheb_lo/cheb_hi, 1.1 lam] with lam the
+ * largest Ritz value of 20 Lanczos steps on D^-1 A in the D inner product
+ * (the bound 2 of the 7-point operator does not hold for R A P). */
+gmg_status gmg_get_level_interval(gmg_handle *h, int32_t level, double *lo, double *hi);
+
 /* Galerkin operator of `level` (>= the handle's galerkin level; GMG_ERR_ARG
  * otherwise) in FP64, written to the device array a27 of N_l^3 * 27 doubles in
  * natural order: a27[((k*N + j)*N + i)*27 + (dz+1)*9 + (dy+1)*3 + (dx+1)] is

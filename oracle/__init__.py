@@ -70,6 +70,10 @@ def lib():
         L.or_create3.restype = I
         L.or_apply27_raw.argtypes = [I, P, P, P]
         L.or_galerkin_raw.argtypes = [I, P, P, P, P, I, P]
+        L.or_lanczos_max_raw.argtypes = [I, P, P, P, P, I, P]
+        L.or_lanczos_max_raw.restype = D
+        L.or_level_interval.argtypes = [P, I, ctypes.POINTER(D), ctypes.POINTER(D)]
+        L.or_level_interval.restype = I
         L.or_get_a27.argtypes = [P, I, P]
         L.or_get_a27.restype = I
         L.or_pcg2.argtypes = [P, P, P, D, I, I, ctypes.POINTER(I), ctypes.POINTER(D), ctypes.POINTER(D),
@@ -176,6 +180,16 @@ def apply27(a27, u):
     return out
 
 
+def lanczos_max(kx, ky, kz, a27=None, steps=20):
+    """Lanczos estimate of lambda_max(D^-1 A) for the 7-point operator of the links
+    (a27 None) or the 27-point operator a27 of shape (N,N,N,27)."""
+    kx, ky, kz = _f64(kx), _f64(ky), _f64(kz)
+    n = kx.shape[0]
+    a = None if a27 is None else _f64(a27)
+    work = np.empty(4 * n ** 3)
+    return lib().or_lanczos_max_raw(n, _p(kx), _p(ky), _p(kz), None if a is None else _p(a), steps, _p(work))
+
+
 def galerkin(kx, ky, kz, a27=None):
     """R A P (27-point, (Nc,Nc,Nc,27)) of the fine operator given by links or by a27."""
     kx, ky, kz = _f64(kx), _f64(ky), _f64(kz)
@@ -260,6 +274,13 @@ class Hierarchy:
         kx, ky, kz = np.empty(sx), np.empty(sy), np.empty(sz)
         lib().or_get_k(self._h, l, _p(kx), _p(ky), _p(kz))
         return kx, ky, kz
+
+    def level_interval(self, l):
+        """Chebyshev interval (lo, hi) of D^-1 A used on level l."""
+        lo, hi = ctypes.c_double(), ctypes.c_double()
+        if lib().or_level_interval(self._h, l, ctypes.byref(lo), ctypes.byref(hi)) != 0:
+            raise OracleError(1)
+        return lo.value, hi.value
 
     def level_a27(self, l):
         """27-point Galerkin operator of level l as an (N,N,N,27) array (index (dz+1)*9+(dy+1)*3+(dx+1))."""

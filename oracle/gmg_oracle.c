@@ -514,6 +514,107 @@ void or_chol_solve_raw(int m, const double *L, double *y)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Chebyshev interval of a Galerkin level.  The fixed bound 2 on the        */
+/* spectrum of D^-1 A holds for the 7-point M-matrix, not for R A P, whose  */
+/* rows mix signs.  On a Galerkin level the interval's upper end is 1.1     */
+/* times an estimate of lambda_max(D^-1 A): the largest eigenvalue of the   */
+/* tridiagonal matrix of OR_LANCZOS_STEPS Lanczos steps in the D inner      */
+/* product (D^-1 A is self-adjoint there), from the fixed start vector      */
+/* u0 = 1 + ((7i + 11j + 13k) mod 5) / 4 at interior vertices.  The lower   */
+/* end keeps the ratio lo/hi of the default interval.                      */
+/* ------------------------------------------------------------------------ */
+#define OR_LANCZOS_STEPS 20
+#define OR_LANCZOS_SAFETY 1.1
+
+/* largest eigenvalue of the symmetric tridiagonal matrix with diagonal a[0..m-1]
+ * and off-diagonal b[0..m-2], by bisection on the Sturm count */
+static double tridiag_max_eig(int m, const double *a, const double *b)
+{
+    double lo = a[0], hi = a[0];
+    for (int i = 0; i < m; i++) {
+        double r = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i + 1 < m ? fabs(b[i]) : 0.0);
+        if (a[i] - r < lo)
+            lo = a[i] - r;
+        if (a[i] + r > hi)
+            hi = a[i] + r;
+    }
+    for (int it = 0; it < 2000; it++) {
+        double mid = 0.5 * (lo + hi);
+        if (!(mid > lo && mid < hi))
+            break;
+        int below = 0; /* eigenvalues below mid = negative pivots of T - mid I */
+        double q = 1.0;
+        for (int i = 0; i < m; i++) {
+            q = a[i] - mid - (i > 0 ? b[i - 1] * b[i - 1] / q : 0.0);
+            if (q == 0.0)
+                q = -1e-300;
+            if (q < 0.0)
+                below++;
+        }
+        if (below == m)
+            hi = mid;
+        else
+            lo = mid;
+    }
+    return hi;
+}
+
+static double lanczos_max(const or_op *A, int steps, double *work)
+{
+    int n = A->n;
+    size_t nv = nvert(n);
+    double *v = work, *vp = work + nv, *w = work + 2 * nv, *dg = work + 3 * nv;
+    double al[64], be[64];
+    if (steps > 64)
+        steps = 64;
+    op_diag(A, dg);
+    for (int k = 0; k < n; k++)
+        for (int j = 0; j < n; j++)
+            for (int i = 0; i < n; i++)
+                v[vid(n, i, j, k)] = interior(n, i, j, k) ? 1.0 + 0.25 * ((7 * i + 11 * j + 13 * k) % 5) : 0.0;
+    double s = 0.0;
+    for (size_t p = 0; p < nv; p++)
+        s += v[p] * dg[p] * v[p];
+    s = sqrt(s);
+    for (size_t p = 0; p < nv; p++) {
+        v[p] /= s;
+        vp[p] = 0.0;
+    }
+    double beta = 0.0;
+    int m = 0;
+    for (int j = 0; j < steps; j++) {
+        op_apply(A, v, w);
+        double alpha = 0.0;
+        for (size_t p = 0; p < nv; p++)
+            alpha += v[p] * w[p];
+        for (size_t p = 0; p < nv; p++)
+            w[p] = dg[p] > 0.0 ? w[p] / dg[p] - alpha * v[p] - beta * vp[p] : 0.0;
+        double bn = 0.0;
+        for (size_t p = 0; p < nv; p++)
+            bn += w[p] * dg[p] * w[p];
+        bn = sqrt(bn);
+        al[m] = alpha;
+        be[m] = bn;
+        m++;
+        if (!(bn > 1e-14 * fabs(alpha)))
+            break; /* invariant subspace: T holds the exact eigenvalues */
+        for (size_t p = 0; p < nv; p++) {
+            vp[p] = v[p];
+            v[p] = w[p] / bn;
+        }
+        beta = bn;
+    }
+    return tridiag_max_eig(m, al, be);
+}
+
+double or_lanczos_max_raw(int n, const double *kx, const double *ky, const double *kz, const double *a27,
+                          int steps, double *work)
+{
+    or_op A = {n, kx, ky, kz, a27};
+    return lanczos_max(&A, steps, work);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Hierarchy (Sec. 2.1.1: per level an operator, a smoother, R and P; an    */
 /* exact solver on the coarsest level).  Coarsening factor 2 (Sec. 1):      */
 /* N_{l+1} = (N_l - 1)/2 + 1, coarse vertex I sits on fine vertex 2I.       */
@@ -522,6 +623,7 @@ typedef struct {
     int n;
     double *kx, *ky, *kz;
     double *a27;              /* Galerkin coarse operator (NULL: the 7-point link form) */
+    double lo, hi;            /* Chebyshev interval of D^-1 A on this level */
     double *x, *b, *r, *work; /* work: 4 vectors for the smoother */
 } or_level;
 
@@ -655,7 +757,19 @@ int or_create3(int n, int levels, int degree, double lo, double hi, int rule, in
                 or_galerkin_op(&Fo, nl, L->a27);
             }
         }
+        L->lo = lo;
+        L->hi = hi;
         nl = (nl - 1) / 2 + 1;
+    }
+    /* Chebyshev intervals of the smoothed Galerkin levels (the coarsest level is
+     * solved, not smoothed) */
+    for (int l = 1; l + 1 < levels; l++) {
+        or_level *L = &H->lv[l];
+        if (!L->a27)
+            continue;
+        or_op Ao = level_op(L);
+        L->hi = OR_LANCZOS_SAFETY * lanczos_max(&Ao, OR_LANCZOS_STEPS, L->work);
+        L->lo = L->hi * (lo / hi);
     }
     or_level *C = &H->lv[levels - 1];
     H->m = m;
@@ -799,7 +913,7 @@ static int vcycle_level(or_hier *H, int l)
         return or_coarse_solve(H, L->b, L->x);
     or_level *C = &H->lv[l + 1];
     or_op A = level_op(L);
-    cheb_op(&A, H->degree, H->lo, H->hi, L->b, L->x, 1, L->work);
+    cheb_op(&A, H->degree, L->lo, L->hi, L->b, L->x, 1, L->work);
     op_apply(&A, L->x, L->r);
     size_t nv = nvert(L->n);
     for (size_t p = 0; p < nv; p++)
@@ -809,7 +923,7 @@ static int vcycle_level(or_hier *H, int l)
     if (st != OR_OK)
         return st;
     or_prolong_add_raw(C->n, C->x, L->n, L->x);
-    cheb_op(&A, H->degree, H->lo, H->hi, L->b, L->x, 0, L->work);
+    cheb_op(&A, H->degree, L->lo, L->hi, L->b, L->x, 0, L->work);
     return OR_OK;
 }
 
@@ -836,7 +950,7 @@ int or_smooth(void *hp, int l, const double *b, double *x, int x0_zero)
         return OR_ERR_ARG;
     or_level *L = &H->lv[l];
     or_op A = level_op(L);
-    cheb_op(&A, H->degree, H->lo, H->hi, b, x, x0_zero, L->work);
+    cheb_op(&A, H->degree, L->lo, L->hi, b, x, x0_zero, L->work);
     return OR_OK;
 }
 
@@ -1041,6 +1155,16 @@ int or_adjoint_gradient(void *hp, const double *phi, const double *dl_dphi, doub
 }
 
 /* Copy the 27-point coarse operator of level l (Galerkin hierarchies). */
+int or_level_interval(void *hp, int l, double *lo, double *hi)
+{
+    or_hier *H = (or_hier *)hp;
+    if (l < 0 || l >= H->levels)
+        return OR_ERR_ARG;
+    *lo = H->lv[l].lo;
+    *hi = H->lv[l].hi;
+    return OR_OK;
+}
+
 int or_get_a27(void *hp, int l, double *out)
 {
     or_hier *H = (or_hier *)hp;

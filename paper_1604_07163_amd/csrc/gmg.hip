@@ -35,6 +35,9 @@ struct LevelHost {
     bf16 *kx16 = nullptr, *ky16 = nullptr, *kz16 = nullptr;
     void *b = nullptr, *x = nullptr, *t1 = nullptr, *dinv = nullptr;
     bool g27 = false;           // Galerkin level: 27-point operator instead of links
+    double lo = 0, hi = 0;      // Chebyshev interval of D^-1 A on this level
+    ChebCoef<double> c64{};     // its coefficients, FP64 and FP32
+    ChebCoef<float> c32{};
     double *a64 = nullptr;      // its 27 coefficient arrays (FP64, padded layout)
     void *av = nullptr;         // the same in the V-cycle type (== a64 in FP64 mode)
     Tiling til{};    // V-cycle stencil kernels
@@ -69,8 +72,6 @@ struct gmg_handle {
     int persist_spread = 1;       // team packing stride (8 = one XCD) for persistent_wgs > 1
     int s2_persist = 0;           // first level on a single workgroup below a team (L-1: none)
     gmg::GridBar *bar = nullptr;  // device barrier of the persistent team
-    ChebCoef<double> cheb64{};
-    ChebCoef<float> cheb32{};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::vector<void *> allocs;
     std::string err;
@@ -110,10 +111,9 @@ int round_up(int a, int b) { return (a + b - 1) / b * b; }
 unsigned blocks_for(long long n, int nt) { return (unsigned)((n + nt - 1) / nt); }
 
 // Workgroup-count targets of the z-marching stencil kernels (the z-chunk
-// length follows from them, at least kMinChunk planes).  Measured on MI355X at
-// 513^3: FP32/BF16 sweeps stream as well with one chunk per column (about 1024
-// workgroups, all resident and advancing through z together) as with 8-plane
-// chunks; FP64 sweeps best with 8-plane chunks.
+// length follows from them, at least kMinChunk planes).  Measured on MI355X:
+// 8-9 plane chunks stream best in FP64 and FP32 alike (at 1025^3 the MIXED
+// V-cycle kernels ran 15 % faster than with one chunk per column).
 int env_int(const char *name, int dflt) {
     const char *e = getenv(name);
     const int v = e ? atoi(e) : 0;
@@ -213,11 +213,38 @@ Lev<V, K> view(const LevelHost &l) {
 }
 
 template <typename V>
-const ChebCoef<V> &cheb(const gmg_handle *h);
+const ChebCoef<V> &cheb(const gmg_handle *h, int l);
 template <>
-const ChebCoef<double> &cheb<double>(const gmg_handle *h) { return h->cheb64; }
+const ChebCoef<double> &cheb<double>(const gmg_handle *h, int l) { return h->lv[l].c64; }
 template <>
-const ChebCoef<float> &cheb<float>(const gmg_handle *h) { return h->cheb32; }
+const ChebCoef<float> &cheb<float>(const gmg_handle *h, int l) { return h->lv[l].c32; }
+
+// Chebyshev-Jacobi coefficients for the interval [lo, hi] of D^-1 A (three-term
+// recurrence of the Chebyshev iteration, Saad Alg. 12.1).
+void set_cheb(LevelHost &lh, int degree, double lo, double hi) {
+    const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo);
+    const double sigma = theta / delta;
+    ChebCoef<double> c{};
+    c.m = degree;
+    c.cfirst = 1.0 / theta;
+    double rho = 1.0 / sigma;
+    for (int j = 1; j < c.m; ++j) {
+        const double rn = 1.0 / (2.0 * sigma - rho);
+        c.c1[j] = rn * rho;
+        c.c2[j] = 2.0 * rn / delta;
+        rho = rn;
+    }
+    lh.lo = lo;
+    lh.hi = hi;
+    lh.c64 = c;
+    lh.c32 = ChebCoef<float>{};
+    lh.c32.m = c.m;
+    lh.c32.cfirst = (float)c.cfirst;
+    for (int j = 0; j < gmg::MAX_DEGREE; ++j) {
+        lh.c32.c1[j] = (float)c.c1[j];
+        lh.c32.c2[j] = (float)c.c2[j];
+    }
+}
 
 // ------------------------------------------------------------------ kernel timing
 // Brackets one launch with HIP events on the handle's stream when profiling
@@ -259,7 +286,7 @@ gmg_status finalize(gmg_handle *h, int count, int stage, PcgState *state = nullp
 template <typename V, typename K>
 gmg_status smooth27(gmg_handle *h, int l, bool from_zero, const int *skip) {
     LevelHost &lh = h->lv[l];
-    const ChebCoef<V> &cc = cheb<V>(h);
+    const ChebCoef<V> &cc = cheb<V>(h, l);
     V *bufs[2] = {(V *)lh.x, (V *)lh.t1};
     V *b = (V *)lh.b;
     const V *a = (const V *)lh.av;
@@ -315,7 +342,7 @@ gmg_status smooth_grid(gmg_handle *h, int l, bool from_zero, const double *r64_c
         return smooth27<V, K>(h, l, from_zero, skip);
     }
     const Lev<V, K> L = view<V, K>(lh);
-    const ChebCoef<V> &cc = cheb<V>(h);
+    const ChebCoef<V> &cc = cheb<V>(h, l);
     V *bufs[2] = {(V *)lh.x, (V *)lh.t1};
     V *b = (V *)lh.b;
     const dim3 grid(lh.til.nblocks), blk(gmg::NT);
@@ -479,8 +506,8 @@ gmg_status coarse_part(gmg_handle *h, const int *skip) {
     Prof pf(h, h->persist ? GMG_K_PERSISTENT : GMG_K_COARSE_SOLVE, true);
     if (h->persist && h->opt.persistent_wgs == 1) {
         gmg::k_persistent<V, K><<<1, gmg::NT_PERSIST, 0, h->stream>>>((const LevBuf<V, K> *)h->dev_levels,
-                                                                       h->s_persist, last, cheb<V>(h), h->chol, h->m,
-                                                                       skip, nullptr, 1, 1, 0);
+                                                                       h->s_persist, last, h->chol, h->m, skip,
+                                                                       nullptr, 1, 1, 0);
     } else if (h->persist) {
         // A team of co-resident workgroups (cooperative launch: an error, never
         // a hang, if they cannot all be resident).  With a second switch level the
@@ -489,14 +516,13 @@ gmg_status coarse_part(gmg_handle *h, const int *skip) {
         const int s2 = h->s2_persist;
         int s0 = h->s_persist, la = s2 < last ? s2 : last, m = h->m, na = h->opt.persistent_wgs,
             sp = h->persist_spread, ph = s2 < last ? 1 : 0;
-        ChebCoef<V> cc = cheb<V>(h);
         const double *lf = h->chol;
         gmg::GridBar *bar = h->bar;
-        void *args[] = {&lv, &s0, &la, &cc, &lf, &m, &skip, &bar, &na, &sp, &ph};
+        void *args[] = {&lv, &s0, &la, &lf, &m, &skip, &bar, &na, &sp, &ph};
         HIPCHK(hipLaunchCooperativeKernel((const void *)gmg::k_persistent<V, K>, dim3(na * sp), dim3(gmg::NT_PERSIST),
                                           args, 0, h->stream));
         if (s2 < last) {
-            gmg::k_persistent<V, K><<<1, gmg::NT_PERSIST, 0, h->stream>>>(lv, s2, last, cc, h->chol, h->m, skip,
+            gmg::k_persistent<V, K><<<1, gmg::NT_PERSIST, 0, h->stream>>>(lv, s2, last, h->chol, h->m, skip,
                                                                            nullptr, 1, 1, 0);
             LAUNCHCHK();
             ph = 2;
@@ -839,9 +865,100 @@ gmg_status upload_levels(gmg_handle *h) {
         lb[l].x = (V *)h->lv[l].x;
         lb[l].t1 = (V *)h->lv[l].t1;
         lb[l].t2 = nullptr;
+        lb[l].cc = cheb<V>(h, l);
     }
     HIPCHK(hipMemcpyAsync(h->dev_levels, lb.data(), sizeof(LevBuf<V, K>) * h->L, hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
+    return GMG_OK;
+}
+
+// ------------------------------------------------------------------ Galerkin-level interval
+// The bound 2 on the spectrum of D^-1 A holds for the 7-point M-matrix, not for
+// R A P, whose rows mix signs.  A smoothed Galerkin level gets the interval
+// [1.1 lam lo/hi, 1.1 lam] (lo, hi: the default interval) with lam the largest
+// Ritz value of kLanczosSteps Lanczos steps on D^-1 A in the D inner product,
+// computed in FP64 on the device; sums of the per-workgroup partials are
+// added on the host in workgroup order.
+constexpr int kLanczosSteps = 20;
+constexpr double kLanczosSafety = 1.1;
+
+gmg_status host_sum(gmg_handle *h, int count, double *out) {
+    std::vector<double> p(count);
+    HIPCHK(hipMemcpyAsync(p.data(), h->partial, count * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    double acc = 0.0;
+    for (int i = 0; i < count; ++i) acc += p[i];
+    *out = acc;
+    return GMG_OK;
+}
+
+// Largest eigenvalue of the symmetric tridiagonal matrix (diag d[0..m-1],
+// off-diagonal e[0..m-2]): bisection on the number of negative pivots of
+// T - x I, starting from the Gershgorin interval.
+double tridiag_top(int m, const double *d, const double *e) {
+    double a = d[0], b = d[0];
+    for (int i = 0; i < m; ++i) {
+        const double r = (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < m ? std::fabs(e[i]) : 0.0);
+        a = std::min(a, d[i] - r);
+        b = std::max(b, d[i] + r);
+    }
+    for (int it = 0; it < 2000; ++it) {
+        const double x = 0.5 * (a + b);
+        if (!(x > a && x < b)) break;
+        int neg = 0;
+        double piv = 1.0;
+        for (int i = 0; i < m; ++i) {
+            piv = d[i] - x - (i > 0 ? e[i - 1] * e[i - 1] / piv : 0.0);
+            if (piv == 0.0) piv = -1e-300;
+            neg += piv < 0.0;
+        }
+        if (neg == m)
+            b = x;  // every eigenvalue lies below x
+        else
+            a = x;
+    }
+    return b;
+}
+
+gmg_status galerkin_lambda(gmg_handle *h, int l, double *lam) {
+    LevelHost &c = h->lv[l];
+    const Tiling &t = c.til;
+    double *v = h->X, *vp = h->R, *w = h->Q;  // free during setup; level-l layout
+    HIPCHK(hipMemsetAsync(v, 0, c.nel * sizeof(double), h->stream));
+    HIPCHK(hipMemsetAsync(vp, 0, c.nel * sizeof(double), h->stream));
+    HIPCHK(hipMemsetAsync(w, 0, c.nel * sizeof(double), h->stream));
+    gmg::k_lz_start<<<t.nblocks, gmg::NT, 0, h->stream>>>(c.n, c.pitch, c.plane, t, c.a64, c.nel, v, h->partial);
+    LAUNCHCHK();
+    double s0;
+    STCHK(host_sum(h, t.nblocks, &s0));
+    gmg::k_lz_div<<<t.nblocks, gmg::NT, 0, h->stream>>>(c.n, c.pitch, c.plane, t, v, std::sqrt(s0));
+    LAUNCHCHK();
+    double al[kLanczosSteps], be[kLanczosSteps], beta = 0.0;
+    int m = 0;
+    for (int j = 0; j < kLanczosSteps; ++j) {
+        gmg::k_sweep27<double, 0, 0, true><<<t.nblocks, gmg::NT, 0, h->stream>>>(
+            c.n, c.pitch, c.plane, t, c.a64, c.nel, nullptr, v, nullptr, w, 0.0, 0.0, nullptr, h->partial);
+        LAUNCHCHK();
+        double alpha, bn2;
+        STCHK(host_sum(h, t.nblocks, &alpha));
+        gmg::k_lz_orth<<<t.nblocks, gmg::NT, 0, h->stream>>>(c.n, c.pitch, c.plane, t, c.a64, c.nel, v, vp, w, alpha,
+                                                             beta, h->partial);
+        LAUNCHCHK();
+        STCHK(host_sum(h, t.nblocks, &bn2));
+        const double bn = std::sqrt(bn2);
+        al[m] = alpha;
+        be[m] = bn;
+        ++m;
+        if (!(bn > 1e-14 * std::fabs(alpha))) break;  // invariant subspace
+        double *old = vp;  // vp <- v, v <- w / bn, w <- free
+        vp = v;
+        v = w;
+        w = old;
+        gmg::k_lz_div<<<t.nblocks, gmg::NT, 0, h->stream>>>(c.n, c.pitch, c.plane, t, v, bn);
+        LAUNCHCHK();
+        beta = bn;
+    }
+    *lam = tridiag_top(m, al, be);
     return GMG_OK;
 }
 
@@ -882,6 +999,13 @@ gmg_status load_coefficients(gmg_handle *h, const double *kx, const double *ky, 
             LAUNCHCHK();
         }
     }
+    for (int l = 1; l + 1 < h->L; ++l) {  // smoothed Galerkin levels (the coarsest is solved)
+        if (!h->lv[l].g27) continue;
+        double lam;
+        STCHK(galerkin_lambda(h, l, &lam));
+        const double hi = kLanczosSafety * lam;
+        set_cheb(h->lv[l], h->opt.cheb_degree, hi * (h->opt.cheb_lo / h->opt.cheb_hi), hi);
+    }
     if (mixed(h)) {
         for (int l = 0; l < h->L; ++l) {
             LevelHost &c = h->lv[l];
@@ -908,7 +1032,7 @@ gmg_status load_coefficients(gmg_handle *h, const double *kx, const double *ky, 
         LAUNCHCHK();
     }
     if (h->opt.coarse_solver == 0) STCHK(factor_coarsest(h));
-    return GMG_OK;
+    return mixed(h) ? upload_levels<float, bf16>(h) : upload_levels<double, double>(h);
 }
 
 gmg_status check_level(gmg_handle *h, int level) {
@@ -1026,7 +1150,7 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
         lh.nel = (long long)n * lh.plane;
         lh.s = (double)(n - 1) * (double)(n - 1);
         const int t64 = env_int("GMG_TARGET_WGS_64", 1 << 20);
-        lh.til = make_tiling(n, mx ? env_int("GMG_TARGET_WGS_V", 1024) : t64);
+        lh.til = make_tiling(n, env_int("GMG_TARGET_WGS_V", 1 << 20));
         lh.til64 = make_tiling(n, t64);
         lh.til2 = make_tiling(n, t64, gmg::TX2);
         lh.rows = make_rows(n, lh.pitch, lh.plane);
@@ -1162,30 +1286,10 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
         h->persist_spread = (8LL * o.persistent_wgs <= cap) ? 8 : 1;
         if ((long long)o.persistent_wgs > cap) return (h->err = "persistent team cannot be co-resident", bail(GMG_ERR_ARG));
     }
-    // Chebyshev coefficients
-    {
-        const double theta = 0.5 * (o.cheb_hi + o.cheb_lo), delta = 0.5 * (o.cheb_hi - o.cheb_lo);
-        const double sigma = theta / delta;
-        ChebCoef<double> c{};
-        c.m = o.cheb_degree;
-        c.cfirst = 1.0 / theta;
-        double rho = 1.0 / sigma;
-        for (int j = 1; j < c.m; ++j) {
-            const double rn = 1.0 / (2.0 * sigma - rho);
-            c.c1[j] = rn * rho;
-            c.c2[j] = 2.0 * rn / delta;
-            rho = rn;
-        }
-        h->cheb64 = c;
-        h->cheb32.m = c.m;
-        h->cheb32.cfirst = (float)c.cfirst;
-        for (int j = 0; j < gmg::MAX_DEGREE; ++j) {
-            h->cheb32.c1[j] = (float)c.c1[j];
-            h->cheb32.c2[j] = (float)c.c2[j];
-        }
-    }
+    // Chebyshev coefficients: the default interval on every level (Galerkin
+    // levels get their own in load_coefficients)
+    for (int l = 0; l < h->L; ++l) set_cheb(h->lv[l], o.cheb_degree, o.cheb_lo, o.cheb_hi);
     if ((s = load_coefficients(h, kx, ky, kz)) != GMG_OK) return bail(s);
-    if ((s = (mx ? upload_levels<float, bf16>(h) : upload_levels<double, double>(h))) != GMG_OK) return bail(s);
     (void)hipEventRecord(t1, h->stream);
     (void)hipEventSynchronize(t1);
     float ms = 0;
@@ -1424,6 +1528,14 @@ gmg_status gmg_get_level_coefficients(gmg_handle *h, int32_t level, double *kx, 
                                                                              lh.kz64, kx, ky, kz);
     LAUNCHCHK();
     HIPCHK(hipStreamSynchronize(h->stream));
+    return GMG_OK;
+}
+
+gmg_status gmg_get_level_interval(gmg_handle *h, int32_t level, double *lo, double *hi) {
+    STCHK(check_level(h, level));
+    if (!lo || !hi) return fail(h, GMG_ERR_ARG, "null pointer");
+    *lo = h->lv[level].lo;
+    *hi = h->lv[level].hi;
     return GMG_OK;
 }
 

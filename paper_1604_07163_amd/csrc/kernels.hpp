@@ -114,23 +114,25 @@ struct Lev {
     long long nel;   // elements per array (n * plane)
 };
 
-// Per-level buffers the V-cycle uses (device-resident array of these).
-template <typename V, typename K>
-struct LevBuf {
-    Lev<V, K> L;
-    V *b, *x, *t1, *t2;
-};
-
-struct Tiling {
-    int tiles_x, tiles_y, zchunk, nblocks;
-};
-
 template <typename V>
 struct ChebCoef {
     int m;          // steps per smoothing
     V cfirst;       // 1/theta
     V c1[MAX_DEGREE], c2[MAX_DEGREE];  // step j >= 1: rho_j rho_{j-1}, 2 rho_j / delta
 };
+
+// Per-level buffers the V-cycle uses (device-resident array of these).
+template <typename V, typename K>
+struct LevBuf {
+    Lev<V, K> L;
+    V *b, *x, *t1, *t2;
+    ChebCoef<V> cc;  // this level's Chebyshev coefficients
+};
+
+struct Tiling {
+    int tiles_x, tiles_y, zchunk, nblocks;
+};
+
 
 // ---------------------------------------------------------------- value functions
 // (A u)_p for one vertex from its 7 values and 6 link coefficients.
@@ -864,7 +866,7 @@ __device__ void p_smooth(const Team &T, const LevBuf<V, K> &lb, const ChebCoef<V
 // runs the ones below (multi-stage agglomeration).
 template <typename V, typename K>
 __global__ __launch_bounds__(NT_PERSIST) void k_persistent(const LevBuf<V, K> *__restrict__ lv, int s, int last,
-                                                           ChebCoef<V> cc, const double *__restrict__ Lf, int m,
+                                                           const double *__restrict__ Lf, int m,
                                                            const int *__restrict__ skip, GridBar *bar, int nactive,
                                                            int spread, int phase) {
     if (skip && *skip) return;
@@ -872,9 +874,9 @@ __global__ __launch_bounds__(NT_PERSIST) void k_persistent(const LevBuf<V, K> *_
     const Team T{(int)blockIdx.x / spread, nactive, bar};
     __shared__ double y[MAX_COARSE];
     for (int l = s; l < last && phase != 2; ++l) {
-        const LevBuf<V, K> F = lv[l];
-        const LevBuf<V, K> C = lv[l + 1];
-        p_smooth(T, F, cc, true);
+        const LevBuf<V, K> &F = lv[l];
+        const LevBuf<V, K> &C = lv[l + 1];
+        p_smooth(T, F, F.cc, true);
         const int nc = C.L.n, mc = nc - 2;
         const int np = mc * mc * mc;
         for (int u = T.first(); u < np; u += T.stride()) {
@@ -887,14 +889,14 @@ __global__ __launch_bounds__(NT_PERSIST) void k_persistent(const LevBuf<V, K> *_
     if (phase == 1) return;
     if (phase == 0) {
         if (T.rank == 0) {
-            const LevBuf<V, K> C = lv[last];
+            const LevBuf<V, K> &C = lv[last];
             chol_solve_block(C.L.n, C.L.pitch, C.L.plane, m, Lf, C.b, C.x, y);
         }
         T.sync();
     }
     for (int l = last - 1; l >= s; --l) {
-        const LevBuf<V, K> F = lv[l];
-        const LevBuf<V, K> C = lv[l + 1];
+        const LevBuf<V, K> &F = lv[l];
+        const LevBuf<V, K> &C = lv[l + 1];
         const int mf = F.L.n - 2;
         const int np = mf * mf * mf;
         for (int u = T.first(); u < np; u += T.stride()) {
@@ -903,7 +905,7 @@ __global__ __launch_bounds__(NT_PERSIST) void k_persistent(const LevBuf<V, K> *_
             F.x[o] = F.x[o] + prolong_at(C.x, C.L.pitch, C.L.plane, i, j, k);
         }
         T.sync();
-        p_smooth(T, F, cc, false);
+        p_smooth(T, F, F.cc, false);
     }
 }
 
@@ -1045,6 +1047,56 @@ __global__ __launch_bounds__(256) void k_stencil_out(int n, int pitch, long long
     const int i = (int)(v % n), j = (int)((v / n) % n), k = (int)(v / ((long long)n * n));
     const long long o = (long long)k * plane + (long long)j * pitch + i;
     for (int d = 0; d < 27; ++d) out[v * 27 + d] = a[(long long)d * nel + o];
+}
+
+// ---------------------------------------------------------------- Lanczos on a Galerkin level
+// Setup-time estimate of lambda_max(D^-1 A) for the Chebyshev interval of a
+// Galerkin level (Lanczos in the D inner product, D = centre coefficients).
+// Start vector: 1 + ((7i + 11j + 13k) mod 5) / 4 at interior vertices;
+// partial[wg] = its sum of v D v.
+__global__ __launch_bounds__(NT) void k_lz_start(int n, int pitch, long long plane, Tiling t,
+                                                 const double *__restrict__ a, long long nel,
+                                                 double *__restrict__ v, double *__restrict__ partial) {
+    const Column col = tile_column(n, t);
+    double acc = 0.0;
+    if (col.active) {
+        long long o = (long long)col.k0 * plane + (long long)col.j * pitch + col.i;
+        for (int k = col.k0; k < col.k1; ++k, o += plane) {
+            const double u = 1.0 + 0.25 * (double)((7 * col.i + 11 * col.j + 13 * k) % 5);
+            v[o] = u;
+            acc = fmaT(u * a[(long long)d27(0, 0, 0) * nel + o], u, acc);
+        }
+    }
+    const double sum = block_sum<NT>(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = sum;
+}
+// w <- w / d - alpha v - beta vp (w holds A v on entry); partial[wg] = sum w D w
+__global__ __launch_bounds__(NT) void k_lz_orth(int n, int pitch, long long plane, Tiling t,
+                                                const double *__restrict__ a, long long nel,
+                                                const double *__restrict__ v, const double *__restrict__ vp,
+                                                double *__restrict__ w, double alpha, double beta,
+                                                double *__restrict__ partial) {
+    const Column col = tile_column(n, t);
+    double acc = 0.0;
+    if (col.active) {
+        long long o = (long long)col.k0 * plane + (long long)col.j * pitch + col.i;
+        for (int k = col.k0; k < col.k1; ++k, o += plane) {
+            const double d = a[(long long)d27(0, 0, 0) * nel + o];
+            const double wn = w[o] / d - alpha * v[o] - beta * vp[o];
+            w[o] = wn;
+            acc = fmaT(wn * d, wn, acc);
+        }
+    }
+    const double sum = block_sum<NT>(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = sum;
+}
+// v <- v / c at interior vertices
+__global__ __launch_bounds__(NT) void k_lz_div(int n, int pitch, long long plane, Tiling t, double *__restrict__ v,
+                                               double c) {
+    const Column col = tile_column(n, t);
+    if (!col.active) return;
+    long long o = (long long)col.k0 * plane + (long long)col.j * pitch + col.i;
+    for (int k = col.k0; k < col.k1; ++k, o += plane) v[o] = v[o] / c;
 }
 
 // ================================================================ PCG vector kernels (FP64)

@@ -101,6 +101,8 @@ def lib():
     L.gmg_get_level_coefficients.restype = st
     L.gmg_get_level_stencil.argtypes = [P, I32, P]
     L.gmg_get_level_stencil.restype = st
+    L.gmg_get_level_interval.argtypes = [P, I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    L.gmg_get_level_interval.restype = st
     L.gmg_profile_start.argtypes = [P]
     L.gmg_profile_start.restype = st
     L.gmg_profile_stop.argtypes = [P]
@@ -319,6 +321,14 @@ class Solver:
         if s != OK:
             self._err(s, "gmg_get_level_coefficients")
         return kx, ky, kz
+
+    def level_interval(self, level):
+        """Chebyshev interval (lo, hi) of D^-1 A the smoother uses on `level`."""
+        lo, hi = ctypes.c_double(), ctypes.c_double()
+        s = lib().gmg_get_level_interval(self._h, level, ctypes.byref(lo), ctypes.byref(hi))
+        if s != OK:
+            self._err(s, "gmg_get_level_interval")
+        return lo.value, hi.value
 
     def level_stencil(self, level):
         """FP64 Galerkin operator of `level` as an (N, N, N, 27) tensor, entry

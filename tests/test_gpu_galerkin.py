@@ -45,6 +45,20 @@ def test_galerkin_stencils(n, levels, g):
 
 
 @pytest.mark.parametrize("n,levels,g", CASES)
+def test_galerkin_chebyshev_intervals(n, levels, g):
+    """The Lanczos-estimated interval of every smoothed Galerkin level equals the
+    oracle's (independent FP64 sums in another order); other levels keep the
+    option interval."""
+    k, s, H = make(n, levels, g)
+    for l in range(levels):
+        lo, hi = s.level_interval(l)
+        lo_o, hi_o = H.level_interval(l)
+        assert abs(hi - hi_o) <= 1e-12 * hi_o and abs(lo - lo_o) <= 1e-12 * hi_o, (l, lo, hi, lo_o, hi_o)
+        if not (g <= l < levels - 1):
+            assert (lo, hi) == (0.25, 2.0)
+
+
+@pytest.mark.parametrize("n,levels,g", CASES)
 def test_galerkin_level_operations(n, levels, g):
     k, s, H = make(n, levels, g)
     for l in range(max(g, 1), levels - 1):

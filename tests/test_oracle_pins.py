@@ -572,9 +572,10 @@ def test_galerkin_operator_is_dense_rap(oracle_mod, n):
                                atol=1e-11 * np.abs(Ac_ref).max())
 
 
-def dense_vcycle_galerkin(A0, n, levels, m=DEG, lo=LO, hi=HI, first=1, rediscretized=None):
+def dense_vcycle_galerkin(A0, n, levels, m=DEG, lo=LO, hi=HI, first=1, rediscretized=None, intervals=None):
     """Dense V-cycle whose levels l >= first are P^T A P / 8; levels 0 < l < first
-    take the dense matrices in `rediscretized[l]` (hybrid construction)."""
+    take the dense matrices in `rediscretized[l]` (hybrid construction).
+    intervals[l] = (lo, hi) overrides the Chebyshev interval of level l."""
     As, ns = [A0], [n]
     for l in range(1, levels):
         P = mf.prolongation_matrix(ns[-1])
@@ -587,7 +588,8 @@ def dense_vcycle_galerkin(A0, n, levels, m=DEG, lo=LO, hi=HI, first=1, rediscret
             return np.linalg.inv(A)
         P = mf.prolongation_matrix(ns[l])
         K = np.diag(1.0 / np.diag(A)) @ A
-        pK = mf.cheb_poly_matrix(K, m, lo, hi)
+        a, b = intervals[l] if intervals else (lo, hi)
+        pK = mf.cheb_poly_matrix(K, m, a, b)
         I = np.eye(A.shape[0])
         E = pK @ (I - P @ B(l + 1) @ (P.T / 8.0) @ A) @ pK
         return (I - E) @ np.linalg.inv(A)
@@ -598,7 +600,8 @@ def dense_vcycle_galerkin(A0, n, levels, m=DEG, lo=LO, hi=HI, first=1, rediscret
 def test_galerkin_vcycle_matches_dense_composition(oracle_mod, n, levels):
     kx, ky, kz = rand_k(n, 95 + n + levels)
     H = oracle_mod.Hierarchy(kx, ky, kz, levels=levels, galerkin=True)
-    Bd = dense_vcycle_galerkin(mf.dense_from_links(kx, ky, kz), n, levels)
+    Bd = dense_vcycle_galerkin(mf.dense_from_links(kx, ky, kz), n, levels,
+                               intervals=[H.level_interval(l) for l in range(levels)])
     r = rand_vec(n, 9)
     ref = Bd @ mf.interior(r)
     np.testing.assert_allclose(mf.interior(H.vcycle(r)), ref, rtol=1e-10, atol=1e-11 * np.abs(ref).max())
@@ -627,9 +630,52 @@ def test_hybrid_galerkin_vcycle_matches_dense_composition(oracle_mod, n, levels,
     for l in range(1, first):
         k = oracle_mod.coarsen_k(*k)
         redisc[l] = mf.dense_from_links(*k)
-    Bd = dense_vcycle_galerkin(mf.dense_from_links(kx, ky, kz), n, levels, first=first, rediscretized=redisc)
+    Bd = dense_vcycle_galerkin(mf.dense_from_links(kx, ky, kz), n, levels, first=first, rediscretized=redisc,
+                               intervals=[H.level_interval(l) for l in range(levels)])
     r = rand_vec(n, 11)
     ref = Bd @ mf.interior(r)
     np.testing.assert_allclose(mf.interior(H.vcycle(r)), ref, rtol=1e-10, atol=1e-11 * np.abs(ref).max())
     with pytest.raises(Exception):
         H.level_a27(first - 1)
+
+
+# ---------------------------------------------------------------- Chebyshev interval of Galerkin levels
+def test_lanczos_estimate_brackets_the_top_eigenvalue(oracle_mod):
+    """20 Lanczos steps in the D inner product: a lower bound on lambda_max(D^-1 A)
+    (Ritz values lie inside the spectrum) within 2 % of it for Galerkin operators
+    from random links (dense generalized eigenproblem A x = lambda D x); the
+    7-point constant-k closed form 1 + cos(pi h); and one unknown, where
+    D^-1 A = 1 exactly."""
+    import scipy.linalg as sl
+    g = np.random.default_rng(21)
+    for n, c in ((9, 2.0), (17, 3.0)):
+        kx, ky, kz = [np.exp(g.uniform(-c, c, size=s)) for s in inputs.face_shapes(n)]
+        a27 = oracle_mod.galerkin(kx, ky, kz)
+        M = a27_to_dense(a27)
+        exact = sl.eigh(M, np.diag(np.diag(M)), eigvals_only=True).max()
+        nc = (n - 1) // 2 + 1
+        est = oracle_mod.lanczos_max(*inputs.const_k(nc), a27=a27)
+        assert exact * 0.98 <= est <= exact * (1 + 1e-12), (n, est, exact)
+        # more steps never lower the estimate (nested Krylov spaces)
+        assert oracle_mod.lanczos_max(*inputs.const_k(nc), a27=a27, steps=30) >= est * (1 - 1e-12)
+    n = 17
+    exact = 1.0 + np.cos(np.pi / (n - 1))
+    est = oracle_mod.lanczos_max(*inputs.const_k(n))
+    assert exact * 0.95 <= est <= exact * (1 + 1e-12)
+    assert abs(oracle_mod.lanczos_max(*inputs.const_k(3)) - 1.0) <= 1e-14
+
+
+@pytest.mark.parametrize("first", [1, 2])
+def test_galerkin_level_intervals(oracle_mod, first):
+    """Smoothed Galerkin levels use [1.1 lam/8, 1.1 lam] with lam the Lanczos
+    estimate of their own operator; every other level keeps [0.25, 2]."""
+    n, levels = 33, 5
+    kx, ky, kz, _ = inputs.inclusion_k(n, 4, rmin_cells=1.0, rmax_cells=4.0)
+    H = oracle_mod.Hierarchy(kx, ky, kz, levels=levels, galerkin=first)
+    for l in range(levels):
+        lo, hi = H.level_interval(l)
+        if first <= l < levels - 1:
+            lam = oracle_mod.lanczos_max(*inputs.const_k(H.level_n(l)), a27=H.level_a27(l))
+            assert abs(hi - 1.1 * lam) <= 1e-14 * hi and abs(lo - hi / 8) <= 1e-14 * hi
+        else:
+            assert (lo, hi) == (LO, HI)

@@ -248,5 +248,5 @@ WORKLOADS = {
     "lognormal257": dict(n=257, levels=8, k_seed=2, f_seed=3),
     "inclusions513": dict(n=513, levels=9, k_seed=4, f_seed=5),
     "adjoint129": dict(n=129, levels=7, k_seed=6, kobs_seed=7, f_seed=8, face_seed=9),
-    "lognormal1025": dict(n=1025, levels=10, k_seed=10, kobs_seed=11, f_seed=12),
+    "lognormal1025": dict(n=1025, levels=10, k_seed=10, kobs_seed=11, f_seed=12, clip=3.0),
 }

@@ -156,3 +156,24 @@ def test_truncated_hierarchy_flexible_cg(n, levels):
     nc = H.level_n(levels - 1)
     b = rand_vec(nc, 7)
     assert rel_max(to_np(s.coarse_solve(to_gpu(b))), H.coarse_solve(b)) <= 1e-10
+
+
+@pytest.mark.parametrize("n,levels", [(3, 1), (5, 2), (9, 1), (9, 3), (17, 4)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_degenerate_hierarchies(n, levels, precision):
+    """One unknown (3^3), the finest level solved directly by Cholesky
+    (levels = 1: the V-cycle is the exact inverse, one CG step), and the
+    deepest hierarchy (coarsest 3^3): against the oracle."""
+    g = np.random.default_rng(n + levels)
+    k = [np.exp(g.uniform(-1.0, 1.0, size=sh)) for sh in inputs.face_shapes(n)]
+    f = inputs.uniform_rhs(n, 9)
+    H = oracle.Hierarchy(*k, levels=levels)
+    xo, io = H.solve(f, rtol=1e-10)
+    s = gmg.Solver(*[to_gpu(a) for a in k], levels=levels, precision=precision)
+    xg, ig = s.solve(to_gpu(f), rtol=1e-10)
+    say(f"    n={n} levels={levels} {precision}: its {ig['iterations']} (oracle {io['iterations']})")
+    assert ig["status"] == "GMG_OK" and ig["rel_res_true"] <= 1e-10
+    if levels == 1:
+        assert io["iterations"] == 1 and ig["iterations"] <= (1 if precision == "fp64" else 3)
+    tol = 1e-10 if precision == "fp64" else 1e-8
+    assert rel_l2(to_np(xg), xo) <= tol

@@ -163,6 +163,9 @@ def sweep(args):
     rows = []
     sizes = [0] + [s for s in (65, 33, 17, 9) if s < n]
     configs = [dict(precision=p, switch_n=sw, persistent_wgs=1) for p in ("fp64", "mixed") for sw in sizes]
+    # the same one-workgroup persistent kernel sweeping its levels in HBM/L2 instead of LDS
+    configs += [dict(precision=p, switch_n=sw, persistent_wgs=1, persistent_lds=False)
+                for p in ("fp64", "mixed") for sw in sizes if sw > 0]
     configs += [dict(precision=p, switch_n=sw, persistent_wgs=t) for p in ("fp64", "mixed")
                 for sw in sizes if sw > 0 for t in args.teams]
     for t in args.teams:  # two-stage: team on the middle levels, one workgroup from 9^3 down
@@ -190,7 +193,7 @@ def sweep(args):
         row = {"levels": lv, **cfg, "iterations": info["iterations"], "coarse_iterations": info["coarse_iterations"],
                "ms": 1e3 * float(np.median(ts)), "ms_per_iteration": 1e3 * float(np.median(ts)) / info["iterations"],
                "coarse_kernel_us": 1e3 * coarse.get("avg_ms", 0.0), "rel_res_true": info["rel_res_true"],
-               "setup_ms": info["setup_ms"]}
+               "setup_ms": info["setup_ms"], "lds_bytes": s.persistent_lds_bytes}
         log(json.dumps(row))
         rows.append(row)
         s.close()

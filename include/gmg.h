@@ -100,6 +100,10 @@ typedef struct {
                                above it; levels below g keep re-discretized links.  g = 1 is
                                Galerkin throughout (Sec. 3.3.2), g > 1 the hybrid construction
                                of Sec. 3.3.3.  0 = re-discretized throughout (default). */
+    int32_t persistent_lds; /* 1 (default): with persistent_wgs == 1, the agglomerated levels
+                               are copied into the workgroup's LDS for the coarse cycle when they
+                               all fit (link levels only); 0: they are swept in HBM/L2.  The
+                               result is the same either way. */
 } gmg_options;
 
 typedef struct {
@@ -169,6 +173,10 @@ gmg_status gmg_debug_coarse_solve(gmg_handle *h, const double *b, double *x);
 gmg_status gmg_debug_vcycle(gmg_handle *h, const double *r, double *z);
 /* Copy level coefficients out in face shapes (MIXED: the BF16 values). */
 gmg_status gmg_get_level_coefficients(gmg_handle *h, int32_t level, double *kx, double *ky, double *kz);
+
+/* Dynamic LDS bytes of the one-workgroup persistent kernel when the handle
+ * runs its agglomerated levels out of LDS (option persistent_lds), else 0. */
+uint64_t gmg_persistent_lds_bytes(const gmg_handle *h);
 
 /* Chebyshev interval [*lo, *hi] of D^-1 A used by the smoother on `level`
  * (host pointers).  The option interval on re-discretized levels; on a

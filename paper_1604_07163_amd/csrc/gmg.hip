@@ -66,11 +66,14 @@ struct gmg_handle {
     long long coarse_its = 0;     // coarse CG iterations in the current solve
     double *chol = nullptr;       // coarsest factor, device
     int m = 0;
-    void *dev_levels = nullptr;   // LevBuf<V,K>[L] on the device
+    void *dev_levels = nullptr;   // LevBuf<V,K>[L] on the device, then ChebCoef<V>[L] at dev_cheb
+    void *dev_cheb = nullptr;
     int s_persist = 0;            // first level run by the persistent kernel (L-1 if none)
     bool persist = false;
     int persist_spread = 1;       // team packing stride (8 = one XCD) for persistent_wgs > 1
     int s2_persist = 0;           // first level on a single workgroup below a team (L-1: none)
+    bool persist_lds = false;     // single-workgroup persistent levels staged in LDS
+    size_t lds_bytes = 0;         // its dynamic LDS size
     gmg::GridBar *bar = nullptr;  // device barrier of the persistent team
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::vector<void *> allocs;
@@ -504,25 +507,30 @@ gmg_status coarse_part(gmg_handle *h, const int *skip) {
     const int last = h->L - 1;
     if (h->opt.coarse_solver == 1) return coarse_cg<V, K>(h, skip);
     Prof pf(h, h->persist ? GMG_K_PERSISTENT : GMG_K_COARSE_SOLVE, true);
-    if (h->persist && h->opt.persistent_wgs == 1) {
+    if (h->persist && h->opt.persistent_wgs == 1 && h->persist_lds) {
+        gmg::k_persistent_lds<V, K><<<1, gmg::NT_PERSIST, h->lds_bytes, h->stream>>>(
+            (const LevBuf<V, K> *)h->dev_levels, (const ChebCoef<V> *)h->dev_cheb, h->s_persist, last, h->chol, h->m,
+            skip);
+    } else if (h->persist && h->opt.persistent_wgs == 1) {
         gmg::k_persistent<V, K><<<1, gmg::NT_PERSIST, 0, h->stream>>>((const LevBuf<V, K> *)h->dev_levels,
-                                                                       h->s_persist, last, h->chol, h->m, skip,
-                                                                       nullptr, 1, 1, 0);
+                                                                       (const ChebCoef<V> *)h->dev_cheb, h->s_persist,
+                                                                       last, h->chol, h->m, skip, nullptr, 1, 1, 0);
     } else if (h->persist) {
         // A team of co-resident workgroups (cooperative launch: an error, never
         // a hang, if they cannot all be resident).  With a second switch level the
         // team runs the middle levels and one workgroup the ones below it.
         const LevBuf<V, K> *lv = (const LevBuf<V, K> *)h->dev_levels;
+        const ChebCoef<V> *cc = (const ChebCoef<V> *)h->dev_cheb;
         const int s2 = h->s2_persist;
         int s0 = h->s_persist, la = s2 < last ? s2 : last, m = h->m, na = h->opt.persistent_wgs,
             sp = h->persist_spread, ph = s2 < last ? 1 : 0;
         const double *lf = h->chol;
         gmg::GridBar *bar = h->bar;
-        void *args[] = {&lv, &s0, &la, &lf, &m, &skip, &bar, &na, &sp, &ph};
+        void *args[] = {&lv, &cc, &s0, &la, &lf, &m, &skip, &bar, &na, &sp, &ph};
         HIPCHK(hipLaunchCooperativeKernel((const void *)gmg::k_persistent<V, K>, dim3(na * sp), dim3(gmg::NT_PERSIST),
                                           args, 0, h->stream));
         if (s2 < last) {
-            gmg::k_persistent<V, K><<<1, gmg::NT_PERSIST, 0, h->stream>>>(lv, s2, last, h->chol, h->m, skip,
+            gmg::k_persistent<V, K><<<1, gmg::NT_PERSIST, 0, h->stream>>>(lv, cc, s2, last, h->chol, h->m, skip,
                                                                            nullptr, 1, 1, 0);
             LAUNCHCHK();
             ph = 2;
@@ -865,9 +873,11 @@ gmg_status upload_levels(gmg_handle *h) {
         lb[l].x = (V *)h->lv[l].x;
         lb[l].t1 = (V *)h->lv[l].t1;
         lb[l].t2 = nullptr;
-        lb[l].cc = cheb<V>(h, l);
     }
     HIPCHK(hipMemcpyAsync(h->dev_levels, lb.data(), sizeof(LevBuf<V, K>) * h->L, hipMemcpyHostToDevice, h->stream));
+    std::vector<ChebCoef<V>> cc(h->L);
+    for (int l = 0; l < h->L; ++l) cc[l] = cheb<V>(h, l);
+    HIPCHK(hipMemcpyAsync(h->dev_cheb, cc.data(), sizeof(ChebCoef<V>) * h->L, hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     return GMG_OK;
 }
@@ -1068,6 +1078,7 @@ void gmg_default_options(gmg_options *o, int32_t n) {
     o->flexible = 0;
     o->switch2_n = 0;
     o->galerkin = 0;
+    o->persistent_lds = 1;
 }
 
 const char *gmg_status_string(gmg_status s) {
@@ -1113,7 +1124,7 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
         o.persistent_wgs < 1 || o.persistent_wgs > 32 || o.switch2_n < 0 || o.check_every < 0 || (o.coeff_is_log != 0 && o.coeff_is_log != 1) ||
         (o.coarse_solver != 0 && o.coarse_solver != 1) || (o.flexible != 0 && o.flexible != 1) ||
         (o.coarse_solver == 1 && (!(o.coarse_rtol > 0.0) || o.coarse_max_it < 1 || o.switch_n != 0)) ||
-        o.galerkin < 0)
+        o.galerkin < 0 || (o.persistent_lds != 0 && o.persistent_lds != 1))
         return GMG_ERR_ARG;
     if ((o.n - 1) % (1 << (o.levels - 1)) != 0) return GMG_ERR_DIMS;
     const int nc = (o.n - 1) / (1 << (o.levels - 1)) + 1;
@@ -1265,6 +1276,10 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
     {
         char *dl;
         const size_t sz = mx ? sizeof(LevBuf<float, bf16>) : sizeof(LevBuf<double, double>);
+        const size_t szc = mx ? sizeof(ChebCoef<float>) : sizeof(ChebCoef<double>);
+        char *dc;
+        ALLOC(dc, (long long)(szc * h->L));
+        h->dev_cheb = dc;
         ALLOC(dl, (long long)(sz * h->L));
         h->dev_levels = dl;
     }
@@ -1285,6 +1300,27 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
         const long long cap = (long long)occ * ncu;
         h->persist_spread = (8LL * o.persistent_wgs <= cap) ? 8 : 1;
         if ((long long)o.persistent_wgs > cap) return (h->err = "persistent team cannot be co-resident", bail(GMG_ERR_ARG));
+    }
+    // one-workgroup persistent levels in LDS when they all fit (link levels only)
+    if (h->persist && o.persistent_wgs == 1 && o.persistent_lds) {
+        size_t bytes = gmg::lds_align((size_t)h->m * sizeof(double));
+        bool links = true;
+        for (int l = h->s_persist; l < h->L; ++l) {
+            bytes += mx ? gmg::lds_level_bytes<float, bf16>(h->lv[l].n) : gmg::lds_level_bytes<double, double>(h->lv[l].n);
+            links = links && !h->lv[l].g27;
+        }
+        int dev = 0, cap = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cap, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
+        hipFuncAttributes fa{};
+        const void *fn = mx ? (const void *)gmg::k_persistent_lds<float, bf16>
+                            : (const void *)gmg::k_persistent_lds<double, double>;
+        if (links && hipFuncGetAttributes(&fa, fn) == hipSuccess && bytes + fa.sharedSizeBytes <= (size_t)cap &&
+            hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess) {
+            h->persist_lds = true;
+            h->lds_bytes = bytes;
+        }
+        (void)hipGetLastError();
     }
     // Chebyshev coefficients: the default interval on every level (Galerkin
     // levels get their own in load_coefficients)
@@ -1530,6 +1566,8 @@ gmg_status gmg_get_level_coefficients(gmg_handle *h, int32_t level, double *kx, 
     HIPCHK(hipStreamSynchronize(h->stream));
     return GMG_OK;
 }
+
+uint64_t gmg_persistent_lds_bytes(const gmg_handle *h) { return h && h->persist_lds ? h->lds_bytes : 0; }
 
 gmg_status gmg_get_level_interval(gmg_handle *h, int32_t level, double *lo, double *hi) {
     STCHK(check_level(h, level));

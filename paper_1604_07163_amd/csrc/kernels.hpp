@@ -126,7 +126,6 @@ template <typename V, typename K>
 struct LevBuf {
     Lev<V, K> L;
     V *b, *x, *t1, *t2;
-    ChebCoef<V> cc;  // this level's Chebyshev coefficients
 };
 
 struct Tiling {
@@ -521,23 +520,19 @@ __global__ __launch_bounds__(NT) void k_cheb_step(Lev<V, K> L, Tiling t, const V
 // ---------------------------------------------------------------- transfer operators
 // Full-weighting restriction of the residual, summed in a fixed order:
 // x first, then y, then z, each with weights (1/4, 1/2, 1/4).
-template <typename V, typename K>
-__device__ __forceinline__ V resid_at(const Lev<V, K> &F, const V *b, const V *x, int i, int j, int k) {
-    if (i < 1 || j < 1 || k < 1 || i > F.n - 2 || j > F.n - 2 || k > F.n - 2) return V(0);
-    const long long o = (long long)k * F.plane + (long long)j * F.pitch + i;
-    return b[o] - apply_at(F, x, o);
-}
-template <typename V, typename K>
-__device__ __forceinline__ V restrict_resid_at(const Lev<V, K> &F, const V *b, const V *x, int I, int J,
-                                               int K_) {
+// Full weighting b_c = R r at coarse vertex (I,J,K) from a stored fine residual
+// r (the 27 fine vertices of an interior coarse vertex are interior): weights
+// (1/4, 1/2, 1/4) summed x first, then y, then z.
+template <typename V>
+__device__ __forceinline__ V restrict_at(const V *r, int pf, long long plf, int I, int J, int K_) {
     const V w[3] = {V(0.25), V(0.5), V(0.25)};
     V accz = V(0);
     for (int c = 0; c < 3; ++c) {
         V accy = V(0);
         for (int bb = 0; bb < 3; ++bb) {
             V accx = V(0);
-            for (int a = 0; a < 3; ++a)
-                accx = fmaT(w[a], resid_at(F, b, x, 2 * I + a - 1, 2 * J + bb - 1, 2 * K_ + c - 1), accx);
+            const long long row = (long long)(2 * K_ + c - 1) * plf + (long long)(2 * J + bb - 1) * pf + 2 * I - 1;
+            for (int a = 0; a < 3; ++a) accx = fmaT(w[a], r[row + a], accx);
             accy = fmaT(w[bb], accx, accy);
         }
         accz = fmaT(w[c], accy, accz);
@@ -573,7 +568,7 @@ __device__ __forceinline__ V prolong_at(const V *e, int pc, long long plc, int i
 // b_c = R r for a fine residual r held in memory (written by k_residual).
 // One thread per coarse column (I, J) marching in K; the in-plane 3x3 sum of
 // fine plane 2K+1 is reused as the lower plane of K+1.  The summation order
-// is that of restrict_resid_at, so both paths round identically.
+// is that of restrict_at, so both paths round identically.
 template <typename V>
 __device__ __forceinline__ V plane_sum(const V *r, long long base, int pf) {
     const V w[3] = {V(0.25), V(0.5), V(0.25)};
@@ -864,39 +859,45 @@ __device__ void p_smooth(const Team &T, const LevBuf<V, K> &lb, const ChebCoef<V
 // phase 2: only the up sweep of levels last-1..s (correction from `last`).
 // Phases 1 and 2 let a team run the middle levels while a single workgroup
 // runs the ones below (multi-stage agglomeration).
+// Levels are copied into registers (value copies): stores through the level
+// pointers could otherwise alias the level table and force reloads of every
+// base pointer after each store.  cc[l]: Chebyshev coefficients of level l.
 template <typename V, typename K>
-__global__ __launch_bounds__(NT_PERSIST) void k_persistent(const LevBuf<V, K> *__restrict__ lv, int s, int last,
-                                                           const double *__restrict__ Lf, int m,
-                                                           const int *__restrict__ skip, GridBar *bar, int nactive,
-                                                           int spread, int phase) {
-    if (skip && *skip) return;
-    if ((int)blockIdx.x % spread != 0) return;
-    const Team T{(int)blockIdx.x / spread, nactive, bar};
-    __shared__ double y[MAX_COARSE];
+__device__ void persistent_cycle(const Team &T, const LevBuf<V, K> *lv, const ChebCoef<V> *cc, int s, int last,
+                                 const double *Lf, int m, int phase, double *y) {
     for (int l = s; l < last && phase != 2; ++l) {
-        const LevBuf<V, K> &F = lv[l];
-        const LevBuf<V, K> &C = lv[l + 1];
-        p_smooth(T, F, F.cc, true);
+        const LevBuf<V, K> F = lv[l];
+        const LevBuf<V, K> C = lv[l + 1];
+        p_smooth(T, F, cc[l], true);
+        // r = b - A x into t1 (free after smoothing), then full weighting of r
+        const int mf = F.L.n - 2, npf = mf * mf * mf;
+        for (int u = T.first(); u < npf; u += T.stride()) {
+            int i, j, k;
+            vertex_of(F.L.n, u, i, j, k);
+            const long long o = (long long)k * F.L.plane + (long long)j * F.L.pitch + i;
+            F.t1[o] = F.b[o] - apply_at(F.L, F.x, o);
+        }
+        T.sync();
         const int nc = C.L.n, mc = nc - 2;
         const int np = mc * mc * mc;
         for (int u = T.first(); u < np; u += T.stride()) {
             const int I = 1 + u % mc, J = 1 + (u / mc) % mc, K_ = 1 + u / (mc * mc);
             C.b[(long long)K_ * C.L.plane + (long long)J * C.L.pitch + I] =
-                restrict_resid_at(F.L, F.b, F.x, I, J, K_);
+                restrict_at(F.t1, F.L.pitch, F.L.plane, I, J, K_);
         }
         T.sync();
     }
     if (phase == 1) return;
     if (phase == 0) {
         if (T.rank == 0) {
-            const LevBuf<V, K> &C = lv[last];
+            const LevBuf<V, K> C = lv[last];
             chol_solve_block(C.L.n, C.L.pitch, C.L.plane, m, Lf, C.b, C.x, y);
         }
         T.sync();
     }
     for (int l = last - 1; l >= s; --l) {
-        const LevBuf<V, K> &F = lv[l];
-        const LevBuf<V, K> &C = lv[l + 1];
+        const LevBuf<V, K> F = lv[l];
+        const LevBuf<V, K> C = lv[l + 1];
         const int mf = F.L.n - 2;
         const int np = mf * mf * mf;
         for (int u = T.first(); u < np; u += T.stride()) {
@@ -905,7 +906,101 @@ __global__ __launch_bounds__(NT_PERSIST) void k_persistent(const LevBuf<V, K> *_
             F.x[o] = F.x[o] + prolong_at(C.x, C.L.pitch, C.L.plane, i, j, k);
         }
         T.sync();
-        p_smooth(T, F, F.cc, false);
+        p_smooth(T, F, cc[l], false);
+    }
+}
+
+template <typename V, typename K>
+__global__ __launch_bounds__(NT_PERSIST) void k_persistent(const LevBuf<V, K> *__restrict__ lv,
+                                                           const ChebCoef<V> *__restrict__ cc, int s, int last,
+                                                           const double *__restrict__ Lf, int m,
+                                                           const int *__restrict__ skip, GridBar *bar, int nactive,
+                                                           int spread, int phase) {
+    if (skip && *skip) return;
+    if ((int)blockIdx.x % spread != 0) return;
+    const Team T{(int)blockIdx.x / spread, nactive, bar};
+    __shared__ double y[MAX_COARSE];
+    persistent_cycle(T, lv, cc, s, last, Lf, m, phase, y);
+}
+
+// The agglomerated levels held in LDS: one workgroup copies the links, D^-1
+// and the right-hand side of level s from HBM into a compact n^3 layout per
+// level (pitch n, plane n^2), runs the same cycle on those copies (every
+// sweep now reads and writes LDS), and writes the correction x_s back.  Same
+// value functions in the same order as the other paths, so the result is
+// identical to theirs.  The host launches it only when all levels fit
+// (lds_bytes_for below) and only for link (7-point) levels.
+__host__ __device__ inline size_t lds_align(size_t b) { return (b + 15) & ~(size_t)15; }
+template <typename V, typename K>
+__host__ __device__ inline size_t lds_level_bytes(int n) {
+    const size_t nv = (size_t)n * n * n;
+    return 4 * lds_align(nv * sizeof(V)) + 3 * lds_align(nv * sizeof(K));
+}
+
+template <typename V, typename K>
+__global__ __launch_bounds__(NT_PERSIST) void k_persistent_lds(const LevBuf<V, K> *__restrict__ lv,
+                                                               const ChebCoef<V> *__restrict__ cc, int s, int last,
+                                                               const double *__restrict__ Lf, int m,
+                                                               const int *__restrict__ skip) {
+    if (skip && *skip) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ LevBuf<V, K> lb[MAX_LEVELS];
+    size_t off = 0;
+    for (int l = s; l <= last; ++l) {
+        const LevBuf<V, K> &G = lv[l];
+        const int n = G.L.n;
+        const int nv = n * n * n;
+        V *x = (V *)(smem + off);
+        off += lds_align(nv * sizeof(V));
+        V *t1 = (V *)(smem + off);
+        off += lds_align(nv * sizeof(V));
+        V *b = (V *)(smem + off);
+        off += lds_align(nv * sizeof(V));
+        V *dv = (V *)(smem + off);
+        off += lds_align(nv * sizeof(V));
+        K *kx = (K *)(smem + off);
+        off += lds_align(nv * sizeof(K));
+        K *ky = (K *)(smem + off);
+        off += lds_align(nv * sizeof(K));
+        K *kz = (K *)(smem + off);
+        off += lds_align(nv * sizeof(K));
+        if (threadIdx.x == 0) {
+            LevBuf<V, K> B = G;
+            B.L.pitch = n;
+            B.L.plane = (long long)n * n;
+            B.L.kx = kx;
+            B.L.ky = ky;
+            B.L.kz = kz;
+            B.L.dinv = dv;
+            B.L.a27 = nullptr;
+            B.L.nel = nv;
+            B.b = b;
+            B.x = x;
+            B.t1 = t1;
+            B.t2 = nullptr;
+            lb[l] = B;
+        }
+        for (int e = threadIdx.x; e < nv; e += blockDim.x) {
+            const int i = e % n, j = (e / n) % n, k = e / (n * n);
+            const long long g = (long long)k * G.L.plane + (long long)j * G.L.pitch + i;
+            kx[e] = G.L.kx[g];
+            ky[e] = G.L.ky[g];
+            kz[e] = G.L.kz[g];
+            dv[e] = G.L.dinv[g];
+            b[e] = l == s ? G.b[g] : V(0);
+            x[e] = V(0);
+            t1[e] = V(0);
+        }
+    }
+    double *y = (double *)(smem + off);
+    __syncthreads();
+    const Team T{0, 1, nullptr};
+    persistent_cycle(T, (const LevBuf<V, K> *)lb, cc, s, last, Lf, m, 0, y);
+    const LevBuf<V, K> &G = lv[s];
+    const int n = G.L.n, mi = n - 2, np = mi * mi * mi;
+    for (int u = threadIdx.x; u < np; u += blockDim.x) {
+        const int i = 1 + u % mi, j = 1 + (u / mi) % mi, k = 1 + u / (mi * mi);
+        G.x[(long long)k * G.L.plane + (long long)j * G.L.pitch + i] = lb[s].x[(k * n + j) * n + i];
     }
 }
 

@@ -32,7 +32,7 @@ class Options(ctypes.Structure):
                 ("check_every", ctypes.c_int32), ("coarse_solver", ctypes.c_int32),
                 ("coarse_rtol", ctypes.c_double), ("coarse_max_it", ctypes.c_int32),
                 ("flexible", ctypes.c_int32), ("switch2_n", ctypes.c_int32),
-                ("galerkin", ctypes.c_int32)]
+                ("galerkin", ctypes.c_int32), ("persistent_lds", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -102,6 +102,8 @@ def lib():
     L.gmg_get_level_stencil.argtypes = [P, I32, P]
     L.gmg_get_level_stencil.restype = st
     L.gmg_get_level_interval.argtypes = [P, I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    L.gmg_persistent_lds_bytes.argtypes = [P]
+    L.gmg_persistent_lds_bytes.restype = ctypes.c_uint64
     L.gmg_get_level_interval.restype = st
     L.gmg_profile_start.argtypes = [P]
     L.gmg_profile_start.restype = st
@@ -147,7 +149,7 @@ class Solver:
     def __init__(self, kx, ky, kz, *, levels=None, precision="fp64", switch_n=0, coarse_rule="arithmetic",
                  cheb_degree=2, cheb_lo=0.25, cheb_hi=2.0, coeff_is_log=False, check_every=0,
                  persistent_wgs=1, coarse_solver="exact", coarse_rtol=1e-4, coarse_max_it=500, flexible=False,
-                 switch2_n=0, galerkin=0):
+                 switch2_n=0, galerkin=0, persistent_lds=True):
         L = lib()
         n = int(kx.shape[0])
         self.n = n
@@ -171,6 +173,7 @@ class Solver:
         o.flexible = 1 if flexible else 0
         o.switch2_n = int(switch2_n)
         o.galerkin = int(galerkin)
+        o.persistent_lds = 1 if persistent_lds else 0
         self.options = o
         self.levels = o.levels
         self._h = ctypes.c_void_p()
@@ -321,6 +324,11 @@ class Solver:
         if s != OK:
             self._err(s, "gmg_get_level_coefficients")
         return kx, ky, kz
+
+    @property
+    def persistent_lds_bytes(self):
+        """LDS bytes of the one-workgroup persistent kernel, 0 when it runs from HBM/L2."""
+        return int(lib().gmg_persistent_lds_bytes(self._h))
 
     def level_interval(self, level):
         """Chebyshev interval (lo, hi) of D^-1 A the smoother uses on `level`."""

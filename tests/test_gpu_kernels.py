@@ -94,12 +94,18 @@ def test_vcycle_and_switch_invariance(n, levels):
     assert rel_max(base, ref) <= 1e-12, rel_max(base, ref)
     sizes = sorted({H.level_n(l) for l in range(1, levels)})
     for sw in sizes:
-        for wgs in (1, 4, 8):
-            sp = gmg.Solver(*[to_gpu(a) for a in k], levels=levels, switch_n=sw, persistent_wgs=wgs)
+        for wgs, lds in ((1, True), (1, False), (4, True), (8, True)):
+            sp = gmg.Solver(*[to_gpu(a) for a in k], levels=levels, switch_n=sw, persistent_wgs=wgs,
+                            persistent_lds=lds)
             z = to_np(sp.vcycle(to_gpu(r)))
             d = rel_max(z, base)
-            say(f"    switch {sw} team {wgs}: max rel diff vs grid path {d:.3e} (bitwise: {np.array_equal(z, base)})")
+            say(f"    switch {sw} team {wgs} lds {sp.persistent_lds_bytes}: max rel diff vs grid path {d:.3e} "
+                f"(bitwise: {np.array_equal(z, base)})")
             assert np.array_equal(z, base)
+            if wgs > 1 or not lds:
+                assert sp.persistent_lds_bytes == 0
+            elif sw <= 9:  # levels 9^3 and below always fit in 64 KiB of LDS
+                assert sp.persistent_lds_bytes > 0
             sp.close()
     # multi-stage: a team on the middle levels, one workgroup below switch2
     if len(sizes) >= 3:
@@ -160,3 +166,24 @@ def test_errors_are_reported():
     assert info["status"] == "GMG_OK" and info["iterations"] == 0 and float(x.abs().max()) == 0.0
     with pytest.raises(gmg.GmgError):
         s.solve(to_gpu(np.full((n, n, n), np.nan)))
+
+
+@pytest.mark.parametrize("n,levels", [(33, 5), (129, 7)])
+def test_mixed_persistent_lds_identical(n, levels):
+    """MIXED V-cycle: the agglomerated levels in LDS, in HBM/L2 and on the grid
+    path give bitwise the same z; and the PCG iterates agree."""
+    k, s, H = make(n, levels, precision="mixed")
+    r = rand_vec(n, 4)
+    base = to_np(s.vcycle(to_gpu(r)))
+    f = to_gpu(inputs.uniform_rhs(n, 6))
+    xb, ib = s.solve(f, rtol=1e-8)
+    for sw in (9, 17):
+        for lds in (True, False):
+            sp = gmg.Solver(*[to_gpu(a) for a in k], levels=levels, precision="mixed", switch_n=sw,
+                            persistent_lds=lds)
+            z = to_np(sp.vcycle(to_gpu(r)))
+            say(f"    mixed switch {sw} lds bytes {sp.persistent_lds_bytes}: bitwise {np.array_equal(z, base)}")
+            assert np.array_equal(z, base)
+            x, info = sp.solve(f, rtol=1e-8)
+            assert info["iterations"] == ib["iterations"] and torch.equal(x, xb)
+            sp.close()

@@ -77,8 +77,10 @@ typedef struct {
                                onto one XCD when it fits, with a device-wide barrier
                                between sweeps; results are identical for any team size */
     int32_t precision;      /* gmg_precision.  MIXED: V-cycle in FP32 with BF16 link
-                               coefficients (round-to-nearest-even from FP64), outer
-                               PCG, dot products and coarsest Cholesky in FP64 */
+                               coefficients (round-to-nearest-even from FP64; Galerkin
+                               levels FP32); x, r, q = A p, the dot products and the
+                               coarsest Cholesky in FP64; the search direction p is
+                               formed in FP64 and stored in FP32 */
     int32_t coarse_rule;    /* gmg_coarse_rule, default ARITHMETIC */
     int32_t coeff_is_log;   /* 1: kx/ky/kz hold ln k (natural log) instead of k */
     int32_t check_every;    /* host reads the convergence flag every this many PCG
@@ -120,11 +122,17 @@ typedef struct {
  * levels = log2(n-1) (coarsest 3^3), FP64, no persistent switch. */
 void gmg_default_options(gmg_options *opt, int32_t n);
 
-/* Build the hierarchy: copy k (device, FP64, face shapes) into the library's
- * padded layout, derive the coarse coefficients level by level, the BF16
- * copies (MIXED), and the Cholesky factor of the dense coarsest operator.
- * Allocates every device buffer the solver needs (no allocation happens in
- * gmg_solve).  On success *out owns them until gmg_destroy. */
+/* Build the hierarchy (the per-level operators, smoothers and transfers of
+ * Sec. 2.1.1): copy k (device, FP64, face shapes) into the library's padded
+ * layout, derive the coarse coefficients level by level (re-discretized, or
+ * R A P from the galerkin level on, with each Galerkin level's Chebyshev
+ * interval), the BF16 copies (MIXED), and the Cholesky factor of the dense
+ * coarsest operator.  Allocates every device buffer the solver needs (no
+ * allocation happens in gmg_solve).  On success *out owns them until
+ * gmg_destroy; on failure *out is NULL and nothing stays allocated.
+ * Errors: GMG_ERR_ARG (null pointer, option out of range), GMG_ERR_DIMS,
+ * GMG_ERR_COEFF (bad k, or a coarsest operator that is not positive
+ * definite), GMG_ERR_NOMEM, GMG_ERR_HIP. */
 gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky, const double *kz,
                       void *stream, gmg_handle **out);
 
@@ -154,9 +162,13 @@ gmg_status gmg_adjoint_gradient(gmg_handle *h, const double *phi, const double *
                                 double *g_y, double *g_z, double *lambda, double rtol, int32_t max_it,
                                 gmg_info *info);
 
-/* ---- test hooks: each runs one step of the path on level `level`, in the
- * handle's V-cycle precision (FP32/BF16 in MIXED mode, with FP64 in and out).
- * Vectors are (N_l, N_l, N_l) device arrays. */
+/* ---- test hooks: each runs one step of the V-cycle of Sec. 2.1.1 (Alg. 1:
+ * smoothing, residual restriction, prolongation and correction, coarse solve)
+ * on level `level`, in the handle's V-cycle precision (FP32/BF16 in MIXED
+ * mode, with FP64 in and out).  Vectors are (N_l, N_l, N_l) device arrays
+ * (natural layout, boundary entries ignored on input, 0 on output).  They use
+ * the handle's level buffers, so they must not overlap a solve on the same
+ * handle.  GMG_ERR_ARG for a null vector or a level out of range. */
 int32_t gmg_level_n(const gmg_handle *h, int32_t level);   /* N_l, or -1 */
 /* y = A_l x (level 0 with use_fp64 = 1 is the outer FP64 operator). */
 gmg_status gmg_apply_operator(gmg_handle *h, int32_t level, int32_t use_fp64, const double *x, double *y);
@@ -167,7 +179,8 @@ gmg_status gmg_debug_residual_restrict(gmg_handle *h, int32_t level, const doubl
                                        double *b_coarse);
 /* x += P e, e on level+1 (trilinear). */
 gmg_status gmg_debug_prolong(gmg_handle *h, int32_t level, const double *e_coarse, double *x);
-/* x = A_c^-1 b on the coarsest level (FP64 Cholesky). */
+/* Coarsest-level solve: x = A_c^-1 b by the FP64 Cholesky factor, or (coarse_solver
+ * = 1) the inexact Jacobi-CG of the truncated hierarchy. */
 gmg_status gmg_debug_coarse_solve(gmg_handle *h, const double *b, double *x);
 /* z = B r, one V-cycle on level 0 (uses the handle's switch level). */
 gmg_status gmg_debug_vcycle(gmg_handle *h, const double *r, double *z);
@@ -220,10 +233,11 @@ gmg_status gmg_profile_stop(gmg_handle *h);   /* stop recording, wait for the st
 gmg_status gmg_profile_get(gmg_handle *h, int32_t kclass, int32_t *launches, double *total_ms);
 const char *gmg_kernel_class_name(int32_t kclass);
 
-/* Plain device-to-device copy of `bytes` (a multiple of 16, at most 2^35) with a
- * streaming kernel (one 16-byte element per thread) on `stream`; returns after
- * it completes; GMG_ERR_ARG for null pointers or an invalid size.  Used to calibrate
- * the profiler's HBM byte counters and to measure achievable copy bandwidth. */
+/* Plain device-to-device copy of `bytes` (a multiple of 16) with a streaming
+ * kernel (one 16-byte element per thread) on `stream`; returns after it
+ * completes; GMG_ERR_ARG for null pointers, a size that is not a multiple of
+ * 16 or needs more than 2^31 - 1 workgroups.  Used to calibrate the
+ * profiler's HBM byte counters and to measure achievable copy bandwidth. */
 gmg_status gmg_calibration_copy(void *dst, const void *src, uint64_t bytes, void *stream);
 
 void gmg_destroy(gmg_handle *h);

@@ -577,7 +577,6 @@ gmg_status vcycle(gmg_handle *h, const int *skip, bool want_dot, int *nparts, bo
     const int s = h->s_persist;  // levels 0..s-1 on the grid path
     for (int l = 0; l < s; ++l) {
         STCHK((smooth_grid<V, K>(h, l, true, (l == 0 && mx && !b_ready) ? h->R : nullptr, nullptr, skip, nullptr)));
-        LevelHost &f = h->lv[l], &c = h->lv[l + 1];
         STCHK((residual_restrict<V, K>(h, l, skip)));
     }
     STCHK((coarse_part<V, K>(h, skip)));
@@ -973,8 +972,6 @@ gmg_status galerkin_lambda(gmg_handle *h, int l, double *lam) {
 }
 
 gmg_status load_coefficients(gmg_handle *h, const double *kx, const double *ky, const double *kz) {
-    const double t0 = 0;
-    (void)t0;
     LevelHost &l0 = h->lv[0];
     // level 0 (+ validation)
     gmg::k_faces_in<<<blocks_for((long long)l0.n * l0.n * l0.n, 256), 256, 0, h->stream>>>(
@@ -1135,13 +1132,13 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
     h->opt = o;
     h->stream = (hipStream_t)stream;
     h->L = o.levels;
+    hipEvent_t t0 = nullptr, t1 = nullptr;  // setup timing
     auto bail = [&](gmg_status s) {
-        std::string e = h->err;
+        if (t0) (void)hipEventDestroy(t0);
+        if (t1) (void)hipEventDestroy(t1);
         gmg_destroy(h);
-        (void)e;
         return s;
     };
-    hipEvent_t t0, t1;
     if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess ||
         hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess)
         return bail(GMG_ERR_HIP);
@@ -1341,8 +1338,11 @@ gmg_status gmg_set_coefficients(gmg_handle *h, const double *kx, const double *k
     if (!h || !kx || !ky || !kz) return GMG_ERR_ARG;
     hipEvent_t t0, t1;
     HIPCHK(hipEventCreate(&t0));
-    HIPCHK(hipEventCreate(&t1));
-    HIPCHK(hipEventRecord(t0, h->stream));
+    if (hipEventCreate(&t1) != hipSuccess) {
+        (void)hipEventDestroy(t0);
+        return fail(h, GMG_ERR_HIP, "hipEventCreate failed");
+    }
+    (void)hipEventRecord(t0, h->stream);
     gmg_status s = load_coefficients(h, kx, ky, kz);
     (void)hipEventRecord(t1, h->stream);
     (void)hipEventSynchronize(t1);
@@ -1515,9 +1515,6 @@ gmg_status gmg_apply_operator(gmg_handle *h, int32_t level, int32_t use_fp64, co
 gmg_status gmg_debug_smooth(gmg_handle *h, int32_t level, const double *b, double *x, int32_t x0_zero) {
     STCHK(check_level(h, level));
     if (!b || !x) return fail(h, GMG_ERR_ARG, "null vector");
-    if (mixed(h) && level == 0) {
-        // the finest FP32 level has its own b buffer; FP64 mode aliases b to r
-    }
     return mixed(h) ? hook_smooth<float, bf16>(h, level, b, x, x0_zero)
                     : hook_smooth<double, double>(h, level, b, x, x0_zero);
 }

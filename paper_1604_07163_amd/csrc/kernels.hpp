@@ -45,23 +45,28 @@ template <typename T>
 __device__ __forceinline__ T ldnt(const T *p) { return __builtin_nontemporal_load(p); }
 template <typename T>
 __device__ __forceinline__ void stnt(T v, T *p) { __builtin_nontemporal_store(v, p); }
+// Pair forms: one 8- or 16-byte access (the address must be aligned to its size).
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ float2 ldnt(const float2 *p) {
-    const float *q = (const float *)p;
-    return make_float2(__builtin_nontemporal_load(q), __builtin_nontemporal_load(q + 1));
+    const f32x2 v = __builtin_nontemporal_load((const f32x2 *)p);
+    return make_float2(v.x, v.y);
 }
 __device__ __forceinline__ double2 ldnt(const double2 *p) {
-    const double *q = (const double *)p;
-    return make_double2(__builtin_nontemporal_load(q), __builtin_nontemporal_load(q + 1));
+    const f64x2 v = __builtin_nontemporal_load((const f64x2 *)p);
+    return make_double2(v.x, v.y);
 }
 __device__ __forceinline__ void stnt(float2 v, float2 *p) {
-    float *q = (float *)p;
-    __builtin_nontemporal_store(v.x, q);
-    __builtin_nontemporal_store(v.y, q + 1);
+    f32x2 w;
+    w.x = v.x;
+    w.y = v.y;
+    __builtin_nontemporal_store(w, (f32x2 *)p);
 }
 __device__ __forceinline__ void stnt(double2 v, double2 *p) {
-    double *q = (double *)p;
-    __builtin_nontemporal_store(v.x, q);
-    __builtin_nontemporal_store(v.y, q + 1);
+    f64x2 w;
+    w.x = v.x;
+    w.y = v.y;
+    __builtin_nontemporal_store(w, (f64x2 *)p);
 }
 template <typename T>
 struct Vec2;
@@ -1247,16 +1252,16 @@ __global__ __launch_bounds__(NT_FLAT) void k_update_r(Rows R, double *__restrict
     double acc = 0.0;
     long long e;
     if (row_item(R, e)) {
-        double2 rv = *(const double2 *)(r + e);
-        const double2 qv = *(const double2 *)(q + e);
+        double2 rv = ldnt((const double2 *)(r + e));
+        const double2 qv = ldnt((const double2 *)(q + e));
         rv.x = fmaT(-a, qv.x, rv.x);
         rv.y = fmaT(-a, qv.y, rv.y);
-        *(double2 *)(r + e) = rv;
+        stnt(rv, (double2 *)(r + e));
         if (b32) {
             B2 bv;
             bv.x = (B)rv.x;
             bv.y = (B)rv.y;
-            *(B2 *)(b32 + e) = bv;
+            stnt(bv, (B2 *)(b32 + e));
         }
         acc = fmaT(rv.x, rv.x, acc);
         acc = fmaT(rv.y, rv.y, acc);
@@ -1280,17 +1285,17 @@ __global__ __launch_bounds__(NT_FLAT) void k_update_xp(Rows R, double *__restric
     typedef typename Vec2<PT>::type P2;
     long long e;
     if (row_item(R, e)) {
-        const P2 pv = *(const P2 *)(p + e);
-        double2 xv = *(const double2 *)(x + e);
+        const P2 pv = ldnt((const P2 *)(p + e));
+        double2 xv = ldnt((const double2 *)(x + e));
         xv.x = fmaT(a, (double)pv.x, xv.x);
         xv.y = fmaT(a, (double)pv.y, xv.y);
-        *(double2 *)(x + e) = xv;
+        stnt(xv, (double2 *)(x + e));
         if (upd_p) {
-            const Z2 zv = *(const Z2 *)(z + e);
+            const Z2 zv = ldnt((const Z2 *)(z + e));
             P2 pn;
             pn.x = (PT)fmaT(bta, (double)pv.x, (double)zv.x);
             pn.y = (PT)fmaT(bta, (double)pv.y, (double)zv.y);
-            *(P2 *)(p + e) = pn;
+            stnt(pn, (P2 *)(p + e));
         }
     }
 }

@@ -56,6 +56,7 @@ struct gmg_handle {
     double *F = nullptr, *X = nullptr, *R = nullptr, *P = nullptr, *Q = nullptr;
     float *P32 = nullptr;  // MIXED: the search direction, stored in FP32
     double *partial = nullptr;
+    double *partial2 = nullptr;   // first-stage sums of a large reduction (2 x NB_CHUNKS)
     int npartial = 0;
     PcgState *st = nullptr;       // device
     PcgState *st_in = nullptr;    // pinned host (uploads)
@@ -602,8 +603,27 @@ gmg_status vcycle_any(gmg_handle *h, const int *skip, bool want_dot, int *nparts
                     : vcycle<double, double>(h, skip, want_dot, nparts);
 }
 
+// Sums `count` per-workgroup partials (two arrays for the paired stages) into
+// the PCG state.  Above kChunkedFrom partials a first stage spreads the loads
+// over NB_CHUNKS workgroups (a single workgroup summing 2.6e5 partials, the
+// row kernels' count at 513^3, takes 50 us).
+constexpr int kChunkedFrom = 4096;
 gmg_status finalize(gmg_handle *h, int count, int stage, PcgState *state) {
-    gmg::k_finalize<<<1, gmg::NT_FIN, 0, h->stream>>>(h->partial, count, stage, state ? state : h->st);
+    PcgState *st = state ? state : h->st;
+    const double *src = h->partial;
+    if (count > kChunkedFrom) {
+        const bool two = stage == gmg::ST_BETA_FLEX || stage == gmg::ST_C_INIT || stage == gmg::ST_C_RR;
+        const bool gated = !(stage == gmg::ST_BB || stage == gmg::ST_RR0 || stage == gmg::ST_RHO0 ||
+                             stage == gmg::ST_TT);
+        const int chunk = (count + gmg::NB_CHUNKS - 1) / gmg::NB_CHUNKS;
+        const int nb = (count + chunk - 1) / chunk;
+        gmg::k_reduce_chunks<<<nb, 256, 0, h->stream>>>(h->partial, count, chunk, two ? 1 : 0, h->partial2,
+                                                        gated ? &st->done : nullptr);
+        LAUNCHCHK();
+        src = h->partial2;
+        count = nb;
+    }
+    gmg::k_finalize<<<1, gmg::NT_FIN, 0, h->stream>>>(src, count, stage, st);
     LAUNCHCHK();
     return GMG_OK;
 }
@@ -1207,6 +1227,7 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
         if (nfaces_blocks > h->npartial) h->npartial = (int)nfaces_blocks;
     }
     ALLOC(h->partial, 2LL * h->npartial);  // two partial arrays for paired sums
+    ALLOC(h->partial2, 2LL * gmg::NB_CHUNKS);
     ALLOC(h->st, 1LL);
     ALLOC(h->cst, 1LL);
     ALLOC(h->bar, 1LL);

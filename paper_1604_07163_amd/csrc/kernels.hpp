@@ -1440,6 +1440,27 @@ enum Stage {
 
 // Sum `count` partials in a fixed order and advance the PCG state.
 constexpr int NT_FIN = 1024;
+constexpr int NB_CHUNKS = 256;  // workgroups of the first stage of a large reduction
+// First stage of a large reduction: workgroup b sums the contiguous chunk
+// [b*chunk, (b+1)*chunk) of p (and, with two, of the second array p + count)
+// in a fixed order into out[b] (out[gridDim.x + b]); k_finalize then sums the
+// gridDim.x values.  Skipped, like the finalize it feeds, once *skip is set.
+__global__ __launch_bounds__(256) void k_reduce_chunks(const double *__restrict__ p, int count, int chunk, int two,
+                                                       double *__restrict__ out, const int *__restrict__ skip) {
+    if (skip && *skip) return;
+    const int lo = blockIdx.x * chunk, hi = min(count, lo + chunk);
+    double acc = 0.0, acc2 = 0.0;
+    for (int w = lo + (int)threadIdx.x; w < hi; w += 256) {
+        acc += p[w];
+        if (two) acc2 += p[count + w];
+    }
+    const double s = block_sum<256>(acc);
+    if (threadIdx.x == 0) out[blockIdx.x] = s;
+    if (two) {
+        const double s2 = block_sum<256>(acc2);
+        if (threadIdx.x == 0) out[gridDim.x + blockIdx.x] = s2;
+    }
+}
 // This thread's share of count partial sums (elements threadIdx.x + m*NT_FIN),
 // eight loads in flight at a time, added in a fixed order.
 __device__ __forceinline__ double fin_thread_sum(const double *__restrict__ p, int count) {

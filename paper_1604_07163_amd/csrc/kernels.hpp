@@ -1300,10 +1300,6 @@ __global__ __launch_bounds__(NT_FLAT) void k_update_xp(Rows R, double *__restric
     }
 }
 
-__global__ void k_clear_pending(PcgState *st) {
-    if (threadIdx.x == 0) st->x_pending = 0;
-}
-
 // p = z + beta p   (z FP64 or FP32; p FP64 or, MIXED, FP32)
 template <typename Z, typename PT>
 __global__ __launch_bounds__(NT_FLAT) void k_update_p(Rows R, PT *__restrict__ p, const Z *__restrict__ z,
@@ -1479,8 +1475,11 @@ __global__ __launch_bounds__(NT_FIN) void k_finalize(const double *__restrict__ 
                                                      PcgState *__restrict__ st) {
     if ((stage == ST_ALPHA || stage == ST_RR || stage == ST_BETA || stage == ST_BETA_FLEX || stage == ST_C_INIT ||
          stage == ST_C_ALPHA || stage == ST_C_RR) &&
-        st->done)
+        st->done) {
+        // an iteration enqueued after the stop: its x update must not run
+        if (stage == ST_ALPHA && threadIdx.x == 0) st->x_pending = 0;
         return;
+    }
     const bool two = stage == ST_BETA_FLEX || stage == ST_C_INIT || stage == ST_C_RR;
     const double sum = block_sum<NT_FIN>(fin_thread_sum(partial, count));
     const double sum2 = two ? block_sum<NT_FIN>(fin_thread_sum(partial + count, count)) : 0.0;
@@ -1533,6 +1532,7 @@ __global__ __launch_bounds__(NT_FIN) void k_finalize(const double *__restrict__ 
         if (!(sum > 0.0) || sum > 1.7e308) {  // p.Ap <= 0, NaN or Inf
             st->status = 7;
             st->done = 1;
+            st->x_pending = 0;
         } else {
             st->alpha = st->rho / sum;
             st->x_pending = 1;

@@ -43,6 +43,7 @@ struct LevelHost {
     Tiling til{};    // V-cycle stencil kernels
     Tiling til64{};  // FP64 outer operator (residual)
     Tiling til2{};   // FP64 outer apply, two points per lane
+    Tiling tilp{};   // pre-smoothing kernel, two rows per thread
     gmg::Rows rows{};
 };
 
@@ -126,11 +127,12 @@ int env_int(const char *name, int dflt) {
 
 constexpr int kMinChunk = 8;
 
-// width: x extent of a tile (TX, or TX2 for the two-points-per-lane apply)
-Tiling make_tiling(int n, int target, int width = gmg::TX) {
+// width: x extent of a tile (TX, or TX2 for the two-points-per-lane apply);
+// rows: y extent (TY, or TY_PRE for the two-rows-per-thread pre-smoothing)
+Tiling make_tiling(int n, int target, int width = gmg::TX, int rows = gmg::TY) {
     Tiling t;
     t.tiles_x = (n - 2) / width + 1;  // covers i = 0 .. n-2
-    t.tiles_y = (n - 2 + gmg::TY - 1) / gmg::TY;
+    t.tiles_y = (n - 2 + rows - 1) / rows;
     const int planes = n - 2;
     int nch = (target + t.tiles_x * t.tiles_y - 1) / (t.tiles_x * t.tiles_y);
     if (nch > planes / kMinChunk) nch = planes / kMinChunk;
@@ -356,12 +358,13 @@ gmg_status smooth_grid(gmg_handle *h, int l, bool from_zero, const double *r64_c
     if (from_zero && !r64_cvt && cc.m >= 2) {
         // x1 and x2 in one sweep; x1 is stored only when a third step needs it
         Prof pf(h, GMG_K_CHEB_PRE2, fin);
+        const dim3 gp(lh.tilp.nblocks);
         if (cc.m == 2)
-            gmg::k_cheb_pre2<V, K, false><<<grid, blk, 0, h->stream>>>(L, lh.til, b, bufs[0], nullptr, cc.cfirst,
-                                                                        cc.c1[1], cc.c2[1], skip);
+            gmg::k_cheb_pre2<V, K, false><<<gp, blk, 0, h->stream>>>(L, lh.tilp, b, bufs[0], nullptr, cc.cfirst,
+                                                                      cc.c1[1], cc.c2[1], skip);
         else
-            gmg::k_cheb_pre2<V, K, true><<<grid, blk, 0, h->stream>>>(L, lh.til, b, bufs[0], bufs[1], cc.cfirst,
-                                                                       cc.c1[1], cc.c2[1], skip);
+            gmg::k_cheb_pre2<V, K, true><<<gp, blk, 0, h->stream>>>(L, lh.tilp, b, bufs[0], bufs[1], cc.cfirst,
+                                                                     cc.c1[1], cc.c2[1], skip);
         LAUNCHCHK();
         cur = 0;
         prev = 1;
@@ -1182,6 +1185,7 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
         lh.til = make_tiling(n, env_int("GMG_TARGET_WGS_V", 1 << 20));
         lh.til64 = make_tiling(n, t64);
         lh.til2 = make_tiling(n, t64, gmg::TX2);
+        lh.tilp = make_tiling(n, env_int("GMG_TARGET_WGS_V", 1 << 20), gmg::TX, gmg::TY_PRE);
         lh.rows = make_rows(n, lh.pitch, lh.plane);
         lh.g27 = o.galerkin > 0 && l >= o.galerkin;
         n = (n - 1) / 2 + 1;

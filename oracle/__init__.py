@@ -6,7 +6,10 @@ links or calls anything in this package, and this package imports nothing from
 the GPU library.
 
 The arithmetic lives in ``gmg_oracle.c`` (plain C loops, FP64); this module only
-builds it with gcc and marshals numpy arrays through ctypes.
+builds it with gcc and marshals numpy arrays through ctypes.  Hierarchy(...,
+precision="mixed") gives the reduced-precision preconditioner of the mixed
+mode (rounded coefficients, FP32 V-cycle input/output and search direction),
+evaluated in FP64.
 
 Array conventions (C order, x fastest), N vertices per side, h = 1/(N-1):
   vertex vectors  (N, N, N)
@@ -91,6 +94,13 @@ def lib():
         L.or_pcg.restype = I
         L.or_adjoint_gradient.argtypes = [P, P, P, P, P, P, P, D, I, ctypes.POINTER(I)]
         L.or_adjoint_gradient.restype = I
+        L.or_set_mixed.argtypes = [P]
+        L.or_set_mixed.restype = I
+        L.or_last_restarts.argtypes = [P]
+        L.or_last_restarts.restype = I
+        L.or_round_bf16_raw.argtypes = [ctypes.c_size_t, P, P]
+        L.or_round_f32.argtypes = [D]
+        L.or_round_f32.restype = D
         _lib = L
     return _lib
 
@@ -171,6 +181,14 @@ def cheb(kx, ky, kz, b, x0=None, degree=2, lo=0.25, hi=2.0):
     return x
 
 
+def round_bf16(a):
+    """Round FP64 values to bfloat16 (8 significant bits, ties to even), as FP64."""
+    a = _f64(a)
+    out = np.empty_like(a)
+    lib().or_round_bf16_raw(a.size, _p(a), _p(out))
+    return out
+
+
 def apply27(a27, u):
     """(A u) for a 27-point stencil a27 of shape (N,N,N,27)."""
     u = _f64(u)
@@ -239,11 +257,18 @@ class Hierarchy:
 
     def __init__(self, kx, ky, kz, levels: int, degree: int = 2, lo: float = 0.25, hi: float = 2.0,
                  rule: int = RULE_ARITHMETIC, coarse_solver: int = 0, coarse_rtol: float = 1e-4,
-                 coarse_max_it: int = 500, galerkin: int = 0):
+                 coarse_max_it: int = 500, galerkin: int = 0, precision: str = "fp64"):
         """coarse_solver 0: exact Cholesky on the coarsest level; 1: truncated
         hierarchy whose coarsest level is solved by Jacobi-CG to coarse_rtol.
         galerkin g > 0: levels l >= g use R A P (True = 1: all coarse levels);
-        levels below g keep re-discretized link coefficients."""
+        levels below g keep re-discretized link coefficients.
+        precision "mixed": the reduced-precision preconditioner (V-cycle
+        coefficients rounded to bfloat16 / FP32, FP32 V-cycle input and output
+        and search direction, true-residual restarts), still computed in FP64;
+        apply(), smooth() and vcycle() then use the rounded coefficients, the
+        outer CG the FP64 ones."""
+        if precision not in ("fp64", "mixed"):
+            raise ValueError("precision must be 'fp64' or 'mixed'")
         self._kx, self._ky, self._kz = _f64(kx), _f64(ky), _f64(kz)
         self.n = self._kx.shape[0]
         self.levels = levels
@@ -253,6 +278,12 @@ class Hierarchy:
         if st != 0:
             raise OracleError(st)
         self._h = h
+        self.precision = precision
+        if precision == "mixed":
+            st = lib().or_set_mixed(h)
+            if st != 0:
+                self.close()
+                raise OracleError(st)
 
     def close(self):
         if self._h:
@@ -328,7 +359,8 @@ class Hierarchy:
         if st in (1, 4):
             raise OracleError(st)
         return x, {"status": STATUS[st], "iterations": its.value, "rel_res": rr.value,
-                   "rel_res_true": rt.value, "coarse_iterations": cits.value}
+                   "rel_res_true": rt.value, "coarse_iterations": cits.value,
+                   "restarts": lib().or_last_restarts(self._h)}
 
     def adjoint_gradient(self, phi, dl_dphi, rtol=1e-12, max_it=200):
         """Return (g_x, g_y, g_z, lambda, info): g = dL/d(ln k) on the face arrays."""

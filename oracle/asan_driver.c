@@ -19,6 +19,9 @@ int or_smooth(void *hp, int l, const double *b, double *x, int x0_zero);
 int or_level_n(void *hp, int l);
 int or_get_a27(void *hp, int l, double *out);
 int or_level_interval(void *hp, int l, double *lo, double *hi);
+int or_set_mixed(void *hp);
+int or_last_restarts(void *hp);
+void or_round_bf16_raw(size_t count, const double *in, double *out);
 
 static double urand(unsigned *s)
 {
@@ -26,7 +29,7 @@ static double urand(unsigned *s)
     return (double)(*s >> 8) / 16777216.0;
 }
 
-static int run(int n, int levels, int rule, int coarse_solver, int galerkin, int flexible)
+static int run(int n, int levels, int rule, int coarse_solver, int galerkin, int flexible, int mixed)
 {
     size_t nv = (size_t)n * n * n, nx = (size_t)n * n * (n - 1);
     double *kx = malloc(nx * sizeof(double)), *ky = malloc(nx * sizeof(double)),
@@ -48,6 +51,11 @@ static int run(int n, int levels, int rule, int coarse_solver, int galerkin, int
     int st = or_create3(n, levels, 2, 0.25, 2.0, rule, coarse_solver, 1e-4, 500, galerkin, kx, ky, kz, &H);
     if (st != 0) {
         fprintf(stderr, "create failed %d (n=%d levels=%d)\n", st, n, levels);
+        return 1;
+    }
+    if (mixed && or_set_mixed(H) != 0) {
+        fprintf(stderr, "mixed mode refused (n=%d levels=%d)\n", n, levels);
+        or_destroy(H);
         return 1;
     }
     int its = 0;
@@ -73,8 +81,9 @@ static int run(int n, int levels, int rule, int coarse_solver, int galerkin, int
     int its2 = 0;
     if (!coarse_solver)
         or_adjoint_gradient(H, x, x, gx, gy, gz, lam, 1e-8, 300, &its2);
-    printf("n=%d levels=%d rule=%d coarse=%d galerkin=%d: status %d, %d its, true %.2e\n", n, levels, rule,
-           coarse_solver, galerkin, st, its, rt);
+    printf("n=%d levels=%d rule=%d coarse=%d galerkin=%d mixed=%d: status %d, %d its, %d restarts, true %.2e\n",
+           n, levels, rule, coarse_solver, galerkin, mixed, st, its, or_last_restarts(H), rt);
+    or_round_bf16_raw(nx, kx, gx);
     or_destroy(H);
     free(kx);
     free(ky);
@@ -92,11 +101,13 @@ static int run(int n, int levels, int rule, int coarse_solver, int galerkin, int
 int main(void)
 {
     int bad = 0;
-    bad |= run(3, 1, 0, 0, 0, 0);
-    bad |= run(9, 3, 1, 0, 0, 0);
-    bad |= run(17, 4, 0, 0, 1, 0);
-    bad |= run(17, 4, 0, 0, 2, 0);
-    bad |= run(17, 2, 0, 1, 0, 1);
-    bad |= run(33, 5, 0, 0, 0, 0);
+    for (int mixed = 0; mixed <= 1; mixed++) {
+        bad |= run(3, 1, 0, 0, 0, 0, mixed);
+        bad |= run(9, 3, 1, 0, 0, 0, mixed);
+        bad |= run(17, 4, 0, 0, 1, 0, mixed);
+        bad |= run(17, 4, 0, 0, 2, 0, mixed);
+        bad |= run(17, 2, 0, 1, 0, 1, mixed);
+        bad |= run(33, 5, 0, 0, 0, 0, mixed);
+    }
     return bad;
 }

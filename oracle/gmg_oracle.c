@@ -30,7 +30,9 @@
  * closed forms, invariants or brute force (sine-mode eigenvalues, an exact
  * quadratic solution, dense assembly, the Chebyshev polynomial, the adjoint
  * of restriction/prolongation, dense two-grid composition, finite
- * differences).  No routine is "parity unpinned".
+ * differences; for the reduced-precision mode: exact rational bfloat16
+ * rounding and a dense composition from the rounded level matrices).  No
+ * routine is "parity unpinned".
  */
 #include <math.h>
 #include <stdint.h>
@@ -57,6 +59,41 @@ static double val(int n, const double *u, int i, int j, int k)
     return interior(n, i, j, k) ? u[vid(n, i, j, k)] : 0.0;
 }
 static size_t nvert(int n) { return (size_t)n * n * n; }
+
+/* ------------------------------------------------------------------------ */
+/* Rounding to the storage formats of the reduced-precision mode (an        */
+/* addition to the paper's method).  Both round to nearest, ties to even,   */
+/* straight from the FP64 value:                                            */
+/*   FP32      24 significant bits (the C conversion double -> float);      */
+/*   bfloat16   8 significant bits, the exponent range of FP32.             */
+/* or_round_bf16 covers finite values whose magnitude lies in the normal    */
+/* range of bfloat16, [2^-126, 2^128) after rounding; or_bf16_ok tells      */
+/* whether a value does.                                                    */
+/* ------------------------------------------------------------------------ */
+double or_round_f32(double v) { return (double)(float)v; }
+
+double or_round_bf16(double v)
+{
+    if (v == 0.0 || !isfinite(v))
+        return v;
+    int e;
+    double m = frexp(v, &e); /* v = m 2^e with 1/2 <= |m| < 1 */
+    /* m 2^8 has 8 bits before the binary point; nearbyint rounds the rest
+     * away in the default mode, to nearest with ties to even */
+    return ldexp(nearbyint(ldexp(m, 8)), e - 8);
+}
+
+int or_bf16_ok(double v)
+{
+    double r = or_round_bf16(fabs(v));
+    return isfinite(v) && r >= ldexp(1.0, -126) && r < ldexp(1.0, 128);
+}
+
+void or_round_bf16_raw(size_t count, const double *in, double *out)
+{
+    for (size_t i = 0; i < count; i++)
+        out[i] = or_round_bf16(in[i]);
+}
 
 /* ------------------------------------------------------------------------ */
 /* Operator (Eq. 2, 7-point finite differences as in Sec. 4.1, Disc. A):    */
@@ -324,7 +361,6 @@ static double pw(int q, int J)
  * (R A P)[I][J] = sum_p sum_q R[I][p] A[p][q] P[q][J] with R[I][p] = P[p][I]/8. */
 void or_galerkin_op(const or_op *A, int nc, double *a27c)
 {
-    int n = A->n;
     memset(a27c, 0, sizeof(double) * nvert(nc) * 27);
 #pragma omp parallel for schedule(dynamic)
     for (int K = 1; K <= nc - 2; K++)
@@ -564,7 +600,7 @@ static double lanczos_max(const or_op *A, int steps, double *work)
     int n = A->n;
     size_t nv = nvert(n);
     double *v = work, *vp = work + nv, *w = work + 2 * nv, *dg = work + 3 * nv;
-    double al[64], be[64];
+    double al[64] = {0}, be[64] = {0};
     if (steps > 64)
         steps = 64;
     op_diag(A, dg);
@@ -623,14 +659,29 @@ typedef struct {
     int n;
     double *kx, *ky, *kz;
     double *a27;              /* Galerkin coarse operator (NULL: the 7-point link form) */
+    double *vkx, *vky, *vkz;  /* reduced-precision mode: the links rounded to bfloat16 */
+    double *va27;             /* reduced-precision mode: a27 rounded to FP32 */
     double lo, hi;            /* Chebyshev interval of D^-1 A on this level */
     double *x, *b, *r, *work; /* work: 4 vectors for the smoother */
 } or_level;
 
+/* the level's operator in FP64: used to build the hierarchy (Galerkin
+ * products, Lanczos intervals, the coarsest factor) */
 static or_op level_op(const or_level *L)
 {
     or_op A = {L->n, L->kx, L->ky, L->kz, L->a27};
     return A;
+}
+
+/* the level's operator as the V-cycle applies it: the FP64 one, or its
+ * rounded copy in the reduced-precision mode */
+static or_op vcycle_op(const or_level *L)
+{
+    if (L->vkx) {
+        or_op A = {L->n, L->vkx, L->vky, L->vkz, L->va27};
+        return A;
+    }
+    return level_op(L);
 }
 
 typedef struct {
@@ -646,6 +697,8 @@ typedef struct {
     double coarse_rtol;    /* coarse CG relative residual target */
     int coarse_max_it;
     long coarse_its;       /* coarse CG iterations since the last reset */
+    int mixed;             /* 1: reduced-precision preconditioner (or_set_mixed) */
+    int restarts;          /* true-residual restarts of the last CG solve */
 } or_hier;
 
 enum { OR_OK = 0, OR_ERR_ARG = 1, OR_ERR_DIMS = 2, OR_ERR_COEFF = 3, OR_ERR_NOMEM = 4,
@@ -661,6 +714,10 @@ void or_destroy(void *hp)
         free(H->lv[l].ky);
         free(H->lv[l].kz);
         free(H->lv[l].a27);
+        free(H->lv[l].vkx);
+        free(H->lv[l].vky);
+        free(H->lv[l].vkz);
+        free(H->lv[l].va27);
         free(H->lv[l].x);
         free(H->lv[l].b);
         free(H->lv[l].r);
@@ -819,6 +876,92 @@ int or_get_k(void *hp, int l, double *kx, double *ky, double *kz)
     return OR_OK;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Reduced-precision preconditioner (the MIXED mode; not in the paper).      */
+/* After this call the hierarchy applies the exact-arithmetic value of the   */
+/* preconditioner that the mixed mode uses:                                  */
+/*  - every level's link coefficients, built in FP64 as above, rounded once  */
+/*    to bfloat16; 27-point Galerkin coefficients rounded once to FP32; the  */
+/*    Jacobi diagonal follows from the rounded coefficients;                */
+/*  - Chebyshev intervals and the coarsest Cholesky factor stay those of     */
+/*    the FP64 operators (the inexact coarse CG of a truncated hierarchy     */
+/*    uses the rounded coefficients);                                        */
+/*  - the V-cycle's input and output are rounded to FP32 (or_vcycle);       */
+/*  - the outer CG stays FP64 (operator with the FP64 links, x, r, q, dot    */
+/*    products), except that each new search direction p = z + beta p is    */
+/*    rounded once to FP32, and that when the recursive residual passes but  */
+/*    the FP64 true residual does not, CG restarts from r = b - A x (at most */
+/*    20 times).                                                             */
+/* The V-cycle arithmetic stays FP64 here: a GPU V-cycle computing in FP32   */
+/* agrees with it to FP32 roundoff, not bit for bit.                         */
+/* Returns OR_ERR_COEFF if a link of a smoothed or CG-solved level rounds    */
+/* outside the normal bfloat16 range.                                        */
+/* ------------------------------------------------------------------------ */
+static void free_vcycle_copies(or_hier *H)
+{
+    for (int l = 0; l < H->levels; l++) {
+        or_level *L = &H->lv[l];
+        free(L->vkx);
+        free(L->vky);
+        free(L->vkz);
+        free(L->va27);
+        L->vkx = L->vky = L->vkz = L->va27 = NULL;
+    }
+}
+
+static int make_vcycle_copies(or_hier *H);
+
+int or_set_mixed(void *hp)
+{
+    or_hier *H = (or_hier *)hp;
+    if (H->mixed)
+        return OR_OK;
+    int st = make_vcycle_copies(H);
+    if (st != OR_OK) {
+        free_vcycle_copies(H);
+        return st;
+    }
+    H->mixed = 1;
+    return OR_OK;
+}
+
+static int make_vcycle_copies(or_hier *H)
+{
+    for (int l = 0; l < H->levels; l++) {
+        or_level *L = &H->lv[l];
+        int n = L->n;
+        size_t nfl = (size_t)n * n * (n - 1);
+        L->vkx = (double *)calloc(nfl, sizeof(double));
+        L->vky = (double *)calloc(nfl, sizeof(double));
+        L->vkz = (double *)calloc(nfl, sizeof(double));
+        if (!L->vkx || !L->vky || !L->vkz)
+            return OR_ERR_NOMEM;
+        for (size_t f = 0; f < nfl; f++) {
+            L->vkx[f] = or_round_bf16(L->kx[f]);
+            L->vky[f] = or_round_bf16(L->ky[f]);
+            L->vkz[f] = or_round_bf16(L->kz[f]);
+        }
+        /* active links (one end point interior) must stay normal bfloat16
+         * values; the coarsest level of an exact solve keeps FP64 */
+        int used = l + 1 < H->levels || H->coarse_solver == 1;
+        for (int k = 1; used && !L->a27 && k <= n - 2; k++)
+            for (int j = 1; j <= n - 2; j++)
+                for (int i = 0; i <= n - 2; i++)
+                    if (!or_bf16_ok(L->kx[xid(n, i, j, k)]) || !or_bf16_ok(L->ky[yid(n, j, i, k)]) ||
+                        !or_bf16_ok(L->kz[zid(n, j, k, i)]))
+                        return OR_ERR_COEFF;
+        if (L->a27) {
+            size_t m = nvert(n) * 27;
+            L->va27 = (double *)malloc(sizeof(double) * m);
+            if (!L->va27)
+                return OR_ERR_NOMEM;
+            for (size_t q = 0; q < m; q++)
+                L->va27[q] = or_round_f32(L->a27[q]);
+        }
+    }
+    return OR_OK;
+}
+
 static double dot_int(int n, const double *a, const double *b);
 
 /* Inexact coarsest solve of a truncated hierarchy (the truncation strategy of
@@ -834,7 +977,7 @@ static int coarse_cg(or_hier *H, const double *b, double *x)
     double *z = (double *)calloc(nv, sizeof(double));
     if (!z)
         return OR_ERR_NOMEM;
-    or_op Ao = level_op(C);
+    or_op Ao = vcycle_op(C);
     op_diag(&Ao, dg);
     for (size_t i = 0; i < nv; i++) {
         x[i] = 0.0;
@@ -912,7 +1055,7 @@ static int vcycle_level(or_hier *H, int l)
     if (l == H->levels - 1)
         return or_coarse_solve(H, L->b, L->x);
     or_level *C = &H->lv[l + 1];
-    or_op A = level_op(L);
+    or_op A = vcycle_op(L);
     cheb_op(&A, H->degree, L->lo, L->hi, L->b, L->x, 1, L->work);
     op_apply(&A, L->x, L->r);
     size_t nv = nvert(L->n);
@@ -936,9 +1079,10 @@ int or_vcycle(void *hp, const double *r, double *z)
     for (int k = 0; k < L->n; k++)
         for (int j = 0; j < L->n; j++)
             for (int i = 0; i < L->n; i++)
-                L->b[vid(L->n, i, j, k)] = val(L->n, r, i, j, k);
+                L->b[vid(L->n, i, j, k)] = H->mixed ? or_round_f32(val(L->n, r, i, j, k)) : val(L->n, r, i, j, k);
     int st = vcycle_level(H, 0);
-    memcpy(z, L->x, sizeof(double) * nv);
+    for (size_t p = 0; p < nv; p++)
+        z[p] = H->mixed ? or_round_f32(L->x[p]) : L->x[p];
     return st;
 }
 
@@ -949,7 +1093,7 @@ int or_smooth(void *hp, int l, const double *b, double *x, int x0_zero)
     if (l < 0 || l >= H->levels)
         return OR_ERR_ARG;
     or_level *L = &H->lv[l];
-    or_op A = level_op(L);
+    or_op A = vcycle_op(L);
     cheb_op(&A, H->degree, L->lo, L->hi, b, x, x0_zero, L->work);
     return OR_OK;
 }
@@ -960,7 +1104,7 @@ int or_apply(void *hp, int l, const double *u, double *out)
     if (l < 0 || l >= H->levels)
         return OR_ERR_ARG;
     or_level *L = &H->lv[l];
-    or_op A = level_op(L);
+    or_op A = vcycle_op(L);
     op_apply(&A, u, out);
     return OR_OK;
 }
@@ -1044,56 +1188,71 @@ static int pcg_impl(void *hp, const double *f, double *x, double rtol, int max_i
     *its = 0;
     *relres = 0.0;
     *relres_true = 0.0;
+    H->restarts = 0;
     if (bnorm == 0.0)
         goto done;
     if (!isfinite(bnorm)) {
         st = OR_ERR_ARG;
         goto done;
     }
-    or_vcycle(H, r, z);
-    memcpy(p, z, sizeof(double) * nv);
-    double rho = dot_int(n, r, z);
     *relres = 1.0;
-    st = OR_ERR_NOT_CONVERGED;
-    for (int it = 0; it < max_it; it++) {
-        or_apply_raw(n, L->kx, L->ky, L->kz, p, q);
-        double pq = dot_int(n, p, q);
-        if (!(pq > 0.0) || !isfinite(pq)) {
-            st = OR_ERR_BREAKDOWN;
-            break;
-        }
-        double alpha = rho / pq;
-        for (size_t i = 0; i < nv; i++) {
-            x[i] += alpha * p[i];
-            r[i] -= alpha * q[i];
-        }
-        *its = it + 1;
-        double rnorm = sqrt(dot_int(n, r, r));
-        *relres = rnorm / bnorm;
-        if (!isfinite(rnorm)) {
-            st = OR_ERR_BREAKDOWN;
-            break;
-        }
-        if (rnorm <= rtol * bnorm) {
-            st = OR_OK;
-            break;
-        }
+    for (;;) {
+        /* start (or restart) of the recurrence from the current r */
         or_vcycle(H, r, z);
-        double rho_new = dot_int(n, r, z);
-        double beta = flexible ? -alpha * dot_int(n, q, z) / rho : rho_new / rho;
-        rho = rho_new;
+        memcpy(p, z, sizeof(double) * nv);
+        double rho = dot_int(n, r, z);
+        st = OR_ERR_NOT_CONVERGED;
+        while (*its < max_it) {
+            or_apply_raw(n, L->kx, L->ky, L->kz, p, q);
+            double pq = dot_int(n, p, q);
+            if (!(pq > 0.0) || !isfinite(pq)) {
+                st = OR_ERR_BREAKDOWN;
+                break;
+            }
+            double alpha = rho / pq;
+            for (size_t i = 0; i < nv; i++) {
+                x[i] += alpha * p[i];
+                r[i] -= alpha * q[i];
+            }
+            *its += 1;
+            double rnorm = sqrt(dot_int(n, r, r));
+            *relres = rnorm / bnorm;
+            if (!isfinite(rnorm)) {
+                st = OR_ERR_BREAKDOWN;
+                break;
+            }
+            if (rnorm <= rtol * bnorm) {
+                st = OR_OK;
+                break;
+            }
+            or_vcycle(H, r, z);
+            double rho_new = dot_int(n, r, z);
+            double beta = flexible ? -alpha * dot_int(n, q, z) / rho : rho_new / rho;
+            rho = rho_new;
+            for (size_t i = 0; i < nv; i++)
+                p[i] = H->mixed ? or_round_f32(z[i] + beta * p[i]) : z[i] + beta * p[i];
+        }
+        /* true residual q = b - A x */
+        or_apply_raw(n, L->kx, L->ky, L->kz, x, q);
         for (size_t i = 0; i < nv; i++)
-            p[i] = z[i] + beta * p[i];
+            q[i] = b[i] - q[i];
+        double tnorm = sqrt(dot_int(n, q, q));
+        *relres_true = tnorm / bnorm;
+        if (st != OR_OK || !H->mixed || tnorm <= rtol * bnorm || H->restarts >= 20 || *its >= max_it)
+            break;
+        /* reduced precision: the recursive residual passed, the true one did
+         * not; continue from the true residual with a fresh search direction */
+        H->restarts++;
+        memcpy(r, q, sizeof(double) * nv);
     }
-    /* true residual */
-    or_apply_raw(n, L->kx, L->ky, L->kz, x, q);
-    for (size_t i = 0; i < nv; i++)
-        q[i] = b[i] - q[i];
-    *relres_true = sqrt(dot_int(n, q, q)) / bnorm;
+    if (st == OR_OK && H->mixed && !(*relres_true <= rtol))
+        st = OR_ERR_NOT_CONVERGED;
 done:
     free(b); free(r); free(z); free(p); free(q);
     return st;
 }
+
+int or_last_restarts(void *hp) { return ((or_hier *)hp)->restarts; }
 
 /* ------------------------------------------------------------------------ */
 /* Adjoint gradient.  With A(k) phi = f and a loss L(phi):                  */

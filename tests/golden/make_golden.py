@@ -5,8 +5,11 @@ seeded synthetic inputs of `paper_1604_07163_amd/inputs.py`; nothing comes from
 the GPU path.  Usage:
 
     python tests/golden/make_golden.py lognormal257 adjoint129 [inclusions513]
+    python tests/golden/make_golden.py lognormal257_mixed [inclusions513_mixed]
 
-(inclusions513 takes ~25 minutes on 8 cores and ~20 GB of RAM.)
+(inclusions513 takes ~25 minutes on 8 cores and ~20 GB of RAM.)  The *_mixed
+targets add a "mixed" entry to an existing file: the same solve with the
+oracle's reduced-precision preconditioner (precision="mixed").
 """
 from __future__ import annotations
 
@@ -49,6 +52,35 @@ def forward(name, n, levels, k, f, rtol=1e-8, max_it=2000):
            "seconds": time.time() - t}
     print(name, info, f"{time.time() - t:.1f}s", flush=True)
     return out, x, H
+
+
+def add_mixed(name, k):
+    """Add the mixed-precision oracle solve of workload `name` to its file."""
+    path = os.path.join(HERE, f"oracle_{name}.json")
+    out = json.load(open(path))
+    w = inputs.WORKLOADS[name]
+    n, levels = w["n"], w["levels"]
+    f = inputs.uniform_rhs(n, w["f_seed"])
+    t = time.time()
+    H = oracle.Hierarchy(*k, levels=levels, precision="mixed")
+    x, info = H.solve(f, rtol=out["rtol"], max_it=2000)
+    pts = np.asarray(out["sample_points"])
+    out["mixed"] = {"iterations": info["iterations"], "restarts": info["restarts"], "status": info["status"],
+                    "rel_res_true": info["rel_res_true"], "norm2": float(np.linalg.norm(x)),
+                    "sample_values": x[pts[:, 0], pts[:, 1], pts[:, 2]].tolist(), "seconds": time.time() - t}
+    print(name, "mixed", info, f"{time.time() - t:.1f}s", flush=True)
+    return out
+
+
+def lognormal257_mixed():
+    w = inputs.WORKLOADS["lognormal257"]
+    return add_mixed("lognormal257", inputs.lognormal_k(w["n"], w["k_seed"]))
+
+
+def inclusions513_mixed():
+    w = inputs.WORKLOADS["inclusions513"]
+    kx, ky, kz, _ = inputs.inclusion_k(w["n"], w["k_seed"])
+    return add_mixed("inclusions513", (kx, ky, kz))
 
 
 def lognormal257():
@@ -96,5 +128,5 @@ if __name__ == "__main__":
     which = sys.argv[1:] or ["lognormal257", "adjoint129"]
     for name in which:
         res = globals()[name]()
-        with open(os.path.join(HERE, f"oracle_{name}.json"), "w") as fh:
+        with open(os.path.join(HERE, f"oracle_{name.replace('_mixed', '')}.json"), "w") as fh:
             json.dump(res, fh)

@@ -132,6 +132,7 @@ def test_mixed_vcycle_matches_dense_composition(oracle_mod, n, levels, galerkin)
     z = Hm.vcycle(r)
     zi = mf.interior(z)
     np.testing.assert_array_equal(z, f32(z))  # an FP32 result
+    np.testing.assert_array_equal(Hm.vcycle(f32(r)), z)  # of an FP32 input
     assert np.all(z[~mf.interior_mask(n)] == 0)
     # FP32 output rounding (half an ulp, 2^-24 relative) on an FP64 result
     assert np.all(np.abs(zi - ref) <= 2.0 ** -24 * np.abs(ref) + 1e-11 * np.abs(ref).max())

@@ -106,6 +106,13 @@ typedef struct {
                                are copied into the workgroup's LDS for the coarse cycle when they
                                all fit (link levels only); 0: they are swept in HBM/L2.  The
                                result is the same either way. */
+    int32_t post_fused;     /* on grid-path link levels with cheb_degree 2: 1 = the
+                               post-smoothing runs as one sweep that keeps the first Chebyshev
+                               iterate in LDS; 0 = two sweeps through HBM; 2 (default) = one
+                               sweep in FP64, two in MIXED (measured at 513^3: FP64 1.7 ms
+                               vs 2.9 ms, MIXED 1.14 ms vs 1.21 ms, where the two sweeps keep
+                               each kernel near the HBM bound).  Same values to the bit; only
+                               the partial sums of r.z are grouped differently. */
 } gmg_options;
 
 typedef struct {
@@ -226,7 +233,8 @@ typedef enum {
     GMG_K_RESTRICT = 13,      /* b_c = R r (full weighting) */
     GMG_K_UPDATE_XP = 14,     /* x += alpha p, p = z + beta p */
     GMG_K_CHEB_PRE2 = 15,     /* first two Chebyshev steps from zero, fused */
-    GMG_K_COUNT = 16
+    GMG_K_CHEB_POST2 = 16,    /* post-smoothing, both Chebyshev steps in one sweep (+ partial r.z) */
+    GMG_K_COUNT = 17
 } gmg_kernel_class;
 gmg_status gmg_profile_start(gmg_handle *h);  /* clear counters, start recording */
 gmg_status gmg_profile_stop(gmg_handle *h);   /* stop recording, wait for the stream */

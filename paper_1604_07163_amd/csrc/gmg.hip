@@ -44,7 +44,11 @@ struct LevelHost {
     Tiling til64{};  // FP64 outer operator (residual)
     Tiling til2{};   // FP64 outer apply, two points per lane
     Tiling tilp{};   // pre-smoothing kernel, two rows per thread
+    Tiling tilq{};   // one-sweep post-smoothing kernel
+    bool post1 = false;  // post-smoothing in one sweep, its result in t1 (else in x)
     gmg::Rows rows{};
+    // the buffer that holds the level's V-cycle result after post-smoothing
+    void *zout() const { return post1 ? t1 : x; }
 };
 
 }  // namespace
@@ -396,6 +400,22 @@ gmg_status smooth_grid(gmg_handle *h, int l, bool from_zero, const double *r64_c
         if (cc.m == 1) return GMG_OK;
         cur = 1;
         prev = -1;
+    } else if (lh.post1) {
+        // both steps in one sweep, x0 in x, the result in t1
+        Prof pf(h, GMG_K_CHEB_POST2, fin);
+        constexpr int rows = sizeof(V) == 4 ? gmg::TY_POST32 : gmg::TY_POST64;
+        const dim3 gq(lh.tilq.nblocks), bq(gmg::TX * rows);
+        if (dot_r64) {
+            gmg::k_post2<V, K, true, rows><<<gq, bq, 0, h->stream>>>(L, lh.tilq, b, bufs[0], bufs[1], cc.cfirst,
+                                                                      cc.c1[1], cc.c2[1], dot_r64, h->partial, skip,
+                                                                      dot_q64);
+            if (nparts) *nparts = lh.tilq.nblocks;
+        } else {
+            gmg::k_post2<V, K, false, rows><<<gq, bq, 0, h->stream>>>(L, lh.tilq, b, bufs[0], bufs[1], cc.cfirst,
+                                                                       cc.c1[1], cc.c2[1], nullptr, nullptr, skip);
+        }
+        LAUNCHCHK();
+        return GMG_OK;
     } else {
         Prof pf(h, GMG_K_CHEB_STEP, fin);
         gmg::k_cheb_step<V, K, 0, false><<<grid, blk, 0, h->stream>>>(L, lh.til, b, bufs[0], nullptr, bufs[1], V(0),
@@ -589,7 +609,7 @@ gmg_status vcycle(gmg_handle *h, const int *skip, bool want_dot, int *nparts, bo
         {
             Prof pf(h, GMG_K_PROLONG, l == 0);
             gmg::k_prolong<V><<<prolong_grid(c.n), gmg::NT, 0, h->stream>>>(f.pitch, f.plane, c.n, c.pitch, c.plane,
-                                                                            (const V *)c.x, (V *)f.x, skip);
+                                                                            (const V *)c.zout(), (V *)f.x, skip);
             LAUNCHCHK();
         }
         STCHK((smooth_grid<V, K>(h, l, false, nullptr, (l == 0 && want_dot) ? h->R : nullptr, skip,
@@ -652,10 +672,10 @@ gmg_status pcg_start(gmg_handle *h) {
     Prof pf(h, GMG_K_UPDATE_P, true);
     if (mixed(h))
         gmg::k_update_p<float, float><<<h->lv[0].rows.nblocks, gmg::NT_FLAT, 0, h->stream>>>(
-            h->lv[0].rows, h->P32, (const float *)h->lv[0].x, h->st);
+            h->lv[0].rows, h->P32, (const float *)h->lv[0].zout(), h->st);
     else
         gmg::k_update_p<double, double><<<h->lv[0].rows.nblocks, gmg::NT_FLAT, 0, h->stream>>>(
-            h->lv[0].rows, h->P, (const double *)h->lv[0].x, h->st);
+            h->lv[0].rows, h->P, (const double *)h->lv[0].zout(), h->st);
     LAUNCHCHK();
     gmg::k_clear_restart<<<1, 64, 0, h->stream>>>(h->st);
     LAUNCHCHK();
@@ -698,10 +718,10 @@ gmg_status pcg_iteration(gmg_handle *h) {
         Prof pf(h, GMG_K_UPDATE_XP, true);
         if (mx)
             gmg::k_update_xp<float, float><<<l0.rows.nblocks, gmg::NT_FLAT, 0, h->stream>>>(
-                l0.rows, h->X, h->P32, (const float *)l0.x, h->st);
+                l0.rows, h->X, h->P32, (const float *)l0.zout(), h->st);
         else
             gmg::k_update_xp<double, double><<<l0.rows.nblocks, gmg::NT_FLAT, 0, h->stream>>>(
-                l0.rows, h->X, h->P, (const double *)l0.x, h->st);
+                l0.rows, h->X, h->P, (const double *)l0.zout(), h->st);
         LAUNCHCHK();
     }
     return GMG_OK;
@@ -1100,6 +1120,7 @@ void gmg_default_options(gmg_options *o, int32_t n) {
     o->switch2_n = 0;
     o->galerkin = 0;
     o->persistent_lds = 1;
+    o->post_fused = 2;
 }
 
 const char *gmg_status_string(gmg_status s) {
@@ -1145,7 +1166,8 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
         o.persistent_wgs < 1 || o.persistent_wgs > 32 || o.switch2_n < 0 || o.check_every < 0 || (o.coeff_is_log != 0 && o.coeff_is_log != 1) ||
         (o.coarse_solver != 0 && o.coarse_solver != 1) || (o.flexible != 0 && o.flexible != 1) ||
         (o.coarse_solver == 1 && (!(o.coarse_rtol > 0.0) || o.coarse_max_it < 1 || o.switch_n != 0)) ||
-        o.galerkin < 0 || (o.persistent_lds != 0 && o.persistent_lds != 1))
+        o.galerkin < 0 || (o.persistent_lds != 0 && o.persistent_lds != 1) ||
+        o.post_fused < 0 || o.post_fused > 2)
         return GMG_ERR_ARG;
     if ((o.n - 1) % (1 << (o.levels - 1)) != 0) return GMG_ERR_DIMS;
     const int nc = (o.n - 1) / (1 << (o.levels - 1)) + 1;
@@ -1186,6 +1208,10 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
         lh.til64 = make_tiling(n, t64);
         lh.til2 = make_tiling(n, t64, gmg::TX2);
         lh.tilp = make_tiling(n, env_int("GMG_TARGET_WGS_V", 1 << 20), gmg::TX, gmg::TY_PRE);
+        // one-sweep post-smoothing: 32-plane chunks at 513^3 (measured best for
+        // both precisions; its two extra x1 planes per chunk favour long chunks)
+        lh.tilq = mx ? make_tiling(n, env_int("GMG_TARGET_WGS_POST", 8192), gmg::TX, gmg::TY_POST32)
+                     : make_tiling(n, env_int("GMG_TARGET_WGS_POST", 2048), gmg::TX, gmg::TY_POST64);
         lh.rows = make_rows(n, lh.pitch, lh.plane);
         lh.g27 = o.galerkin > 0 && l >= o.galerkin;
         n = (n - 1) / 2 + 1;
@@ -1210,6 +1236,9 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
                 break;
             }
     }
+    // one-sweep post-smoothing on the grid-path link levels (degree 2)
+    for (int l = 0; l < h->s_persist; ++l)
+        h->lv[l].post1 = (o.post_fused == 1 || (o.post_fused == 2 && !mx)) && !h->lv[l].g27 && o.cheb_degree == 2;
     // allocations
     gmg_status s;
     LevelHost &l0 = h->lv[0];
@@ -1226,7 +1255,7 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
         ALLOC(h->P, l0.nel);
     ALLOC(h->Q, l0.nel);
     h->npartial = std::max(std::max(std::max(l0.til.nblocks, l0.til64.nblocks), l0.til2.nblocks),
-                           std::max(l0.rows.nblocks, gmg::NB_FLAT));
+                           std::max(std::max(l0.rows.nblocks, l0.tilq.nblocks), gmg::NB_FLAT));
     {
         const long long nfaces_blocks = blocks_for((long long)l0.n * l0.n * l0.n, 256);
         if (nfaces_blocks > h->npartial) h->npartial = (int)nfaces_blocks;
@@ -1472,7 +1501,7 @@ gmg_status hook_smooth(gmg_handle *h, int level, const double *b, double *x, int
     STCHK(in_vec<V>(h, lh, b, (V *)lh.b));
     if (!x0_zero) STCHK(in_vec<V>(h, lh, x, (V *)lh.x));
     STCHK((smooth_grid<V, K>(h, level, x0_zero != 0, nullptr, nullptr, nullptr, nullptr)));
-    return out_vec<V>(h, lh, (const V *)lh.x, x);
+    return out_vec<V>(h, lh, (const V *)(x0_zero ? lh.x : lh.zout()), x);
 }
 
 template <typename V, typename K>
@@ -1515,7 +1544,7 @@ gmg_status hook_vcycle(gmg_handle *h, const double *r, double *z) {
     if (h->persist && h->opt.persistent_wgs > 1) HIPCHK(hipMemsetAsync(h->bar, 0, sizeof(gmg::GridBar), h->stream));
     STCHK(in_vec<double>(h, l0, r, h->R));
     STCHK((vcycle<V, K>(h, nullptr, false, nullptr)));
-    return out_vec<V>(h, l0, (const V *)l0.x, z);
+    return out_vec<V>(h, l0, (const V *)l0.zout(), z);
 }
 
 }  // namespace
@@ -1650,7 +1679,8 @@ const char *gmg_kernel_class_name(int32_t c) {
     static const char *names[GMG_K_COUNT] = {"apply_dot",      "residual",  "update_r",       "update_p",
                                              "cheb_first",     "cheb_step", "cheb_step_prev", "cheb_step_dot",
                                              "level_residual", "prolong",   "persistent",     "coarse_solve",
-                                             "face_gradient",  "restrict",  "update_xp",      "cheb_pre2"};
+                                             "face_gradient",  "restrict",  "update_xp",      "cheb_pre2",
+                                             "cheb_post2"};
     return (c >= 0 && c < GMG_K_COUNT) ? names[c] : "unknown";
 }
 

@@ -29,6 +29,10 @@ constexpr int TY = 4;           // rows per tile
 constexpr int NT = TX * TY;     // threads per stencil workgroup
 constexpr int TX2 = 2 * TX;     // x extent of a tile of the two-points-per-lane apply
 constexpr int TY_PRE = 2 * TY;  // rows per tile of the two-rows-per-thread pre-smoothing kernel
+// rows per tile of the one-sweep post-smoothing kernel, FP32 and FP64 (measured
+// at 513^3: FP32 fastest with 8, FP64 with 16)
+constexpr int TY_POST32 = 8;
+constexpr int TY_POST64 = 16;
 constexpr int NT_FLAT = 256;    // threads per workgroup of the flat vector kernels
 constexpr int NB_FLAT = 2048;   // workgroups of the flat vector kernels (fixed => deterministic sums)
 constexpr int NT_PERSIST = 1024;
@@ -543,6 +547,172 @@ __global__ __launch_bounds__(NT) void k_cheb_step(Lev<V, K> L, Tiling t, const V
         if (threadIdx.x == 0) partial[blockIdx.x] = s;
         if (q64) {  // flexible CG: second partial array q.z after the first
             const double sq = block_sum<NT>(dotq);
+            if (threadIdx.x == 0) partial[gridDim.x + blockIdx.x] = sq;
+        }
+    }
+}
+
+// Post-smoothing by a degree-2 Chebyshev polynomial in one sweep (7-point
+// link levels):
+//   x1 = x0 + c0 D^-1 (b - A x0),   x2 = x1 + c1 (x1 - x0) + c2 D^-1 (b - A x1),
+// with the arithmetic of a k_cheb_step with PM = 0 followed by one with PM = 2,
+// so x2 is the same to the bit.  x1 never goes to memory: marching up its
+// z-chunk, the workgroup computes x1 one plane ahead on its 64 x 8 tile plus a
+// one-point ring (the ring is recomputed by the neighbouring tiles too) into
+// LDS, from x0 of that plane staged in LDS with a two-point ring; x2 of the
+// plane below then takes its in-plane x1 neighbours from LDS and x1 above and
+// below from registers.  One read of x0, b and the links and one write of x2
+// replace the two sweeps' reads of x0 (twice), b and the links (twice) and
+// the write and read of x1.  out must not alias x0 (other tiles read x0 in
+// their rings).  DOTR: partial[wg] = sum r64 . x2 (and q64 . x2 after it).
+// A tile is 64 x ROWS points, one thread each.
+template <typename V, typename K, bool DOTR, int ROWS>
+__global__ __launch_bounds__(TX * ROWS) void k_post2(Lev<V, K> L, Tiling t, const V *__restrict__ b,
+                                                   const V *__restrict__ x0, V *__restrict__ out, V c0, V c1, V c2,
+                                                   const double *__restrict__ r64, double *__restrict__ partial,
+                                                   const int *__restrict__ skip,
+                                                   const double *__restrict__ q64 = nullptr) {
+    constexpr int W = TX, H = ROWS, NTH = TX * ROWS;
+    constexpr int HALO0 = 4 * (W + 4) + 4 * H;  // two-point ring of the x0 tile
+    constexpr int RING = 2 * (W + 2) + 2 * H;   // one-point ring of the x1 tile
+    static_assert(HALO0 <= NTH && RING <= NTH, "one pass per ring");
+    __shared__ V sx0[2][H + 4][W + 4];  // x0 of a plane, 2-point ring (tile at [2, H+1] x [2, W+1]), by parity
+    __shared__ V sx1[2][H + 2][W + 2];  // x1 of a plane, 1-point ring (tile at [1, H] x [1, W]), by parity
+    if (skip && *skip) return;
+    int tx, ty, cz;
+    tile_of(blockIdx.x, t, tx, ty, cz);
+    const int lx = (int)(threadIdx.x & (W - 1)), ly = (int)(threadIdx.x >> 6);
+    const int i0 = tx * W, j0 = 1 + ty * H;  // grid position of tile point (0, 0)
+    const int i = i0 + lx, j = j0 + ly;
+    const int n = L.n, pitch = L.pitch;
+    const long long plane = L.plane;
+    const int k0 = 1 + cz * t.zchunk, k1 = min(k0 + t.zchunk, n - 1);
+    if (k0 >= k1) return;  // uniform over the workgroup
+    auto inside = [n](int a, int c, int m) {
+        return (unsigned)a < (unsigned)n && (unsigned)c < (unsigned)n && (unsigned)m < (unsigned)n;
+    };
+    auto inner = [n](int a, int c, int m) {
+        return a >= 1 && a <= n - 2 && c >= 1 && c <= n - 2 && m >= 1 && m <= n - 2;
+    };
+    auto at = [pitch, plane](int a, int c, int m) { return (long long)m * plane + (long long)c * pitch + a; };
+    auto vx0 = [&](int a, int c, int m) { return inside(a, c, m) ? x0[at(a, c, m)] : V(0); };
+    // x1 of vertex (a, c, m); its in-plane x0 neighbours are staged at sx0[m & 1][ry][rx] +- 1
+    auto x1_of = [&](int a, int c, int m, int ry, int rx, V xb, V xt) -> V {
+        if (!inner(a, c, m)) return V(0);
+        const long long q = at(a, c, m);
+        const V kw = kval(L.kx[q - 1]), ke = kval(L.kx[q]), ks = kval(L.ky[q - pitch]), kn = kval(L.ky[q]),
+                kb = kval(L.kz[q - plane]), kt = kval(L.kz[q]);
+        const V(*t0)[W + 4] = sx0[m & 1];
+        const V xc = t0[ry][rx];
+        const V ax = apply7(xc, t0[ry][rx - 1], t0[ry][rx + 1], t0[ry - 1][rx], t0[ry + 1][rx], xb, xt, kw, ke, ks,
+                            kn, kb, kt, L.s);
+        const V d = diag7(kw, ke, ks, kn, kb, kt, L.s);
+        return cheb_step_val(xc, V(0), b[q], ax, d, V(0), c0);
+    };
+    // the same for the thread's own vertex; its links and b are kept for x2
+    struct Own {
+        V kw, ke, ks, kn, kb, kt, bv;
+    };
+    auto x1_own = [&](int m, V xb, V xt, Own &w) -> V {
+        if (!inner(i, j, m)) {
+            w = Own{V(0), V(0), V(0), V(0), V(0), V(0), V(0)};
+            return V(0);
+        }
+        const long long q = at(i, j, m);
+        w.kw = kval(L.kx[q - 1]);
+        w.ke = kval(L.kx[q]);
+        w.ks = kval(L.ky[q - pitch]);
+        w.kn = kval(L.ky[q]);
+        w.kb = kval(L.kz[q - plane]);
+        w.kt = kval(L.kz[q]);
+        w.bv = b[q];
+        const int ry = ly + 2, rx = lx + 2;
+        const V(*t0)[W + 4] = sx0[m & 1];
+        const V xc = t0[ry][rx];
+        const V ax = apply7(xc, t0[ry][rx - 1], t0[ry][rx + 1], t0[ry - 1][rx], t0[ry + 1][rx], xb, xt, w.kw,
+                            w.ke, w.ks, w.kn, w.kb, w.kt, L.s);
+        const V d = diag7(w.kw, w.ke, w.ks, w.kn, w.kb, w.kt, L.s);
+        return cheb_step_val(xc, V(0), w.bv, ax, d, V(0), c0);
+    };
+    // x0 of plane m into sx0[m & 1]: the thread's own value, then the ring
+    auto stage_x0 = [&](int m, V own) {
+        V(*t0)[W + 4] = sx0[m & 1];
+        t0[ly + 2][lx + 2] = own;
+        const int h = (int)threadIdx.x;
+        if (h < HALO0) {
+            int ry, rx;
+            if (h < 4 * (W + 4)) {
+                const int r = h / (W + 4);
+                ry = r < 2 ? r : r + H;
+                rx = h % (W + 4);
+            } else {
+                const int r = h - 4 * (W + 4);
+                ry = 2 + r / 4;
+                rx = (r & 3) < 2 ? (r & 3) : (r & 3) + W;
+            }
+            t0[ry][rx] = vx0(i0 - 2 + rx, j0 - 2 + ry, m);
+        }
+    };
+    // x1 of the ring of plane m into sx1[m & 1] (sx0[m & 1] holds plane m)
+    auto ring_x1 = [&](int m) {
+        const int r = (int)threadIdx.x;
+        if (r < RING) {
+            int ry, rx;
+            if (r < 2 * (W + 2)) {
+                ry = r < W + 2 ? 0 : H + 1;
+                rx = r % (W + 2);
+            } else {
+                const int q = r - 2 * (W + 2);
+                ry = 1 + q / 2;
+                rx = (q & 1) ? W + 1 : 0;
+            }
+            const int a = i0 - 1 + rx, c = j0 - 1 + ry;
+            sx1[m & 1][ry][rx] = x1_of(a, c, m, ry + 1, rx + 1, vx0(a, c, m - 1), vx0(a, c, m + 1));
+        }
+    };
+    // Phase m (m = k0-1 .. k1), one barrier each: x1 of plane m (from m = k0
+    // on with its ring) from sx0[m & 1]; x2 of plane m-1 from sx1[(m-1) & 1];
+    // x0 of plane m+1 staged into the other sx0 buffer.
+    V xb0 = vx0(i, j, k0 - 2), xc0 = vx0(i, j, k0 - 1);  // the thread's x0 at m-1, m
+    V x1b = V(0), x1c = V(0);                            // its x1 at m-2, m-1
+    Own wc{}, wt{};
+    double dot = 0.0, dotq = 0.0;
+    stage_x0(k0 - 1, xc0);
+    __syncthreads();
+    for (int m = k0 - 1; m <= k1; ++m) {
+        const V xn0 = vx0(i, j, m + 1);
+        const V x1t = x1_own(m, xb0, xn0, wt);
+        if (m >= k0 && m < k1) {
+            sx1[m & 1][ly + 1][lx + 1] = x1t;
+            ring_x1(m);
+        }
+        const int k = m - 1;
+        if (k >= k0 && inner(i, j, k)) {
+            const long long o = at(i, j, k);
+            const V(*t1)[W + 2] = sx1[k & 1];
+            const V ax = apply7(x1c, t1[ly + 1][lx], t1[ly + 1][lx + 2], t1[ly][lx + 1], t1[ly + 2][lx + 1], x1b, x1t,
+                                wc.kw, wc.ke, wc.ks, wc.kn, wc.kb, wc.kt, L.s);
+            const V d = diag7(wc.kw, wc.ke, wc.ks, wc.kn, wc.kb, wc.kt, L.s);
+            const V v = cheb_step_val(x1c, x1c - xb0, wc.bv, ax, d, c1, c2);
+            stnt(v, &out[o]);
+            if (DOTR) {
+                dot = fmaT(ldnt(&r64[o]), (double)v, dot);
+                if (q64) dotq = fmaT(ldnt(&q64[o]), (double)v, dotq);
+            }
+        }
+        if (m < k1) stage_x0(m + 1, xn0);
+        __syncthreads();
+        x1b = x1c;
+        x1c = x1t;
+        xb0 = xc0;
+        xc0 = xn0;
+        wc = wt;
+    }
+    if (DOTR) {
+        const double sm = block_sum<NTH>(dot);
+        if (threadIdx.x == 0) partial[blockIdx.x] = sm;
+        if (q64) {
+            const double sq = block_sum<NTH>(dotq);
             if (threadIdx.x == 0) partial[gridDim.x + blockIdx.x] = sq;
         }
     }

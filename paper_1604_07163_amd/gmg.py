@@ -32,7 +32,8 @@ class Options(ctypes.Structure):
                 ("check_every", ctypes.c_int32), ("coarse_solver", ctypes.c_int32),
                 ("coarse_rtol", ctypes.c_double), ("coarse_max_it", ctypes.c_int32),
                 ("flexible", ctypes.c_int32), ("switch2_n", ctypes.c_int32),
-                ("galerkin", ctypes.c_int32), ("persistent_lds", ctypes.c_int32)]
+                ("galerkin", ctypes.c_int32), ("persistent_lds", ctypes.c_int32),
+                ("post_fused", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -149,7 +150,7 @@ class Solver:
     def __init__(self, kx, ky, kz, *, levels=None, precision="fp64", switch_n=0, coarse_rule="arithmetic",
                  cheb_degree=2, cheb_lo=0.25, cheb_hi=2.0, coeff_is_log=False, check_every=0,
                  persistent_wgs=1, coarse_solver="exact", coarse_rtol=1e-4, coarse_max_it=500, flexible=False,
-                 switch2_n=0, galerkin=0, persistent_lds=True):
+                 switch2_n=0, galerkin=0, persistent_lds=True, post_fused="auto"):
         L = lib()
         n = int(kx.shape[0])
         self.n = n
@@ -174,6 +175,7 @@ class Solver:
         o.switch2_n = int(switch2_n)
         o.galerkin = int(galerkin)
         o.persistent_lds = 1 if persistent_lds else 0
+        o.post_fused = 2 if post_fused == "auto" else (1 if post_fused else 0)
         self.options = o
         self.levels = o.levels
         self._h = ctypes.c_void_p()
@@ -352,7 +354,7 @@ class Solver:
 
 KERNEL_CLASSES = ["apply_dot", "residual", "update_r", "update_p", "cheb_first", "cheb_step", "cheb_step_prev",
                   "cheb_step_dot", "level_residual", "prolong", "persistent", "coarse_solve", "face_gradient",
-                  "restrict", "update_xp", "cheb_pre2"]
+                  "restrict", "update_xp", "cheb_pre2", "cheb_post2"]
 
 
 class Profile:

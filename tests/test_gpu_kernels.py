@@ -187,3 +187,34 @@ def test_mixed_persistent_lds_identical(n, levels):
             x, info = sp.solve(f, rtol=1e-8)
             assert info["iterations"] == ib["iterations"] and torch.equal(x, xb)
             sp.close()
+
+
+@pytest.mark.parametrize("n,levels", [(17, 4), (33, 5), (81, 5), (161, 6)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_post_smoothing_one_sweep_bitwise(n, levels, precision):
+    """The one-sweep post-smoothing (first Chebyshev iterate kept in LDS) gives
+    the two-sweep values to the bit: the smoother hook on every grid level and
+    whole V-cycles, with and without agglomerated coarse levels."""
+    k = inputs.lognormal_k(n, 7, width=3.0)
+    kg = [to_gpu(a) for a in k]
+    for sw in (0, 9):
+        say(f"  post-smoothing n={n} levels={levels} {precision} switch={sw}")
+        sf = gmg.Solver(*kg, levels=levels, precision=precision, switch_n=sw)
+        su = gmg.Solver(*kg, levels=levels, precision=precision, switch_n=sw, post_fused=False)
+        for l in range(levels - 1):
+            nl = sf.level_n(l)
+            b, x0 = to_gpu(rand_vec(nl, 60 + l)), to_gpu(rand_vec(nl, 70 + l))
+            np.testing.assert_array_equal(to_np(sf.smooth(l, b, x0)), to_np(su.smooth(l, b, x0)))
+        r = to_gpu(rand_vec(n, 5))
+        zf, zu = to_np(sf.vcycle(r)), to_np(su.vcycle(r))
+        say(f"    V-cycle bitwise {np.array_equal(zf, zu)}")
+        np.testing.assert_array_equal(zf, zu)
+        f = to_gpu(inputs.uniform_rhs(n, 8))
+        xf, i_f = sf.solve(f, rtol=1e-10)
+        xu, i_u = su.solve(f, rtol=1e-10)
+        d = rel_max(to_np(xf), to_np(xu))
+        say(f"    solve its {i_f['iterations']} / {i_u['iterations']}, max rel diff {d:.1e}")
+        # the r.z partial sums are grouped by different tiles: FP64 rounding only
+        assert i_f["iterations"] == i_u["iterations"] and d <= 1e-12
+        sf.close()
+        su.close()

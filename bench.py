@@ -362,6 +362,8 @@ def main():
                          "folders and exit (host only)")
     ap.add_argument("--galerkin", type=int, nargs="*", default=[],
                     help="with --sweep: also time Galerkin coarse operators from these first levels")
+    ap.add_argument("--post-fused", default="auto", choices=["auto", "0", "1"],
+                    help="one-sweep post-smoothing: auto (the library default: FP64 only), 0 never, 1 always")
     args = ap.parse_args()
     if args.profile_summary:
         profile_summary(args.profile_summary)
@@ -397,7 +399,8 @@ def main():
     legs = {}
     results = {}
     for prec in (["mixed"] if args.no_fp64 else ["mixed", "fp64"]):
-        s = gmg.Solver(*k, levels=levels, precision=prec, switch_n=args.switch_n)
+        s = gmg.Solver(*k, levels=levels, precision=prec, switch_n=args.switch_n,
+                       post_fused="auto" if args.post_fused == "auto" else args.post_fused == "1")
         # phi_obs: forward solve with the observation coefficients (untimed)
         s.set_coefficients(*kobs)
         phi_obs, _ = s.solve(f, rtol=1e-10, max_it=2000)
@@ -447,7 +450,7 @@ def main():
         "dtype": "f32+bf16 V-cycle, f64 outer",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {w['desc']}", "n": n, "levels": levels,
-                   "unknowns": n_unk, "switch_n": args.switch_n, "rtol": args.rtol,
+                   "unknowns": n_unk, "switch_n": args.switch_n, "post_fused": args.post_fused, "rtol": args.rtol,
                    "step": "setup + mixed PCG solve + adjoint gradient"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(dom, args.workload),

@@ -116,19 +116,24 @@ def test_mixed_precision_solve():
     assert imx["iterations"] <= i64["iterations"] + 2 + i64["iterations"] // 10
 
 
-def test_adjoint_gradient_vs_oracle():
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_adjoint_gradient_vs_oracle(precision):
+    """The link gradient against the oracle's (MIXED: the oracle's reduced-
+    precision mode, the same preconditioner); both solves to rtol 1e-13."""
     n, levels = 33, 5
     k = inputs.lognormal_k(n, 6, width=3.0)
     kobs = inputs.lognormal_k(n, 7, width=3.0)
     f = inputs.uniform_rhs(n, 8)
     Hobs = oracle.Hierarchy(*kobs, levels=levels)
     phi_obs, _ = Hobs.solve(f, rtol=1e-13)
-    H = oracle.Hierarchy(*k, levels=levels)
+    H = oracle.Hierarchy(*k, levels=levels, precision=precision)
     phi, _ = H.solve(f, rtol=1e-13)
-    gxo, gyo, gzo, lamo, _ = H.adjoint_gradient(phi, phi - phi_obs, rtol=1e-13)
-    s = gmg.Solver(*[to_gpu(a) for a in k], levels=levels)
+    gxo, gyo, gzo, lamo, io = H.adjoint_gradient(phi, phi - phi_obs, rtol=1e-13)
+    s = gmg.Solver(*[to_gpu(a) for a in k], levels=levels, precision=precision)
     phig, _ = s.solve(to_gpu(f), rtol=1e-13)
     gx, gy, gz, lam, info = s.adjoint_gradient(phig, phig - to_gpu(phi_obs), rtol=1e-13)
+    say(f"    {precision} adjoint its gpu {info['iterations']} oracle {io['iterations']}")
+    assert abs(info["iterations"] - io["iterations"]) <= 1
     scale = max(np.abs(a).max() for a in (gxo, gyo, gzo))
     for a, b in ((gx, gxo), (gy, gyo), (gz, gzo)):
         assert np.abs(to_np(a) - b).max() <= 1e-6 * scale

@@ -110,9 +110,10 @@ typedef struct {
                                post-smoothing runs as one sweep that keeps the first Chebyshev
                                iterate in LDS; 0 = two sweeps through HBM; 2 (default) = one
                                sweep in FP64, two in MIXED (measured at 513^3: FP64 1.7 ms
-                               vs 2.9 ms, MIXED 1.14 ms vs 1.21 ms, where the two sweeps keep
-                               each kernel near the HBM bound).  Same values to the bit; only
-                               the partial sums of r.z are grouped differently. */
+                               vs 2.9 ms; MIXED 1.02 ms vs 1.21 ms, where the one sweep is
+                               instruction-bound and the two keep each kernel near the HBM
+                               bound).  Same values to the bit; only the partial sums of r.z
+                               are grouped differently. */
 } gmg_options;
 
 typedef struct {

@@ -588,37 +588,47 @@ __global__ __launch_bounds__(TX * ROWS) void k_post2(Lev<V, K> L, Tiling t, cons
     const long long plane = L.plane;
     const int k0 = 1 + cz * t.zchunk, k1 = min(k0 + t.zchunk, n - 1);
     if (k0 >= k1) return;  // uniform over the workgroup
-    auto inside = [n](int a, int c, int m) {
-        return (unsigned)a < (unsigned)n && (unsigned)c < (unsigned)n && (unsigned)m < (unsigned)n;
-    };
-    auto inner = [n](int a, int c, int m) {
-        return a >= 1 && a <= n - 2 && c >= 1 && c <= n - 2 && m >= 1 && m <= n - 2;
-    };
-    auto at = [pitch, plane](int a, int c, int m) { return (long long)m * plane + (long long)c * pitch + a; };
-    auto vx0 = [&](int a, int c, int m) { return inside(a, c, m) ? x0[at(a, c, m)] : V(0); };
-    // x1 of vertex (a, c, m); its in-plane x0 neighbours are staged at sx0[m & 1][ry][rx] +- 1
-    auto x1_of = [&](int a, int c, int m, int ry, int rx, V xb, V xt) -> V {
-        if (!inner(a, c, m)) return V(0);
-        const long long q = at(a, c, m);
-        const V kw = kval(L.kx[q - 1]), ke = kval(L.kx[q]), ks = kval(L.ky[q - pitch]), kn = kval(L.ky[q]),
-                kb = kval(L.kz[q - plane]), kt = kval(L.kz[q]);
-        const V(*t0)[W + 4] = sx0[m & 1];
-        const V xc = t0[ry][rx];
-        const V ax = apply7(xc, t0[ry][rx - 1], t0[ry][rx + 1], t0[ry - 1][rx], t0[ry + 1][rx], xb, xt, kw, ke, ks,
-                            kn, kb, kt, L.s);
-        const V d = diag7(kw, ke, ks, kn, kb, kt, L.s);
-        return cheb_step_val(xc, V(0), b[q], ax, d, V(0), c0);
-    };
-    // the same for the thread's own vertex; its links and b are kept for x2
+    // Every staged value sits at an in-plane offset that is fixed per thread
+    // (its own vertex, its slot in the x0 ring, its slot in the x1 ring); only
+    // the plane index m, uniform over the workgroup, changes.
+    auto in_xy = [n](int a, int c) { return (unsigned)a < (unsigned)n && (unsigned)c < (unsigned)n; };
+    auto inner_xy = [n](int a, int c) { return a >= 1 && a <= n - 2 && c >= 1 && c <= n - 2; };
+    const bool own_xy = in_xy(i, j), own_inner = inner_xy(i, j);
+    const int own_off = j * pitch + i;
+    const int h = (int)threadIdx.x;
+    int hy = 0, hx = 0;
+    if (h < 4 * (W + 4)) {
+        const int r = h / (W + 4);
+        hy = r < 2 ? r : r + H;
+        hx = h % (W + 4);
+    } else {
+        const int r = h - 4 * (W + 4);
+        hy = 2 + r / 4;
+        hx = (r & 3) < 2 ? (r & 3) : (r & 3) + W;
+    }
+    const bool hal = h < HALO0, hal_xy = hal && in_xy(i0 - 2 + hx, j0 - 2 + hy);
+    const int hal_off = (j0 - 2 + hy) * pitch + (i0 - 2 + hx);
+    int gy = 0, gx = 0;
+    if (h < 2 * (W + 2)) {
+        gy = h < W + 2 ? 0 : H + 1;
+        gx = h % (W + 2);
+    } else {
+        const int q = h - 2 * (W + 2);
+        gy = 1 + q / 2;
+        gx = (q & 1) ? W + 1 : 0;
+    }
+    const bool rng = h < RING, rng_inner = rng && inner_xy(i0 - 1 + gx, j0 - 1 + gy);
+    const int rng_off = (j0 - 1 + gy) * pitch + (i0 - 1 + gx);
+    auto zin = [n](int m) { return (unsigned)m < (unsigned)n; };
+    auto zinner = [n](int m) { return m >= 1 && m <= n - 2; };
+    auto x0_at = [&](int m, bool xy, int off) -> V { return (xy && zin(m)) ? x0[(long long)m * plane + off] : V(0); };
+    // x1 of the interior vertex at in-plane offset off of plane m; its in-plane
+    // x0 neighbours are staged at sx0[m & 1][ry][rx] +- 1
     struct Own {
         V kw, ke, ks, kn, kb, kt, bv;
     };
-    auto x1_own = [&](int m, V xb, V xt, Own &w) -> V {
-        if (!inner(i, j, m)) {
-            w = Own{V(0), V(0), V(0), V(0), V(0), V(0), V(0)};
-            return V(0);
-        }
-        const long long q = at(i, j, m);
+    auto x1_at = [&](int m, int off, int ry, int rx, V xb, V xt, Own &w) -> V {
+        const long long q = (long long)m * plane + off;
         w.kw = kval(L.kx[q - 1]);
         w.ke = kval(L.kx[q]);
         w.ks = kval(L.ky[q - pitch]);
@@ -626,69 +636,51 @@ __global__ __launch_bounds__(TX * ROWS) void k_post2(Lev<V, K> L, Tiling t, cons
         w.kb = kval(L.kz[q - plane]);
         w.kt = kval(L.kz[q]);
         w.bv = b[q];
-        const int ry = ly + 2, rx = lx + 2;
         const V(*t0)[W + 4] = sx0[m & 1];
         const V xc = t0[ry][rx];
-        const V ax = apply7(xc, t0[ry][rx - 1], t0[ry][rx + 1], t0[ry - 1][rx], t0[ry + 1][rx], xb, xt, w.kw,
-                            w.ke, w.ks, w.kn, w.kb, w.kt, L.s);
+        const V ax = apply7(xc, t0[ry][rx - 1], t0[ry][rx + 1], t0[ry - 1][rx], t0[ry + 1][rx], xb, xt, w.kw, w.ke,
+                            w.ks, w.kn, w.kb, w.kt, L.s);
         const V d = diag7(w.kw, w.ke, w.ks, w.kn, w.kb, w.kt, L.s);
         return cheb_step_val(xc, V(0), w.bv, ax, d, V(0), c0);
     };
-    // x0 of plane m into sx0[m & 1]: the thread's own value, then the ring
     auto stage_x0 = [&](int m, V own) {
         V(*t0)[W + 4] = sx0[m & 1];
         t0[ly + 2][lx + 2] = own;
-        const int h = (int)threadIdx.x;
-        if (h < HALO0) {
-            int ry, rx;
-            if (h < 4 * (W + 4)) {
-                const int r = h / (W + 4);
-                ry = r < 2 ? r : r + H;
-                rx = h % (W + 4);
-            } else {
-                const int r = h - 4 * (W + 4);
-                ry = 2 + r / 4;
-                rx = (r & 3) < 2 ? (r & 3) : (r & 3) + W;
-            }
-            t0[ry][rx] = vx0(i0 - 2 + rx, j0 - 2 + ry, m);
-        }
+        if (hal) t0[hy][hx] = x0_at(m, hal_xy, hal_off);
     };
-    // x1 of the ring of plane m into sx1[m & 1] (sx0[m & 1] holds plane m)
     auto ring_x1 = [&](int m) {
-        const int r = (int)threadIdx.x;
-        if (r < RING) {
-            int ry, rx;
-            if (r < 2 * (W + 2)) {
-                ry = r < W + 2 ? 0 : H + 1;
-                rx = r % (W + 2);
-            } else {
-                const int q = r - 2 * (W + 2);
-                ry = 1 + q / 2;
-                rx = (q & 1) ? W + 1 : 0;
+        if (rng) {
+            V v = V(0);
+            if (rng_inner && zinner(m)) {
+                Own w;
+                v = x1_at(m, rng_off, gy + 1, gx + 1, x0_at(m - 1, true, rng_off), x0_at(m + 1, true, rng_off), w);
             }
-            const int a = i0 - 1 + rx, c = j0 - 1 + ry;
-            sx1[m & 1][ry][rx] = x1_of(a, c, m, ry + 1, rx + 1, vx0(a, c, m - 1), vx0(a, c, m + 1));
+            sx1[m & 1][gy][gx] = v;
         }
     };
     // Phase m (m = k0-1 .. k1), one barrier each: x1 of plane m (from m = k0
     // on with its ring) from sx0[m & 1]; x2 of plane m-1 from sx1[(m-1) & 1];
     // x0 of plane m+1 staged into the other sx0 buffer.
-    V xb0 = vx0(i, j, k0 - 2), xc0 = vx0(i, j, k0 - 1);  // the thread's x0 at m-1, m
-    V x1b = V(0), x1c = V(0);                            // its x1 at m-2, m-1
+    V xb0 = x0_at(k0 - 2, own_xy, own_off), xc0 = x0_at(k0 - 1, own_xy, own_off);  // the thread's x0 at m-1, m
+    V x1b = V(0), x1c = V(0);                                                        // its x1 at m-2, m-1
     Own wc{}, wt{};
     double dot = 0.0, dotq = 0.0;
     stage_x0(k0 - 1, xc0);
     __syncthreads();
     for (int m = k0 - 1; m <= k1; ++m) {
-        const V xn0 = vx0(i, j, m + 1);
-        const V x1t = x1_own(m, xb0, xn0, wt);
+        const V xn0 = x0_at(m + 1, own_xy, own_off);
+        V x1t = V(0);
+        if (own_inner && zinner(m))
+            x1t = x1_at(m, own_off, ly + 2, lx + 2, xb0, xn0, wt);
+        else
+            wt = Own{V(0), V(0), V(0), V(0), V(0), V(0), V(0)};
         if (m >= k0 && m < k1) {
             sx1[m & 1][ly + 1][lx + 1] = x1t;
             ring_x1(m);
         }
         const int k = m - 1;
-        if (k >= k0 && inner(i, j, k)) {
-            const long long o = at(i, j, k);
+        if (k >= k0 && own_inner) {
+            const long long o = (long long)k * plane + own_off;
             const V(*t1)[W + 2] = sx1[k & 1];
             const V ax = apply7(x1c, t1[ly + 1][lx], t1[ly + 1][lx + 2], t1[ly][lx + 1], t1[ly + 2][lx + 1], x1b, x1t,
                                 wc.kw, wc.ke, wc.ks, wc.kn, wc.kb, wc.kt, L.s);

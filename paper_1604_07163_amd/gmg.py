@@ -145,7 +145,18 @@ def default_levels(n: int) -> int:
 
 
 class Solver:
-    """A hierarchy on the GPU plus its solver state (one handle)."""
+    """A hierarchy on the GPU plus its solver state (one handle).
+
+    kx, ky, kz: CUDA float64 link coefficients (shapes (N,N,N-1), (N,N-1,N),
+    (N-1,N,N); ln k with coeff_is_log).  Keyword options map one to one onto
+    gmg_options in include/gmg.h: levels (default log2(N-1)), precision
+    ("fp64" | "mixed"), switch_n (persistent coarse kernel for N_l <= switch_n,
+    0 = off), persistent_wgs / switch2_n (a team of workgroups, two-stage),
+    persistent_lds, coarse_rule ("arithmetic" | "harmonic"), cheb_degree /
+    cheb_lo / cheb_hi, coarse_solver ("exact" | "cg") with coarse_rtol /
+    coarse_max_it, flexible (Polak-Ribiere beta), galerkin (first Galerkin
+    level, 0 = none), post_fused ("auto" | True | False), check_every.
+    """
 
     def __init__(self, kx, ky, kz, *, levels=None, precision="fp64", switch_n=0, coarse_rule="arithmetic",
                  cheb_degree=2, cheb_lo=0.25, cheb_hi=2.0, coeff_is_log=False, check_every=0,

@@ -122,7 +122,10 @@ unsigned blocks_for(long long n, int nt) { return (unsigned)((n + nt - 1) / nt);
 // Workgroup-count targets of the z-marching stencil kernels (the z-chunk
 // length follows from them, at least kMinChunk planes).  Measured on MI355X:
 // 8-9 plane chunks stream best in FP64 and FP32 alike (at 1025^3 the MIXED
-// V-cycle kernels ran 15 % faster than with one chunk per column).
+// V-cycle kernels ran 15 % faster than with one chunk per column).  Levels
+// too small to give kMinWorkgroups workgroups that way take shorter chunks,
+// down to one plane: there a kernel is bound by the latency of its z-march
+// (129^3 .. 33^3 levels: a MIXED V-cycle at 257^3 8 % faster, 513^3 1.5 %).
 int env_int(const char *name, int dflt) {
     const char *e = getenv(name);
     const int v = e ? atoi(e) : 0;
@@ -130,6 +133,7 @@ int env_int(const char *name, int dflt) {
 }
 
 constexpr int kMinChunk = 8;
+constexpr int kMinWorkgroups = 1024;
 
 // width: x extent of a tile (TX, or TX2 for the two-points-per-lane apply);
 // rows: y extent (TY, or TY_PRE for the two-rows-per-thread pre-smoothing)
@@ -138,8 +142,12 @@ Tiling make_tiling(int n, int target, int width = gmg::TX, int rows = gmg::TY) {
     t.tiles_x = (n - 2) / width + 1;  // covers i = 0 .. n-2
     t.tiles_y = (n - 2 + rows - 1) / rows;
     const int planes = n - 2;
-    int nch = (target + t.tiles_x * t.tiles_y - 1) / (t.tiles_x * t.tiles_y);
+    const int tiles = t.tiles_x * t.tiles_y;
+    int nch = (target + tiles - 1) / tiles;
     if (nch > planes / kMinChunk) nch = planes / kMinChunk;
+    // small levels: too few workgroups to hide the latency of a long z-march,
+    // so chunks shorten (down to one plane) until kMinWorkgroups are launched
+    if ((long long)tiles * nch < kMinWorkgroups) nch = std::min(planes, (kMinWorkgroups + tiles - 1) / tiles);
     if (nch < 1) nch = 1;
     t.zchunk = (planes + nch - 1) / nch;
     nch = (planes + t.zchunk - 1) / t.zchunk;
@@ -1256,6 +1264,9 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
     ALLOC(h->Q, l0.nel);
     h->npartial = std::max(std::max(std::max(l0.til.nblocks, l0.til64.nblocks), l0.til2.nblocks),
                            std::max(std::max(l0.rows.nblocks, l0.tilq.nblocks), gmg::NB_FLAT));
+    for (int l = 1; l < h->L; ++l)  // coarse-level sums (truncated coarse CG, Lanczos) use their own tilings
+        h->npartial = std::max(h->npartial, std::max(std::max(h->lv[l].til.nblocks, h->lv[l].tilq.nblocks),
+                                                     h->lv[l].rows.nblocks));
     {
         const long long nfaces_blocks = blocks_for((long long)l0.n * l0.n * l0.n, 256);
         if (nfaces_blocks > h->npartial) h->npartial = (int)nfaces_blocks;

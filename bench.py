@@ -344,7 +344,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="inclusions513", choices=sorted(WORKLOADS))
-    ap.add_argument("--switch-n", type=int, default=17)
+    ap.add_argument("--switch-n", type=int, default=9)
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -99,3 +99,12 @@ def test_pmc_traffic_is_calibrated_by_the_copy(tmp_path, monkeypatch):
     assert bench.traffic_for("apply_dot", "test") is None  # sources changed since
     monkeypatch.setattr(bench, "traffic_file", lambda w: str(tmp_path / "absent.md"))
     assert bench.traffic_for("apply_dot", "test") is None
+
+
+def test_full_size_tests_use_the_benchmark_switch_level():
+    import re
+
+    from tests import test_gpu_configs
+    src = open(os.path.join(ROOT, "bench.py")).read()
+    default = int(re.search(r'"--switch-n", type=int, default=(\d+)', src).group(1))
+    assert test_gpu_configs.BENCH_SWITCH == default

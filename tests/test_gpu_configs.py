@@ -18,6 +18,7 @@ from tests.gpu_util import say, to_gpu, to_np
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+BENCH_SWITCH = 9  # the switch level bench.py times (its measured argmin)
 
 
 def golden(name):
@@ -38,7 +39,7 @@ def sample_rel(x, g):
     return float(np.linalg.norm(v - ref) / np.linalg.norm(ref))
 
 
-@pytest.mark.parametrize("switch_n", [0, 17])
+@pytest.mark.parametrize("switch_n", [0, 9, 17])
 def test_lognormal257_fp64(switch_n):
     g = golden("lognormal257")
     w = inputs.WORKLOADS["lognormal257"]
@@ -83,7 +84,7 @@ def test_lognormal257_mixed():
     n, levels = w["n"], w["levels"]
     kg = [to_gpu(a) for a in inputs.lognormal_k(n, w["k_seed"])]
     f = to_gpu(inputs.uniform_rhs(n, w["f_seed"]))
-    s = gmg.Solver(*kg, levels=levels, precision="mixed", switch_n=17)
+    s = gmg.Solver(*kg, levels=levels, precision="mixed", switch_n=BENCH_SWITCH)
     x, info = s.solve(f, rtol=1e-8)
     d = sample_rel(x, g)
     say(f"  mixed 257^3: its {info['iterations']} (oracle {g['iterations']}), restarts {info['restarts']}, "
@@ -119,7 +120,7 @@ def test_inclusions513_fp64_and_mixed():
     kx, ky, kz, _ = inputs.inclusion_k(n, w["k_seed"])
     kg = [to_gpu(a) for a in (kx, ky, kz)]
     f = to_gpu(inputs.uniform_rhs(n, w["f_seed"]))
-    s = gmg.Solver(*kg, levels=levels, switch_n=17)
+    s = gmg.Solver(*kg, levels=levels, switch_n=BENCH_SWITCH)
     x, info = s.solve(f, rtol=1e-8, max_it=2000)
     say(f"  513^3 fp64: its {info['iterations']} (oracle {g['iterations']}), {info['solve_ms']:.0f} ms")
     assert info["status"] == "GMG_OK" and abs(info["iterations"] - g["iterations"]) <= 1
@@ -129,7 +130,7 @@ def test_inclusions513_fp64_and_mixed():
     assert d <= 1e-10
     s.close()
     del s
-    sm = gmg.Solver(*kg, levels=levels, precision="mixed", switch_n=17)
+    sm = gmg.Solver(*kg, levels=levels, precision="mixed", switch_n=BENCH_SWITCH)
     xm, im = sm.solve(f, rtol=1e-8, max_it=2000)
     dm = sample_rel(xm, g)
     say(f"  513^3 mixed: its {im['iterations']}, restarts {im['restarts']}, true {im['rel_res_true']:.2e}, "
@@ -243,7 +244,7 @@ def test_lognormal1025_full_size_sampled():
     say("  generating 1025^3 inputs on the GPU")
     k = inputs.lognormal_k_gpu(n, w["k_seed"], clip=w["clip"])
     f = inputs.uniform_rhs_gpu(n, w["f_seed"])
-    s = gmg.Solver(*k, levels=levels, precision="mixed", switch_n=17)
+    s = gmg.Solver(*k, levels=levels, precision="mixed", switch_n=BENCH_SWITCH)
     x, info = s.solve(f, rtol=1e-8, max_it=500)
     say(f"  1025^3 mixed: its {info['iterations']}, true {info['rel_res_true']:.2e}, {info['solve_ms']:.0f} ms")
     assert info["status"] == "GMG_OK" and info["rel_res_true"] <= 1e-8

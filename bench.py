@@ -348,7 +348,7 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--sweep", action="store_true",
                     help="switch-level / truncation sweep of forward solves instead of the benchmark step")
     ap.add_argument("--teams", type=int, nargs="*", default=[],

@@ -35,11 +35,11 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # kernel class: every array read or written once, neighbours from cache.
 BYTES_PER_POINT = {
     "fp64": {"apply_dot": 40, "residual": 48, "update_r": 24, "update_xp": 40, "update_p": 16, "cheb_first": 24, "cheb_pre2": 48,
-             "cheb_step": 48, "cheb_step_prev": 56, "cheb_step_dot": 56, "level_residual": 48,
-             "restrict": 9, "prolong": 17, "face_gradient": 64, "cheb_post2": 56},
+             "cheb_step": 48, "cheb_step_prev": 56, "cheb_step_dot": 56, "level_residual": 44,
+             "restrict": 5, "prolong": 17, "face_gradient": 64, "cheb_post2": 56},
     "mixed": {"apply_dot": 36, "residual": 48, "update_r": 28, "update_xp": 28, "update_p": 8, "cheb_first": 20, "cheb_pre2": 18,
-              "cheb_step": 18, "cheb_step_prev": 22, "cheb_step_dot": 30, "level_residual": 18,
-              "restrict": 4.5, "prolong": 8.5, "face_gradient": 64, "cheb_post2": 26},
+              "cheb_step": 18, "cheb_step_prev": 22, "cheb_step_dot": 30, "level_residual": 16,
+              "restrict": 2.5, "prolong": 8.5, "face_gradient": 64, "cheb_post2": 26},
 }
 
 WORKLOADS = {
@@ -253,8 +253,8 @@ CLASS_KERNELS = {
     "cheb_step": "k_cheb_step<float, bf16, 0, false>",
     "cheb_step_dot": "k_cheb_step<float, bf16, 2, true>",
     "cheb_post2": "k_post2<float, bf16, true, 8>",
-    "level_residual": "k_residual<float, bf16>",
-    "restrict": "k_restrict<float>",
+    "level_residual": "k_residual_zr<float, bf16>",
+    "restrict": "k_restrict_xy<float>",
     "prolong": "k_prolong<float>",
 }
 def traffic_file(workload):

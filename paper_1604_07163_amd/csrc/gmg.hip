@@ -45,6 +45,7 @@ struct LevelHost {
     Tiling til2{};   // FP64 outer apply, two points per lane
     Tiling tilp{};   // pre-smoothing kernel, two rows per thread
     Tiling tilq{};   // one-sweep post-smoothing kernel
+    Tiling tilr{};   // residual with z-reduction (even z-chunks)
     bool post1 = false;  // post-smoothing in one sweep, its result in t1 (else in x)
     gmg::Rows rows{};
     // the buffer that holds the level's V-cycle result after post-smoothing
@@ -151,6 +152,16 @@ Tiling make_tiling(int n, int target, int width = gmg::TX, int rows = gmg::TY) {
     if (nch < 1) nch = 1;
     t.zchunk = (planes + nch - 1) / nch;
     nch = (planes + t.zchunk - 1) / t.zchunk;
+    t.nblocks = t.tiles_x * t.tiles_y * nch;
+    return t;
+}
+
+// The same tiling with an even number of planes per z-chunk (so every chunk
+// starts on an odd plane), for the residual with z-reduction.
+Tiling even_chunks(Tiling t, int n) {
+    const int planes = n - 2;
+    t.zchunk += t.zchunk & 1;
+    const int nch = (planes + t.zchunk - 1) / t.zchunk;
     t.nblocks = t.tiles_x * t.tiles_y * nch;
     return t;
 }
@@ -522,14 +533,19 @@ gmg_status residual_restrict(gmg_handle *h, int l, const int *skip) {
             gmg::k_sweep27<V, 1, 0><<<f.til.nblocks, gmg::NT, 0, h->stream>>>(
                 f.n, f.pitch, f.plane, f.til, (const V *)f.av, f.nel, (const V *)f.b, (const V *)f.x, nullptr,
                 (V *)f.t1, V(0), V(0), skip);
-        else
-            gmg::k_residual<V, K><<<f.til.nblocks, gmg::NT, 0, h->stream>>>(view<V, K>(f), f.til, (const V *)f.b,
-                                                                            (const V *)f.x, (V *)f.t1, skip);
+        else  // z-sums of the residual at the coarse planes, into t1
+            gmg::k_residual_zr<V, K><<<f.tilr.nblocks, gmg::NT, 0, h->stream>>>(view<V, K>(f), f.tilr,
+                                                                               (const V *)f.b, (const V *)f.x,
+                                                                               (V *)f.t1, skip);
         LAUNCHCHK();
     }
     Prof pf(h, GMG_K_RESTRICT, l == 0);
-    gmg::k_restrict<V><<<c.til.nblocks, gmg::NT, 0, h->stream>>>(c.n, c.pitch, c.plane, c.til, f.pitch, f.plane,
-                                                                 (const V *)f.t1, (V *)c.b, skip);
+    if (f.g27)
+        gmg::k_restrict<V><<<c.til.nblocks, gmg::NT, 0, h->stream>>>(c.n, c.pitch, c.plane, c.til, f.pitch, f.plane,
+                                                                     (const V *)f.t1, (V *)c.b, skip);
+    else
+        gmg::k_restrict_xy<V><<<c.til.nblocks, gmg::NT, 0, h->stream>>>(c.n, c.pitch, c.plane, c.til, f.pitch,
+                                                                        f.plane, (const V *)f.t1, (V *)c.b, skip);
     LAUNCHCHK();
     return GMG_OK;
 }
@@ -1216,6 +1232,7 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
         lh.til64 = make_tiling(n, t64);
         lh.til2 = make_tiling(n, t64, gmg::TX2);
         lh.tilp = make_tiling(n, env_int("GMG_TARGET_WGS_V", 1 << 20), gmg::TX, gmg::TY_PRE);
+        lh.tilr = even_chunks(lh.til, n);
         // one-sweep post-smoothing: 32-plane chunks at 513^3 (measured best for
         // both precisions; its two extra x1 planes per chunk favour long chunks)
         lh.tilq = mx ? make_tiling(n, env_int("GMG_TARGET_WGS_POST", 8192), gmg::TX, gmg::TY_POST32)

@@ -711,26 +711,45 @@ __global__ __launch_bounds__(TX * ROWS) void k_post2(Lev<V, K> L, Tiling t, cons
 }
 
 // ---------------------------------------------------------------- transfer operators
-// Full-weighting restriction of the residual, summed in a fixed order:
-// x first, then y, then z, each with weights (1/4, 1/2, 1/4).
-// Full weighting b_c = R r at coarse vertex (I,J,K) from a stored fine residual
-// r (the 27 fine vertices of an interior coarse vertex are interior): weights
-// (1/4, 1/2, 1/4) summed x first, then y, then z.
+// Full-weighting restriction b_c = R r, weights (1/4, 1/2, 1/4) per axis,
+// summed in one fixed order on every path: z first (the three fine planes of
+// a fine column), then x, then y.
+template <typename V>
+__device__ __forceinline__ V zsum3(V lo, V mid, V hi) {
+    V acc = fmaT(V(0.25), lo, V(0));
+    acc = fmaT(V(0.5), mid, acc);
+    return fmaT(V(0.25), hi, acc);
+}
+// the in-plane 3 x 3 weighting of z-summed values s around offset base: x, then y
+template <typename V>
+__device__ __forceinline__ V plane_sum(const V *s, long long base, int pf) {
+    const V w[3] = {V(0.25), V(0.5), V(0.25)};
+    V accy = V(0);
+#pragma unroll
+    for (int bb = 0; bb < 3; ++bb) {
+        const V *row = s + base + (long long)(bb - 1) * pf;
+        V accx = V(0);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) accx = fmaT(w[a], row[a - 1], accx);
+        accy = fmaT(w[bb], accx, accy);
+    }
+    return accy;
+}
+// b_c at coarse vertex (I,J,K) from a stored fine residual r (the 27 fine
+// vertices of an interior coarse vertex are interior).
 template <typename V>
 __device__ __forceinline__ V restrict_at(const V *r, int pf, long long plf, int I, int J, int K_) {
     const V w[3] = {V(0.25), V(0.5), V(0.25)};
-    V accz = V(0);
-    for (int c = 0; c < 3; ++c) {
-        V accy = V(0);
-        for (int bb = 0; bb < 3; ++bb) {
-            V accx = V(0);
-            const long long row = (long long)(2 * K_ + c - 1) * plf + (long long)(2 * J + bb - 1) * pf + 2 * I - 1;
-            for (int a = 0; a < 3; ++a) accx = fmaT(w[a], r[row + a], accx);
-            accy = fmaT(w[bb], accx, accy);
+    V accy = V(0);
+    for (int bb = 0; bb < 3; ++bb) {
+        V accx = V(0);
+        for (int a = 0; a < 3; ++a) {
+            const long long o = (long long)(2 * K_) * plf + (long long)(2 * J + bb - 1) * pf + 2 * I + a - 1;
+            accx = fmaT(w[a], zsum3(r[o - plf], r[o], r[o + plf]), accx);
         }
-        accz = fmaT(w[c], accy, accz);
+        accy = fmaT(w[bb], accx, accy);
     }
-    return accz;
+    return accy;
 }
 // (P e) at fine vertex (i,j,k): trilinear, tensor product of the 1D rules
 // (even index -> coarse i/2, odd -> mean of (i-1)/2 and (i+1)/2).
@@ -758,24 +777,9 @@ __device__ __forceinline__ V prolong_at(const V *e, int pc, long long plc, int i
     return accz;
 }
 
-// b_c = R r for a fine residual r held in memory (written by k_residual).
-// One thread per coarse column (I, J) marching in K; the in-plane 3x3 sum of
-// fine plane 2K+1 is reused as the lower plane of K+1.  The summation order
-// is that of restrict_at, so both paths round identically.
-template <typename V>
-__device__ __forceinline__ V plane_sum(const V *r, long long base, int pf) {
-    const V w[3] = {V(0.25), V(0.5), V(0.25)};
-    V accy = V(0);
-#pragma unroll
-    for (int bb = 0; bb < 3; ++bb) {
-        const V *row = r + base + (long long)(bb - 1) * pf;
-        V accx = V(0);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) accx = fmaT(w[a], row[a - 1], accx);
-        accy = fmaT(w[bb], accx, accy);
-    }
-    return accy;
-}
+// b_c = R r for a fine residual r held in memory (Galerkin levels, written by
+// the 27-point residual sweep).  One thread per coarse column (I, J) marching
+// in K; the order of restrict_at, so both paths round identically.
 template <typename V>
 __global__ __launch_bounds__(NT) void k_restrict(int nc, int pc, long long plc, Tiling t, int pf, long long plf,
                                                  const V *__restrict__ r, V *__restrict__ bc,
@@ -783,18 +787,66 @@ __global__ __launch_bounds__(NT) void k_restrict(int nc, int pc, long long plc, 
     if (skip && *skip) return;
     const Column c = tile_column(nc, t);
     if (!c.active) return;
-    const long long col = (long long)(2 * c.j) * pf + 2 * c.i;
-    V lo = plane_sum(r, (long long)(2 * c.k0 - 1) * plf + col, pf);
     long long oc = (long long)c.k0 * plc + (long long)c.j * pc + c.i;
-    for (int K = c.k0; K < c.k1; ++K, oc += plc) {
-        const V mid = plane_sum(r, (long long)(2 * K) * plf + col, pf);
-        const V hi = plane_sum(r, (long long)(2 * K + 1) * plf + col, pf);
-        V acc = fmaT(V(0.25), lo, V(0));
-        acc = fmaT(V(0.5), mid, acc);
-        acc = fmaT(V(0.25), hi, acc);
-        bc[oc] = acc;
-        lo = hi;
+    for (int K = c.k0; K < c.k1; ++K, oc += plc) bc[oc] = restrict_at(r, pf, plf, c.i, c.j, K);
+}
+
+// The residual of a 7-point level reduced along z on the fly: the thread of
+// fine column (i, j) computes r = b - A u plane by plane (the arithmetic of
+// k_residual) and stores, for each coarse plane K of its chunk, the z-sum
+// s(i,j,K) = r(2K-1)/4 + r(2K)/2 + r(2K+1)/4 at s[K * plane + j * pitch + i]
+// (fine rows, coarse plane index).  Chunks have an even number of planes and
+// start on an odd plane, so a chunk needs one plane beyond its end (its
+// neighbour computes that plane too).  Half the fine writes of a stored
+// residual, and the restriction that follows reads half as much.
+template <typename V, typename K>
+__global__ __launch_bounds__(NT) void k_residual_zr(Lev<V, K> L, Tiling t, const V *__restrict__ b,
+                                                    const V *__restrict__ u, V *__restrict__ s,
+                                                    const int *__restrict__ skip) {
+    if (skip && *skip) return;
+    const Column c = tile_column(L.n, t);
+    if (!c.active) return;
+    const int pitch = L.pitch;
+    const long long plane = L.plane;
+    // N - 1 is even on a level that restricts, so k1 is odd, or N - 1 with
+    // N - 2 (odd) the last plane needed: the march always ends on an odd plane
+    const int kend = min(c.k1, L.n - 2);
+    long long o = (long long)c.k0 * plane + (long long)c.j * pitch + c.i;
+    V ub = u[o - plane], up = u[o];
+    V kb = kval(L.kz[o - plane]);
+    V acc = V(0);
+    for (int k = c.k0; k <= kend; ++k, o += plane) {
+        const V ut = u[o + plane];
+        const V uw = u[o - 1], ue = u[o + 1], us = u[o - pitch], un = u[o + pitch];
+        const V kw = kval(L.kx[o - 1]), ke = kval(ldnt(&L.kx[o])), ks = kval(L.ky[o - pitch]),
+                kn = kval(L.ky[o]), kt = kval(ldnt(&L.kz[o]));
+        const V r = ldnt(&b[o]) - apply7(up, uw, ue, us, un, ub, ut, kw, ke, ks, kn, kb, kt, L.s);
+        if (k & 1) {
+            if (k > c.k0) {  // closes coarse plane (k-1)/2
+                const long long os = (long long)((k - 1) >> 1) * plane + (long long)c.j * pitch + c.i;
+                stnt(fmaT(V(0.25), r, acc), &s[os]);
+            }
+            acc = fmaT(V(0.25), r, V(0));  // opens coarse plane (k+1)/2
+        } else {
+            acc = fmaT(V(0.5), r, acc);
+        }
+        ub = up;
+        up = ut;
+        kb = kt;
     }
+}
+
+// b_c = R r from the z-sums of k_residual_zr: the in-plane 3x3 weighting.
+template <typename V>
+__global__ __launch_bounds__(NT) void k_restrict_xy(int nc, int pc, long long plc, Tiling t, int pf, long long plf,
+                                                    const V *__restrict__ s, V *__restrict__ bc,
+                                                    const int *__restrict__ skip) {
+    if (skip && *skip) return;
+    const Column c = tile_column(nc, t);
+    if (!c.active) return;
+    const long long col = (long long)(2 * c.j) * pf + 2 * c.i;
+    long long oc = (long long)c.k0 * plc + (long long)c.j * pc + c.i;
+    for (int K = c.k0; K < c.k1; ++K, oc += plc) bc[oc] = plane_sum(s, (long long)K * plf + col, pf);
 }
 
 // x += P e by coarse cells: the thread of cell (I,J,K) reads its 8 corner

@@ -32,6 +32,15 @@
  *  * Nothing aborts and no exception crosses the ABI: every call returns a
  *    gmg_status; gmg_last_error() gives a per-handle message.
  *  * A handle is not thread-safe; distinct handles are independent.
+ *  * Launch-shape overrides (read once, in gmg_create; unset or <= 0 keeps the
+ *    measured default; results do not change, only timing, except that the
+ *    grouping of partial sums in reductions follows the workgroup count):
+ *      GMG_TARGET_WGS_V     workgroups targeted by the V-cycle stencil sweeps
+ *                           (smoothing, residual; both precisions)
+ *      GMG_TARGET_WGS_64    the same for the outer FP64 apply and true residual
+ *      GMG_TARGET_WGS_POST  the same for the one-sweep post-smoother
+ *    A target sets the z-chunk length of a launch (at least 8 planes where
+ *    that still yields 1024 workgroups).
  */
 #ifndef GMG_H
 #define GMG_H

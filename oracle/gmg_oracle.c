@@ -31,8 +31,11 @@
  * quadratic solution, dense assembly, the Chebyshev polynomial, the adjoint
  * of restriction/prolongation, dense two-grid composition, finite
  * differences; for the reduced-precision mode: exact rational bfloat16
- * rounding and a dense composition from the rounded level matrices).  No
- * routine is "parity unpinned".
+ * rounding and a dense composition from the rounded level matrices).  One
+ * step has no pin of its own: the reduced-precision PCG rounds its search
+ * direction to FP32, and no observable of the solve isolates that rounding
+ * (the solve as a whole is pinned by convergence to the dense solution), so
+ * that step is "parity unpinned".
  */
 #include <math.h>
 #include <stdint.h>

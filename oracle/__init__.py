@@ -98,6 +98,8 @@ def lib():
         L.or_set_mixed.restype = I
         L.or_last_restarts.argtypes = [P]
         L.or_last_restarts.restype = I
+        L.or_last_direction.argtypes = [P, P]
+        L.or_last_direction.restype = I
         L.or_round_bf16_raw.argtypes = [ctypes.c_size_t, P, P]
         L.or_round_f32.argtypes = [D]
         L.or_round_f32.restype = D
@@ -361,6 +363,13 @@ class Hierarchy:
         return x, {"status": STATUS[st], "iterations": its.value, "rel_res": rr.value,
                    "rel_res_true": rt.value, "coarse_iterations": cits.value,
                    "restarts": lib().or_last_restarts(self._h)}
+
+    def last_direction(self):
+        """The CG search direction as the last solve left it (test observable)."""
+        p = np.empty((self.n, self.n, self.n))
+        if lib().or_last_direction(self._h, _p(p)) != 0:
+            raise OracleError(1)
+        return p
 
     def adjoint_gradient(self, phi, dl_dphi, rtol=1e-12, max_it=200):
         """Return (g_x, g_y, g_z, lambda, info): g = dL/d(ln k) on the face arrays."""

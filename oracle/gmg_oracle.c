@@ -31,11 +31,9 @@
  * quadratic solution, dense assembly, the Chebyshev polynomial, the adjoint
  * of restriction/prolongation, dense two-grid composition, finite
  * differences; for the reduced-precision mode: exact rational bfloat16
- * rounding and a dense composition from the rounded level matrices).  One
- * step has no pin of its own: the reduced-precision PCG rounds its search
- * direction to FP32, and no observable of the solve isolates that rounding
- * (the solve as a whole is pinned by convergence to the dense solution), so
- * that step is "parity unpinned".
+ * rounding, a dense composition from the rounded level matrices, and the
+ * FP32 search direction read back through or_last_direction).  No routine is
+ * "parity unpinned".
  */
 #include <math.h>
 #include <stdint.h>
@@ -702,6 +700,8 @@ typedef struct {
     long coarse_its;       /* coarse CG iterations since the last reset */
     int mixed;             /* 1: reduced-precision preconditioner (or_set_mixed) */
     int restarts;          /* true-residual restarts of the last CG solve */
+    double *last_p;        /* the search direction as the last CG solve left it (N^3), an
+                              observable for the tests; NULL before the first solve */
 } or_hier;
 
 enum { OR_OK = 0, OR_ERR_ARG = 1, OR_ERR_DIMS = 2, OR_ERR_COEFF = 3, OR_ERR_NOMEM = 4,
@@ -727,6 +727,7 @@ void or_destroy(void *hp)
         free(H->lv[l].work);
     }
     free(H->chol);
+    free(H->last_p);
     free(H);
 }
 
@@ -1251,11 +1252,26 @@ static int pcg_impl(void *hp, const double *f, double *x, double rtol, int max_i
     if (st == OR_OK && H->mixed && !(*relres_true <= rtol))
         st = OR_ERR_NOT_CONVERGED;
 done:
+    if (!H->last_p)
+        H->last_p = (double *)malloc(sizeof(double) * nv);
+    if (H->last_p)
+        memcpy(H->last_p, p, sizeof(double) * nv);
     free(b); free(r); free(z); free(p); free(q);
     return st;
 }
 
 int or_last_restarts(void *hp) { return ((or_hier *)hp)->restarts; }
+
+/* The search direction p as the last CG solve left it: the direction the
+ * next x update would use (after a solve stopped by max_it), N^3 values. */
+int or_last_direction(void *hp, double *out)
+{
+    or_hier *H = (or_hier *)hp;
+    if (!H || !out || !H->last_p)
+        return OR_ERR_ARG;
+    memcpy(out, H->last_p, sizeof(double) * nvert(H->lv[0].n));
+    return OR_OK;
+}
 
 /* ------------------------------------------------------------------------ */
 /* Adjoint gradient.  With A(k) phi = f and a loss L(phi):                  */

@@ -154,6 +154,43 @@ def test_mixed_pcg_reaches_dense_solution(oracle_mod):
     np.testing.assert_allclose(mf.interior(x), ref, rtol=1e-10, atol=1e-11 * np.abs(ref).max())
 
 
+def update_ratio(x0, x1, p):
+    """x1 - x0 over p where p is not small: one scalar (the CG step length)
+    if p is the direction that moved x0 to x1."""
+    d, pi = mf.interior(x1) - mf.interior(x0), mf.interior(p)
+    big = np.abs(pi) > 1e-3 * np.abs(pi).max()
+    ratio = d[big] / pi[big]
+    mid = np.median(ratio)
+    return mid, np.abs(ratio - mid).max() / abs(mid)
+
+
+def test_mixed_search_direction_is_fp32(oracle_mod):
+    """The mixed CG moves x along an FP32 search direction: the direction the
+    oracle leaves after m iterations is the one that takes x_m to x_{m+1}
+    (x_{m+1} - x_m is a scalar multiple of it, to FP64 roundoff), and every
+    value of it is an FP32 number.  The FP64 solve's direction is not, so the
+    check would see a direction left unrounded."""
+    n, levels = 17, 3
+    k = rand_k(n, 81)
+    f = inputs.uniform_rhs(n, 82)
+    Hm = oracle_mod.Hierarchy(*k, levels=levels, precision="mixed")
+    H = oracle_mod.Hierarchy(*k, levels=levels)
+    for m in (1, 2, 3):
+        xm, info = Hm.solve(f, rtol=0.0, max_it=m)
+        assert info["iterations"] == m and info["restarts"] == 0
+        p = Hm.last_direction()
+        np.testing.assert_array_equal(p, f32(p))
+        assert np.abs(mf.interior(p)).max() > 0
+        x_next, _ = Hm.solve(f, rtol=0.0, max_it=m + 1)
+        alpha, spread = update_ratio(xm, x_next, p)
+        assert alpha > 0 and spread <= 1e-9, (m, spread)
+        x64, _ = H.solve(f, rtol=0.0, max_it=m)
+        p64 = H.last_direction()
+        x64_next, _ = H.solve(f, rtol=0.0, max_it=m + 1)
+        assert update_ratio(x64, x64_next, p64)[1] <= 1e-9
+        assert not np.array_equal(p64, f32(p64))
+
+
 @pytest.mark.parametrize("n,levels", [(33, 5), (65, 6)])
 def test_mixed_pcg_iterations_match_fp64(oracle_mod, n, levels):
     """With coefficients that bfloat16 holds exactly on every level (constant k)

@@ -157,7 +157,7 @@ def test_adjoint129_against_oracle_and_finite_differences():
     loss = 0.5 * ((phi - phi_obs) ** 2).sum()
     loss.backward()
     grads = [t.grad for t in theta]
-    say(f"  loss {float(loss):.10e} (oracle {g['loss']:.10e})")
+    say(f"  loss {float(loss.detach()):.10e} (oracle {g['loss']:.10e})")
     assert abs(float(loss) - g["loss"]) <= 1e-9 * g["loss"]
     gmax = g["gmax"]
     for (ax, kk, jj, ii), ref in zip(g["faces"], g["gradient"]):

@@ -158,7 +158,7 @@ def test_adjoint129_against_oracle_and_finite_differences():
     loss.backward()
     grads = [t.grad for t in theta]
     say(f"  loss {float(loss.detach()):.10e} (oracle {g['loss']:.10e})")
-    assert abs(float(loss) - g["loss"]) <= 1e-9 * g["loss"]
+    assert abs(float(loss.detach()) - g["loss"]) <= 1e-9 * g["loss"]
     gmax = g["gmax"]
     for (ax, kk, jj, ii), ref in zip(g["faces"], g["gradient"]):
         got = float(grads[ax][kk, jj, ii])

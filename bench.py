@@ -363,7 +363,7 @@ def main():
     ap.add_argument("--galerkin", type=int, nargs="*", default=[],
                     help="with --sweep: also time Galerkin coarse operators from these first levels")
     ap.add_argument("--post-fused", default="auto", choices=["auto", "0", "1"],
-                    help="one-sweep post-smoothing: auto (the library default: FP64 only), 0 never, 1 always")
+                    help="one-sweep post-smoothing: auto (the library default: one sweep), 0 two sweeps, 1 one sweep")
     args = ap.parse_args()
     if args.profile_summary:
         profile_summary(args.profile_summary)

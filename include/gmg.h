@@ -117,12 +117,12 @@ typedef struct {
                                result is the same either way. */
     int32_t post_fused;     /* on grid-path link levels with cheb_degree 2: 1 = the
                                post-smoothing runs as one sweep that keeps the first Chebyshev
-                               iterate in LDS; 0 = two sweeps through HBM; 2 (default) = one
-                               sweep in FP64, two in MIXED (measured at 513^3: FP64 1.7 ms
-                               vs 2.9 ms; MIXED 1.02 ms vs 1.21 ms, where the one sweep is
-                               instruction-bound and the two keep each kernel near the HBM
-                               bound).  Same values to the bit; only the partial sums of r.z
-                               are grouped differently. */
+                               iterate in LDS; 0 = two sweeps through HBM; 2 (default) = the
+                               library's choice, currently the one sweep in both precisions
+                               (measured at 513^3: FP64 1.7 ms vs 2.9 ms; MIXED 1.02 ms vs
+                               1.21 ms, a 3.9 % shorter MIXED solve although the one sweep is
+                               instruction-bound at 43 % of HBM peak).  Same values to the bit;
+                               only the partial sums of r.z are grouped differently. */
 } gmg_options;
 
 typedef struct {

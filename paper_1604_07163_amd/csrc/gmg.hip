@@ -1263,7 +1263,7 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
     }
     // one-sweep post-smoothing on the grid-path link levels (degree 2)
     for (int l = 0; l < h->s_persist; ++l)
-        h->lv[l].post1 = (o.post_fused == 1 || (o.post_fused == 2 && !mx)) && !h->lv[l].g27 && o.cheb_degree == 2;
+        h->lv[l].post1 = (o.post_fused == 1 || o.post_fused == 2) && !h->lv[l].g27 && o.cheb_degree == 2;
     // allocations
     gmg_status s;
     LevelHost &l0 = h->lv[0];

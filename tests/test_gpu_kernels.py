@@ -199,7 +199,7 @@ def test_post_smoothing_one_sweep_bitwise(n, levels, precision):
     kg = [to_gpu(a) for a in k]
     for sw in (0, 9):
         say(f"  post-smoothing n={n} levels={levels} {precision} switch={sw}")
-        sf = gmg.Solver(*kg, levels=levels, precision=precision, switch_n=sw)
+        sf = gmg.Solver(*kg, levels=levels, precision=precision, switch_n=sw, post_fused=True)
         su = gmg.Solver(*kg, levels=levels, precision=precision, switch_n=sw, post_fused=False)
         for l in range(levels - 1):
             nl = sf.level_n(l)

@@ -4,19 +4,24 @@
 Workload (default "inclusions513"): -div(k grad phi) = f on a 513^3 vertex grid
 (511^3 = 133,432,831 unknowns), two-phase k (random spheres, radius 4-16 cells,
 20 % volume, k = 1e3 inside, 1 outside), f ~ U(-1,1), 9 levels (coarsest 3^3),
-Chebyshev-Jacobi degree 2 pre/post, levels N <= 17 agglomerated into the
+Chebyshev-Jacobi degree 2 pre/post, levels N <= 9 agglomerated into the
 persistent coarse kernel.
 
 One step = the whole hot path once:
   hierarchy setup from k  ->  mixed-precision PCG solve to an FP64 relative
   residual of 1e-8  ->  adjoint gradient dL/d ln k for L = 0.5 ||phi - phi_obs||^2
   (adjoint PCG solve + link-gradient kernel).
-value = fine-grid unknowns solved per second = 2 solves x 511^3 / step time.
-The same step in plain FP64 is timed beside it (speedup, error).
+value = fine-grid unknowns solved per second = 2 solves x 511^3 / step time,
+with the steps timed with kernel profiling off; every timed solve must reach
+the tolerance (else the run fails).  Beside it: T_solve, the median of 5
+forward solves with setup excluded, as unknowns/s; the same figures for plain
+FP64; the error of both forward solutions against the stored FP64 oracle
+solution (sampled); per-kernel HBM figures from one separate profiled step;
+the agglomeration sweep on 33^3-129^3 grids; the 1025^3 combined workload.
 
-Inputs are generated on the host and copied to HBM before the timed region.
-Kernel durations come from HIP events the library records around every
-finest-level launch on its stream during the timed steps.
+Inputs are generated on the host (1025^3: on the GPU) and copied to HBM before
+the timed region.  Kernel durations come from HIP events the library records
+around every finest-level launch on its stream during the profiled step.
 """
 from __future__ import annotations
 
@@ -88,8 +93,17 @@ def _host(a):
     return a.cpu().numpy() if torch.is_tensor(a) else a
 
 
+def check_leg(info, rtol, what):
+    """A timed solve that did not converge must not be reported as throughput."""
+    if info["status"] != "GMG_OK" or not (info["rel_res_true"] <= rtol):
+        raise RuntimeError(f"{what}: status {info['status']}, FP64 true relative residual "
+                           f"{info['rel_res_true']:.3e} (tolerance {rtol:.1e})")
+
+
 def run_steps(solver, k, f, phi_obs, steps, rtol, profile=False):
-    """Time `steps` full steps; returns (seconds per step list, last infos, profile dict)."""
+    """Run `steps` full steps; returns (seconds per step, last forward and adjoint
+    infos, kernel-class profile (profile=True only), last forward solution).
+    Every solve's status and true residual are checked."""
     import torch
     from paper_1604_07163_amd import gmg
     times, fwd, adj, phi = [], None, None, None
@@ -105,9 +119,52 @@ def run_steps(solver, k, f, phi_obs, steps, rtol, profile=False):
         gx, gy, gz, lam, adj = solver.adjoint_gradient(phi, dl, rtol=rtol, max_it=2000, want_lambda=False)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
+        check_leg(fwd, rtol, "forward solve")
+        check_leg(adj, rtol, "adjoint solve")
     if prof:
         prof.__exit__(None, None, None)
     return times, fwd, adj, (prof.result if prof else {}), phi
+
+
+def t_solve(solver, f, rtol, reps=5):
+    """Median of `reps` forward solves from x0 = 0 (setup excluded), each timed
+    by the library with HIP events on its stream; after one untimed solve."""
+    import numpy as np
+    solver.solve(f, rtol=rtol, max_it=2000)
+    ms, info = [], None
+    for _ in range(reps):
+        _, info = solver.solve(f, rtol=rtol, max_it=2000)
+        check_leg(info, rtol, "forward solve")
+        ms.append(info["solve_ms"])
+    return float(np.median(ms)), info
+
+
+def kernel_table(prof, prec, n_unk):
+    out = {}
+    for c, v in prof.items():
+        entry = dict(v)
+        if c in BYTES_PER_POINT[prec]:
+            entry["GBs"] = BYTES_PER_POINT[prec][c] * n_unk / (v["avg_ms"] / 1e3) / 1e9
+            entry["frac_peak"] = entry["GBs"] / HBM_PEAK_GBS
+        out[c] = entry
+    return out
+
+
+def error_vs_oracle(x, workload):
+    """Sampled relative L2 difference between a forward solution and the stored
+    FP64 oracle solution of the same workload (4096 seeded interior points,
+    written by tests/golden/make_golden.py from the oracle alone), or None."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", f"oracle_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    g = json.load(open(path))
+    import torch
+    pts = torch.as_tensor(np.asarray(g["sample_points"]), device=x.device)
+    ref = np.asarray(g["sample_values"])
+    v = x[pts[:, 0], pts[:, 1], pts[:, 2]].cpu().numpy()
+    return {"rel_l2_sampled": float(np.linalg.norm(v - ref) / np.linalg.norm(ref)), "samples": int(len(ref)),
+            "oracle_iterations": g["iterations"], "oracle_rel_res_true": g["rel_res_true"]}
 
 
 def copy_bandwidth(nbytes=2 << 30, reps=5):
@@ -130,28 +187,43 @@ def copy_bandwidth(nbytes=2 << 30, reps=5):
 
 
 def cpu_baseline(w, k, f, its_needed, iters=2):
-    """Time the FP64 CPU oracle for `iters` PCG iterations at the full size and
-    scale to the iteration count the solve needs (setup not timed)."""
+    """Time the FP64 CPU oracle for `iters` PCG iterations at the full size on
+    all the host threads OpenMP uses, then one iteration on one thread, and
+    scale both to the iteration count the solve needs (setup not timed)."""
+    import ctypes
     import oracle
     oracle.build(force=False)
     H = oracle.Hierarchy(*k, levels=w["levels"])
     t0 = time.perf_counter()
     _, info = H.solve(f, rtol=1e-8, max_it=iters)
     dt = time.perf_counter() - t0
-    H.close()
     per_it = dt / max(info["iterations"], 1)
-    t_solve = per_it * its_needed
     n_unk = (w["n"] - 2) ** 3
     cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
-    return {"value": n_unk / t_solve, "unit": "unknowns/s", "cores": cores, "kind": "oracle",
-            "sample": f"{info['iterations']} FP64 PCG iterations of the oracle at {w['n']}^3 "
-                      f"({dt:.1f} s, setup excluded), scaled to the {its_needed} iterations of one solve",
-            "seconds_per_iteration": per_it}
+    out = {"value": n_unk / (per_it * its_needed), "unit": "unknowns/s", "cores": cores, "kind": "oracle",
+           "sample": f"{info['iterations']} FP64 PCG iterations of the oracle at {w['n']}^3 "
+                     f"({dt:.1f} s, setup excluded), scaled to the {its_needed} iterations of one solve",
+           "seconds_per_iteration": per_it}
+    try:  # the same loop on one thread (the oracle's OpenMP runtime)
+        gomp = ctypes.CDLL("libgomp.so.1")
+        gomp.omp_set_num_threads(1)
+        t0 = time.perf_counter()
+        _, i1 = H.solve(f, rtol=1e-8, max_it=1)
+        dt1 = time.perf_counter() - t0
+        gomp.omp_set_num_threads(cores)
+        out["one_thread"] = {"value": n_unk / (dt1 * its_needed), "seconds_per_iteration": dt1,
+                             "sample": "1 FP64 PCG iteration of the oracle on 1 thread, scaled likewise"}
+    except OSError:
+        pass
+    H.close()
+    return out
 
 
 def sweep(args):
     """Switch-level sweep (grid launches vs the persistent coarse kernel) and the
-    truncation arm, forward solves on the chosen workload; prints one JSON line."""
+    truncation arm, forward solves on the chosen workload; prints one JSON line.
+    Every solve must converge; the iteration count must not depend on the
+    switch level, LDS staging or team size (they change no arithmetic)."""
     import numpy as np
     import torch
     from paper_1604_07163_amd import gmg
@@ -175,29 +247,138 @@ def sweep(args):
         configs.append(dict(precision="fp64", levels=lt, coarse_solver="cg", coarse_rtol=1e-4, flexible=True))
     for g in args.galerkin:  # Galerkin (g = 1) or hybrid (g > 1) coarse operators
         configs += [dict(precision=p, switch_n=sw, galerkin=g) for p in ("fp64", "mixed") for sw in (0, 17)]
+    base_its = {}
     for cfg in configs:
         kw = dict(cfg)
         lv = kw.pop("levels", levels)
         s = gmg.Solver(*k, levels=lv, **kw)
-        s.solve(f, rtol=args.rtol, max_it=3000)
-        ts, info = [], None
-        for _ in range(max(1, args.steps)):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            _, info = s.solve(f, rtol=args.rtol, max_it=3000)
-            torch.cuda.synchronize()
-            ts.append(time.perf_counter() - t0)
+        ms, info = t_solve(s, f, args.rtol, reps=max(1, args.steps))
         with gmg.Profile(s) as pr:
             s.solve(f, rtol=args.rtol, max_it=3000)
         coarse = pr.result.get("persistent") or pr.result.get("coarse_solve") or {}
+        if lv == levels and not cfg.get("galerkin"):  # same arithmetic for every switch / team / LDS row
+            ref = base_its.setdefault(cfg["precision"], info["iterations"])
+            if info["iterations"] != ref:
+                raise RuntimeError(f"{cfg}: {info['iterations']} iterations, {ref} with the grid path")
         row = {"levels": lv, **cfg, "iterations": info["iterations"], "coarse_iterations": info["coarse_iterations"],
-               "ms": 1e3 * float(np.median(ts)), "ms_per_iteration": 1e3 * float(np.median(ts)) / info["iterations"],
+               "ms": ms, "ms_per_iteration": ms / info["iterations"],
                "coarse_kernel_us": 1e3 * coarse.get("avg_ms", 0.0), "rel_res_true": info["rel_res_true"],
                "setup_ms": info["setup_ms"], "lds_bytes": s.persistent_lds_bytes}
         log(json.dumps(row))
         rows.append(row)
         s.close()
     print(json.dumps({"workload": args.workload, "n": n, "rtol": args.rtol, "rows": rows}), flush=True)
+
+
+def agglomeration_sweep(rtol=1e-8, reps=5, teams=(1, 8, 32)):
+    """Forward solves on the small grids where the coarse levels are launch- and
+    latency-bound: the 33^3 constant-k sine problem (4 levels, coarsest 5^3) and
+    log-normal grids (contrast 1e4) at 65^3 and 129^3, for every switch level
+    (0 = grid launches on every level) and persistent team size, FP64 and
+    MIXED.  Every solve must converge and, per grid and precision, take the same
+    iteration count on every row.  Returns per grid the rows (median of `reps`
+    solves, setup excluded; the coarse part's microseconds per V-cycle) and the
+    argmin per precision."""
+    import torch
+    from paper_1604_07163_amd import gmg, inputs
+    out = {}
+    for n in (33, 65, 129):
+        if n == 33:
+            name, levels, k_in, f_in = "poisson33", 4, inputs.const_k(n), inputs.sine_rhs(n)
+        else:
+            name, levels = f"lognormal{n}", gmg.default_levels(n)
+            k_in, f_in = inputs.lognormal_k(n, 2), inputs.uniform_rhs(n, 3)
+        k = [torch.from_numpy(a).cuda() for a in k_in]
+        f = torch.from_numpy(f_in).cuda()
+        switches = [0] + [sw for sw in (65, 33, 17, 9) if sw < n]
+        rows, best = [], {}
+        for prec in ("fp64", "mixed"):
+            its = None
+            for sw in switches:
+                for team in (teams if sw > 0 else (1,)):
+                    s = gmg.Solver(*k, levels=levels, precision=prec, switch_n=sw, persistent_wgs=team)
+                    ms, info = t_solve(s, f, rtol, reps)
+                    with gmg.Profile(s) as pr:
+                        s.solve(f, rtol=rtol, max_it=2000)
+                    s.close()
+                    coarse = pr.result.get("persistent") or pr.result.get("coarse_solve") or {}
+                    its = info["iterations"] if its is None else its
+                    if info["iterations"] != its:
+                        raise RuntimeError(f"{name} {prec} switch {sw} team {team}: {info['iterations']} "
+                                           f"iterations, {its} on the first row")
+                    row = {"precision": prec, "switch_n": sw, "persistent_wgs": team, "iterations": its,
+                           "ms": ms, "us_per_iteration": 1e3 * ms / its,
+                           "coarse_us_per_vcycle": 1e3 * coarse.get("avg_ms", 0.0),
+                           "unknowns_per_s": (n - 2) ** 3 / (ms / 1e3)}
+                    rows.append(row)
+                    if prec not in best or ms < best[prec]["ms"]:
+                        best[prec] = row
+        none = {p: next(r for r in rows if r["precision"] == p and r["switch_n"] == 0) for p in best}
+        out[name] = {"n": n, "levels": levels, "unknowns": (n - 2) ** 3, "rows": rows,
+                     "argmin": {p: {"switch_n": b["switch_n"], "persistent_wgs": b["persistent_wgs"], "ms": b["ms"],
+                                    "unknowns_per_s": b["unknowns_per_s"],
+                                    "speedup_vs_grid_launches": none[p]["ms"] / b["ms"]} for p, b in best.items()}}
+        log(f"[agglomeration] {name}: " + ", ".join(f"{p} best switch {b['switch_n']} team {b['persistent_wgs']} "
+                                                   f"{b['ms']:.2f} ms ({none[p]['ms'] / b['ms']:.2f}x vs none)"
+                                                   for p, b in best.items()))
+        del k, f
+    return out
+
+
+def large_block(rtol, switch_n):
+    """The 1025^3 combined workload (log-normal k, contrast 1e6, 10 levels):
+    MIXED forward T_solve (median of 3), the adjoint, per-kernel figures from a
+    profiled forward solve, the FP64 forward T_solve (median of 2) and the
+    MIXED-vs-FP64 difference.  Inputs are drawn on the GPU."""
+    import torch
+    from paper_1604_07163_amd import gmg
+    w = WORKLOADS["lognormal1025"]
+    n, levels = w["n"], w["levels"]
+    n_unk = (n - 2) ** 3
+    t0 = time.perf_counter()
+    k, kobs, f = make_inputs(w)
+    log(f"[1025] inputs generated in {time.perf_counter() - t0:.1f}s")
+    out = {"workload": f"lognormal1025: {w['desc']}", "n": n, "levels": levels, "unknowns": n_unk,
+           "switch_n": switch_n}
+    s = gmg.Solver(*k, levels=levels, precision="mixed", switch_n=switch_n)
+    out["setup_ms_mixed"] = s.solve(f, rtol=rtol, max_it=2000)[1]["setup_ms"]
+    s.set_coefficients(*kobs)
+    phi_obs, io = s.solve(f, rtol=1e-10, max_it=2000)
+    check_leg(io, 1e-10, "observation solve")
+    del kobs
+    s.set_coefficients(*k)
+    ms_m, im = t_solve(s, f, rtol, reps=3)
+    x_m, _ = s.solve(f, rtol=rtol, max_it=2000)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    _, _, _, _, ia = s.adjoint_gradient(x_m, x_m - phi_obs, rtol=rtol, max_it=2000, want_lambda=False)
+    torch.cuda.synchronize()
+    adj_wall = time.perf_counter() - t1
+    check_leg(ia, rtol, "adjoint solve")
+    with gmg.Profile(s) as pr:
+        s.solve(f, rtol=rtol, max_it=2000)
+    s.close()
+    del s, phi_obs
+    torch.cuda.empty_cache()
+    out["mixed"] = {"T_solve_ms": ms_m, "unknowns_per_s": n_unk / (ms_m / 1e3), "iterations": im["iterations"],
+                    "restarts": im["restarts"], "rel_res_true": im["rel_res_true"],
+                    "adjoint_iterations": ia["iterations"], "adjoint_ms": 1e3 * adj_wall,
+                    "kernels": kernel_table(pr.result, "mixed", n_unk)}
+    log(f"[1025] mixed: {ms_m:.0f} ms per forward solve, {im['iterations']} its; adjoint {1e3 * adj_wall:.0f} ms")
+    s64 = gmg.Solver(*k, levels=levels, precision="fp64", switch_n=switch_n)
+    ms_d, i64 = t_solve(s64, f, rtol, reps=2)
+    x64, _ = s64.solve(f, rtol=rtol, max_it=2000)
+    s64.close()
+    del s64
+    diff = float(torch.linalg.vector_norm(x_m - x64) / torch.linalg.vector_norm(x64))
+    out["fp64"] = {"T_solve_ms": ms_d, "unknowns_per_s": n_unk / (ms_d / 1e3), "iterations": i64["iterations"],
+                   "rel_res_true": i64["rel_res_true"]}
+    out["speedup_mixed_forward"] = ms_d / ms_m
+    out["mixed_vs_fp64_rel_l2"] = diff
+    log(f"[1025] fp64: {ms_d:.0f} ms per forward solve; speedup {ms_d / ms_m:.2f}x; mixed vs fp64 {diff:.2e}")
+    del k, f, x_m, x64
+    torch.cuda.empty_cache()
+    return out
 
 
 def profile_summary(d, top=25):
@@ -362,6 +543,9 @@ def main():
                          "folders and exit (host only)")
     ap.add_argument("--galerkin", type=int, nargs="*", default=[],
                     help="with --sweep: also time Galerkin coarse operators from these first levels")
+    ap.add_argument("--no-agglomeration", action="store_true",
+                    help="skip the 33^3-129^3 switch-level / team sweep of the bench line")
+    ap.add_argument("--no-large", action="store_true", help="skip the 1025^3 block of the bench line")
     ap.add_argument("--post-fused", default="auto", choices=["auto", "0", "1"],
                     help="one-sweep post-smoothing: auto (the library default: one sweep), 0 two sweeps, 1 one sweep")
     args = ap.parse_args()
@@ -403,38 +587,35 @@ def main():
                        post_fused="auto" if args.post_fused == "auto" else args.post_fused == "1")
         # phi_obs: forward solve with the observation coefficients (untimed)
         s.set_coefficients(*kobs)
-        phi_obs, _ = s.solve(f, rtol=1e-10, max_it=2000)
+        phi_obs, io = s.solve(f, rtol=1e-10, max_it=2000)
+        check_leg(io, 1e-10, "observation solve")
         s.set_coefficients(*k)
         steps = args.steps if prec == "mixed" else max(1, (args.steps + 1) // 2)
         run_steps(s, k, f, phi_obs, args.warmup, args.rtol)
         log(f"[{prec}] warmup done; timing {steps} steps")
-        times, fwd, adj, prof, phi = run_steps(s, k, f, phi_obs, steps, args.rtol, profile=True)
+        times, fwd, adj, _, phi = run_steps(s, k, f, phi_obs, steps, args.rtol)
+        tsol, tinfo = t_solve(s, f, args.rtol)
+        _, _, _, prof, _ = run_steps(s, k, f, phi_obs, 1, args.rtol, profile=True)
         legs[prec] = {"ms_per_step": 1e3 * float(np.mean(times)), "ms_min": 1e3 * float(np.min(times)),
-                      "forward": fwd, "adjoint": adj, "kernels": prof}
+                      "forward": fwd, "adjoint": adj, "kernels": prof, "T_solve_ms": tsol}
         results[prec] = phi.clone()
-        log(f"[{prec}] {legs[prec]['ms_per_step']:.1f} ms/step; fwd its {fwd['iterations']} "
-            f"true {fwd['rel_res_true']:.2e}; adj its {adj['iterations']}")
+        legs[prec]["error_vs_oracle"] = error_vs_oracle(phi, args.workload)
+        log(f"[{prec}] {legs[prec]['ms_per_step']:.1f} ms/step; T_solve {tsol:.1f} ms; fwd its {fwd['iterations']} "
+            f"true {fwd['rel_res_true']:.2e}; adj its {adj['iterations']}; vs oracle {legs[prec]['error_vs_oracle']}")
         s.close()
-        del s
+        del s, phi_obs, phi
         torch.cuda.empty_cache()
 
     mixed = legs["mixed"]
     ms = mixed["ms_per_step"]
     value = 2 * n_unk / (ms / 1e3)
-    # dominant finest-level HBM kernel of the mixed step
+    # dominant finest-level HBM kernel of the mixed step (profiled step)
     bpp = BYTES_PER_POINT["mixed"]
     cands = {c: v for c, v in mixed["kernels"].items() if c in bpp}
     dom = max(cands, key=lambda c: cands[c]["total_ms"])
     bytes_per_launch = bpp[dom] * n_unk
     achieved = bytes_per_launch / (cands[dom]["avg_ms"] / 1e3) / 1e9
-    kernels = {}
-    for prec, leg in legs.items():
-        for c, v in leg["kernels"].items():
-            entry = dict(v)
-            if c in BYTES_PER_POINT[prec]:
-                entry["GBs"] = BYTES_PER_POINT[prec][c] * n_unk / (v["avg_ms"] / 1e3) / 1e9
-                entry["frac_peak"] = entry["GBs"] / HBM_PEAK_GBS
-            kernels[f"{prec}:{c}"] = entry
+    kernels = {f"{prec}:{c}": v for prec, leg in legs.items() for c, v in kernel_table(leg["kernels"], prec, n_unk).items()}
 
     out = {
         "metric": "fine-grid unknowns solved/s to 1e-8 rel res (mixed vs FP64) + stencil HBM GB/s",
@@ -456,13 +637,19 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(dom, args.workload),
                      "bytes_per_launch": bytes_per_launch, "avg_ms": cands[dom]["avg_ms"],
                      "copy_GBs": copy_gbs},
+        "T_solve": {"definition": "median of 5 forward solves from x0 = 0, setup excluded (HIP events)",
+                    "mixed_ms": mixed["T_solve_ms"], "mixed_unknowns_per_s": n_unk / (mixed["T_solve_ms"] / 1e3)},
         "forward": {"iterations": mixed["forward"]["iterations"], "rel_res_true": mixed["forward"]["rel_res_true"],
                     "restarts": mixed["forward"]["restarts"], "solve_ms": mixed["forward"]["solve_ms"]},
-        "adjoint": {"iterations": mixed["adjoint"]["iterations"], "solve_ms": mixed["adjoint"]["solve_ms"]},
+        "adjoint": {"iterations": mixed["adjoint"]["iterations"], "solve_ms": mixed["adjoint"]["solve_ms"],
+                    "rel_res_true": mixed["adjoint"]["rel_res_true"]},
+        "error_vs_oracle": {p: legs[p]["error_vs_oracle"] for p in legs},
         "kernels": kernels,
     }
     if "fp64" in legs:
         f64 = legs["fp64"]
+        out["T_solve"].update({"fp64_ms": f64["T_solve_ms"], "fp64_unknowns_per_s": n_unk / (f64["T_solve_ms"] / 1e3),
+                               "speedup_mixed": f64["T_solve_ms"] / mixed["T_solve_ms"]})
         out["fp64"] = {"ms_per_step": f64["ms_per_step"], "value": 2 * n_unk / (f64["ms_per_step"] / 1e3),
                        "forward_iterations": f64["forward"]["iterations"],
                        "forward_solve_ms": f64["forward"]["solve_ms"],
@@ -471,12 +658,20 @@ def main():
                        "speedup_mixed_forward": f64["forward"]["solve_ms"] / mixed["forward"]["solve_ms"]}
         d = torch.linalg.vector_norm(results["mixed"] - results["fp64"]) / torch.linalg.vector_norm(results["fp64"])
         out["fp64"]["mixed_vs_fp64_rel_l2"] = float(d)
+    del results, k, kobs, f
+    torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         its = legs.get("fp64", mixed)["forward"]["iterations"]
         log("timing the CPU oracle sample ...")
         out["cpu_baseline"] = cpu_baseline(w, [_host(a) for a in k_in], _host(f_in), its, iters=args.cpu_iters)
+    del k_in, f_in
+    if not args.no_agglomeration:
+        out["agglomeration"] = agglomeration_sweep(args.rtol)
+        p33 = out["agglomeration"]["poisson33"]["argmin"]["fp64"]
+        out["config1_fp64_unknowns_per_s"] = p33["unknowns_per_s"]
+    if not args.no_large:
+        out["large"] = large_block(args.rtol, args.switch_n)
     print(json.dumps(out), flush=True)
-
 
 if __name__ == "__main__":
     main()

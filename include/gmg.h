@@ -130,7 +130,7 @@ typedef struct {
     int32_t restarts;     /* MIXED: restarts from the true residual */
     double rel_res;       /* recursive ||r|| / ||f|| at exit */
     double rel_res_true;  /* ||f - A x|| / ||f|| at exit, FP64 */
-    double setup_ms;      /* gmg_create / gmg_set_coefficients wall time */
+    double setup_ms;      /* device time of gmg_create / the last gmg_set_coefficients */
     double solve_ms;      /* device time of the solve (HIP events on the stream) */
     int32_t coarse_iterations; /* truncated hierarchy: coarse CG iterations over the solve */
 } gmg_info;
@@ -154,7 +154,14 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
                       void *stream, gmg_handle **out);
 
 /* Replace the coefficients (same N, levels, options); rebuilds every derived
- * level and the coarsest factor without reallocating. */
+ * level and the coarsest factor without reallocating.  Everything, the check
+ * of k and of the coarsest factor included, is enqueued on the handle's
+ * stream and the call returns without waiting (with Galerkin levels it waits
+ * for their Lanczos intervals); k must stay valid until that work has run.
+ * A bad k (<= 0, NaN or Inf on an active link) or a coarsest operator that is
+ * not positive definite makes the next gmg_solve / gmg_adjoint_gradient, and
+ * every one after it until valid coefficients are set, return GMG_ERR_COEFF
+ * before any iteration.  Errors here: GMG_ERR_ARG, GMG_ERR_HIP. */
 gmg_status gmg_set_coefficients(gmg_handle *h, const double *kx, const double *ky, const double *kz);
 
 /* Change the stream used by later calls. */
@@ -187,8 +194,12 @@ gmg_status gmg_adjoint_gradient(gmg_handle *h, const double *phi, const double *
  * the handle's level buffers, so they must not overlap a solve on the same
  * handle.  GMG_ERR_ARG for a null vector or a level out of range. */
 int32_t gmg_level_n(const gmg_handle *h, int32_t level);   /* N_l, or -1 */
-/* y = A_l x (level 0 with use_fp64 = 1 is the outer FP64 operator). */
-gmg_status gmg_apply_operator(gmg_handle *h, int32_t level, int32_t use_fp64, const double *x, double *y);
+/* y = A_l x in the V-cycle precision (Eq. 2 discretized with the 7-point
+ * stencil of Sec. 4.1 on level l; the 27-point R A P on Galerkin levels). */
+gmg_status gmg_apply_operator(gmg_handle *h, int32_t level, const double *x, double *y);
+/* y = A x on level 0 with the FP64 operator of the outer CG (the kernel that
+ * forms q = A p in every iteration), in either precision mode.  x, y: (N,N,N). */
+gmg_status gmg_apply_outer_operator(gmg_handle *h, const double *x, double *y);
 /* x <- Chebyshev-Jacobi smoothing of A_l x = b from x (x0_zero: from 0). */
 gmg_status gmg_debug_smooth(gmg_handle *h, int32_t level, const double *b, double *x, int32_t x0_zero);
 /* b_c = R (b - A_l x) on level+1 (full weighting). */

@@ -69,6 +69,14 @@ struct gmg_handle {
     PcgState *st_out = nullptr;   // pinned host (read-back)
     PcgState *cst = nullptr;      // device: inexact coarse CG (truncated hierarchy)
     PcgState *cst_out = nullptr;  // pinned host
+    // device check of the last coefficients: tt = count of active links that
+    // are not positive and finite, status = 3 if the coarsest operator is not
+    // positive definite (read by gmg_create, and by every solve after
+    // gmg_set_coefficients, which does not wait for it)
+    PcgState *vst = nullptr;
+    PcgState *vst_out = nullptr;  // pinned host
+    hipEvent_t es0 = nullptr, es1 = nullptr;  // around the last gmg_set_coefficients
+    bool setup_pending = false;   // its time is read at the next solve
     void *cp = nullptr, *cq = nullptr;  // coarse CG direction and A p (coarsest level, V type)
     long long coarse_its = 0;     // coarse CG iterations in the current solve
     double *chol = nullptr;       // coarsest factor, device
@@ -307,6 +315,7 @@ struct Prof {
 };
 
 gmg_status finalize(gmg_handle *h, int count, int stage, PcgState *state = nullptr);
+gmg_status coefficient_status(gmg_handle *h, const PcgState &v);
 
 // ------------------------------------------------------------------ smoothing
 // Chebyshev-Jacobi smoothing on a Galerkin level: the recurrence and buffer
@@ -799,7 +808,15 @@ gmg_status solve_core(gmg_handle *h, const double *f, const double *x0, double r
     }
     STCHK(dot64(h, h->F, h->F, gmg::ST_BB, nullptr));
     STCHK(dot64(h, h->R, h->R, gmg::ST_RR0, nullptr));
+    HIPCHK(hipMemcpyAsync(h->vst_out, h->vst, sizeof(PcgState), hipMemcpyDeviceToHost, h->stream));
     STCHK(read_state(h));
+    if (h->setup_pending) {  // the last gmg_set_coefficients has completed by now
+        float sms = 0;
+        HIPCHK(hipEventElapsedTime(&sms, h->es0, h->es1));
+        h->setup_ms = sms;
+        h->setup_pending = false;
+    }
+    STCHK(coefficient_status(h, *h->vst_out));
     const double bb = h->st_out->bb;
     int restarts = 0;
     gmg_status status = GMG_OK;
@@ -868,66 +885,13 @@ gmg_status solve_core(gmg_handle *h, const double *f, const double *x0, double r
 }
 
 // ------------------------------------------------------------------ setup
-// Dense Cholesky (right-looking, outer-product form) of the coarsest operator,
-// assembled from its padded link coefficients.  Host-side, FP64.
+// Dense Cholesky factor of the coarsest operator, on the device (one
+// workgroup); a pivot that is not positive is recorded in h->vst.
 gmg_status factor_coarsest(gmg_handle *h) {
     LevelHost &c = h->lv[h->L - 1];
-    const int n = c.n, nn = n - 2, m = nn * nn * nn;
-    std::vector<double> A((size_t)m * m, 0.0);
-    auto off = [&](int i, int j, int k) { return (long long)k * c.plane + (long long)j * c.pitch + i; };
-    auto unk = [&](int i, int j, int k) { return ((k - 1) * nn + (j - 1)) * nn + (i - 1); };
-    auto in = [&](int i, int j, int k) { return i >= 1 && j >= 1 && k >= 1 && i <= n - 2 && j <= n - 2 && k <= n - 2; };
-    std::vector<double> kx, ky, kz, a27;
-    if (c.g27) {
-        a27.resize(27 * c.nel);
-        HIPCHK(hipMemcpyAsync(a27.data(), c.a64, 27 * c.nel * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-        HIPCHK(hipStreamSynchronize(h->stream));
-        for (int k = 1; k <= n - 2; ++k)
-            for (int j = 1; j <= n - 2; ++j)
-                for (int i = 1; i <= n - 2; ++i)
-                    for (int d = 0; d < 27; ++d) {
-                        const int di = d % 3 - 1, dj = (d / 3) % 3 - 1, dk = d / 9 - 1;
-                        if (in(i + di, j + dj, k + dk))
-                            A[(size_t)unk(i, j, k) * m + unk(i + di, j + dj, k + dk)] = a27[d * c.nel + off(i, j, k)];
-                    }
-    } else {
-        kx.resize(c.nel);
-        ky.resize(c.nel);
-        kz.resize(c.nel);
-        HIPCHK(hipMemcpyAsync(kx.data(), c.kx64, c.nel * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-        HIPCHK(hipMemcpyAsync(ky.data(), c.ky64, c.nel * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-        HIPCHK(hipMemcpyAsync(kz.data(), c.kz64, c.nel * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-        HIPCHK(hipStreamSynchronize(h->stream));
-    }
-    for (int k = 1; k <= n - 2 && !c.g27; ++k)
-        for (int j = 1; j <= n - 2; ++j)
-            for (int i = 1; i <= n - 2; ++i) {
-                const int p = unk(i, j, k);
-                const long long o = off(i, j, k);
-                const double lk[6] = {kx[o - 1], kx[o], ky[o - c.pitch], ky[o], kz[o - c.plane], kz[o]};
-                const int nb[6][3] = {{i - 1, j, k}, {i + 1, j, k}, {i, j - 1, k}, {i, j + 1, k}, {i, j, k - 1}, {i, j, k + 1}};
-                for (int f = 0; f < 6; ++f) {
-                    A[(size_t)p * m + p] += c.s * lk[f];
-                    if (in(nb[f][0], nb[f][1], nb[f][2])) A[(size_t)p * m + unk(nb[f][0], nb[f][1], nb[f][2])] -= c.s * lk[f];
-                }
-            }
-    // right-looking: for each column, scale it, then update the trailing block
-    for (int col = 0; col < m; ++col) {
-        double piv = A[(size_t)col * m + col];
-        if (!(piv > 0.0)) return fail(h, GMG_ERR_COEFF, "coarsest operator is not positive definite");
-        piv = std::sqrt(piv);
-        A[(size_t)col * m + col] = piv;
-        for (int r = col + 1; r < m; ++r) A[(size_t)r * m + col] /= piv;
-        for (int cc = col + 1; cc < m; ++cc) {
-            const double lc = A[(size_t)cc * m + col];
-            if (lc == 0.0) continue;
-            for (int r = cc; r < m; ++r) A[(size_t)r * m + cc] -= A[(size_t)r * m + col] * lc;
-        }
-    }
-    for (int r = 0; r < m; ++r)
-        for (int cc = r + 1; cc < m; ++cc) A[(size_t)r * m + cc] = 0.0;
-    HIPCHK(hipMemcpyAsync(h->chol, A.data(), (size_t)m * m * sizeof(double), hipMemcpyHostToDevice, h->stream));
-    HIPCHK(hipStreamSynchronize(h->stream));
+    gmg::k_chol_factor<<<1, 1024, 0, h->stream>>>(c.n, c.pitch, c.plane, c.kx64, c.ky64, c.kz64,
+                                                  c.g27 ? c.a64 : nullptr, c.nel, c.s, h->m, h->chol, h->vst);
+    LAUNCHCHK();
     return GMG_OK;
 }
 
@@ -1039,17 +1003,19 @@ gmg_status galerkin_lambda(gmg_handle *h, int l, double *lam) {
     return GMG_OK;
 }
 
-gmg_status load_coefficients(gmg_handle *h, const double *kx, const double *ky, const double *kz) {
+// Rebuild every level from k and enqueue the checks into h->vst; no host
+// synchronization unless the hierarchy has Galerkin levels (their Chebyshev
+// intervals come from Lanczos sums added on the host) or `first` (the level
+// table is uploaded once, at creation).
+gmg_status load_coefficients(gmg_handle *h, const double *kx, const double *ky, const double *kz, bool first) {
     LevelHost &l0 = h->lv[0];
-    // level 0 (+ validation)
+    // level 0 (+ the count of bad active links into vst->tt)
+    gmg::k_clear_state<<<1, 64, 0, h->stream>>>(h->vst);
+    LAUNCHCHK();
     gmg::k_faces_in<<<blocks_for((long long)l0.n * l0.n * l0.n, 256), 256, 0, h->stream>>>(
         l0.n, l0.pitch, kx, ky, kz, h->opt.coeff_is_log, l0.kx64, l0.ky64, l0.kz64, h->partial);
     LAUNCHCHK();
-    STCHK(finalize(h, (int)blocks_for((long long)l0.n * l0.n * l0.n, 256), gmg::ST_TT));
-    STCHK(read_state(h));
-    if (h->st_out->tt != 0.0)
-        return fail(h, GMG_ERR_COEFF, std::to_string((long long)h->st_out->tt) +
-                                          " active link coefficients are not positive and finite");
+    STCHK(finalize(h, (int)blocks_for((long long)l0.n * l0.n * l0.n, 256), gmg::ST_TT, h->vst));
     for (int l = 1; l < h->L; ++l) {
         LevelHost &f = h->lv[l - 1], &c = h->lv[l];
         gmg::k_coarsen<<<blocks_for((long long)c.n * c.n * c.n, 256), 256, 0, h->stream>>>(
@@ -1107,7 +1073,19 @@ gmg_status load_coefficients(gmg_handle *h, const double *kx, const double *ky, 
         LAUNCHCHK();
     }
     if (h->opt.coarse_solver == 0) STCHK(factor_coarsest(h));
+    bool galerkin = false;
+    for (int l = 0; l < h->L; ++l) galerkin = galerkin || h->lv[l].g27;
+    if (!first && !galerkin) return GMG_OK;  // the level table and intervals are unchanged
     return mixed(h) ? upload_levels<float, bf16>(h) : upload_levels<double, double>(h);
+}
+
+// The result of the checks enqueued by the last load_coefficients (waits).
+gmg_status coefficient_status(gmg_handle *h, const PcgState &v) {
+    if (v.tt != 0.0)
+        return fail(h, GMG_ERR_COEFF,
+                    std::to_string((long long)v.tt) + " active link coefficients are not positive and finite");
+    if (v.status == 3) return fail(h, GMG_ERR_COEFF, "coarsest operator is not positive definite");
+    return GMG_OK;
 }
 
 gmg_status check_level(gmg_handle *h, int level) {
@@ -1172,6 +1150,9 @@ void gmg_destroy(gmg_handle *h) {
     if (h->st_in) (void)hipHostFree(h->st_in);
     if (h->st_out) (void)hipHostFree(h->st_out);
     if (h->cst_out) (void)hipHostFree(h->cst_out);
+    if (h->vst_out) (void)hipHostFree(h->vst_out);
+    if (h->es0) (void)hipEventDestroy(h->es0);
+    if (h->es1) (void)hipEventDestroy(h->es1);
     if (h->ev0) (void)hipEventDestroy(h->ev0);
     if (h->ev1) (void)hipEventDestroy(h->ev1);
     delete h;
@@ -1215,8 +1196,10 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
     (void)hipEventRecord(t0, h->stream);
     if (hipHostMalloc((void **)&h->st_in, sizeof(PcgState)) != hipSuccess ||
         hipHostMalloc((void **)&h->st_out, sizeof(PcgState)) != hipSuccess ||
-        hipHostMalloc((void **)&h->cst_out, sizeof(PcgState)) != hipSuccess)
+        hipHostMalloc((void **)&h->cst_out, sizeof(PcgState)) != hipSuccess ||
+        hipHostMalloc((void **)&h->vst_out, sizeof(PcgState)) != hipSuccess)
         return bail(GMG_ERR_NOMEM);
+    if (hipEventCreate(&h->es0) != hipSuccess || hipEventCreate(&h->es1) != hipSuccess) return bail(GMG_ERR_HIP);
     const bool mx = o.precision == GMG_MIXED;
     // level geometry
     int n = o.n;
@@ -1292,6 +1275,7 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
     ALLOC(h->partial2, 2LL * gmg::NB_CHUNKS);
     ALLOC(h->st, 1LL);
     ALLOC(h->cst, 1LL);
+    ALLOC(h->vst, 1LL);
     ALLOC(h->bar, 1LL);
     for (int l = 0; l < h->L; ++l) {
         LevelHost &lh = h->lv[l];
@@ -1405,9 +1389,12 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
     // Chebyshev coefficients: the default interval on every level (Galerkin
     // levels get their own in load_coefficients)
     for (int l = 0; l < h->L; ++l) set_cheb(h->lv[l], o.cheb_degree, o.cheb_lo, o.cheb_hi);
-    if ((s = load_coefficients(h, kx, ky, kz)) != GMG_OK) return bail(s);
+    if ((s = load_coefficients(h, kx, ky, kz, true)) != GMG_OK) return bail(s);
     (void)hipEventRecord(t1, h->stream);
-    (void)hipEventSynchronize(t1);
+    if (hipMemcpyAsync(h->vst_out, h->vst, sizeof(PcgState), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess)
+        return bail(GMG_ERR_HIP);
+    if ((s = coefficient_status(h, *h->vst_out)) != GMG_OK) return bail(s);
     float ms = 0;
     (void)hipEventElapsedTime(&ms, t0, t1);
     (void)hipEventDestroy(t0);
@@ -1419,22 +1406,12 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
 
 gmg_status gmg_set_coefficients(gmg_handle *h, const double *kx, const double *ky, const double *kz) {
     if (!h || !kx || !ky || !kz) return GMG_ERR_ARG;
-    hipEvent_t t0, t1;
-    HIPCHK(hipEventCreate(&t0));
-    if (hipEventCreate(&t1) != hipSuccess) {
-        (void)hipEventDestroy(t0);
-        return fail(h, GMG_ERR_HIP, "hipEventCreate failed");
-    }
-    (void)hipEventRecord(t0, h->stream);
-    gmg_status s = load_coefficients(h, kx, ky, kz);
-    (void)hipEventRecord(t1, h->stream);
-    (void)hipEventSynchronize(t1);
-    float ms = 0;
-    (void)hipEventElapsedTime(&ms, t0, t1);
-    (void)hipEventDestroy(t0);
-    (void)hipEventDestroy(t1);
-    h->setup_ms = ms;
-    return s;
+    HIPCHK(hipEventRecord(h->es0, h->stream));
+    const gmg_status s = load_coefficients(h, kx, ky, kz, false);
+    if (s != GMG_OK) return s;
+    HIPCHK(hipEventRecord(h->es1, h->stream));
+    h->setup_pending = true;
+    return GMG_OK;
 }
 
 gmg_status gmg_set_stream(gmg_handle *h, void *stream) {
@@ -1579,20 +1556,22 @@ gmg_status hook_vcycle(gmg_handle *h, const double *r, double *z) {
 
 extern "C" {
 
-gmg_status gmg_apply_operator(gmg_handle *h, int32_t level, int32_t use_fp64, const double *x, double *y) {
+gmg_status gmg_apply_operator(gmg_handle *h, int32_t level, const double *x, double *y) {
     STCHK(check_level(h, level));
     if (!x || !y) return fail(h, GMG_ERR_ARG, "null vector");
-    if (use_fp64) {
-        if (level != 0) return fail(h, GMG_ERR_ARG, "the FP64 outer operator exists on level 0 only");
-        LevelHost &l0 = h->lv[0];
-        double *u = h->X;  // free between solves (every solve re-initializes it)
-        STCHK(in_vec<double>(h, l0, x, u));
-        gmg::k_apply_x2<false, double><<<l0.til2.nblocks, gmg::NT, 0, h->stream>>>(view<double, double>(l0), l0.til2,
-                                                                                  u, h->Q, nullptr, nullptr);
-        LAUNCHCHK();
-        return out_vec<double>(h, l0, h->Q, y);
-    }
     return mixed(h) ? hook_apply<float, bf16>(h, level, x, y) : hook_apply<double, double>(h, level, x, y);
+}
+
+gmg_status gmg_apply_outer_operator(gmg_handle *h, const double *x, double *y) {
+    if (!h) return GMG_ERR_ARG;
+    if (!x || !y) return fail(h, GMG_ERR_ARG, "null vector");
+    LevelHost &l0 = h->lv[0];
+    double *u = h->X;  // free between solves (every solve re-initializes it)
+    STCHK(in_vec<double>(h, l0, x, u));
+    gmg::k_apply_x2<false, double><<<l0.til2.nblocks, gmg::NT, 0, h->stream>>>(view<double, double>(l0), l0.til2, u,
+                                                                              h->Q, nullptr, nullptr);
+    LAUNCHCHK();
+    return out_vec<double>(h, l0, h->Q, y);
 }
 
 gmg_status gmg_debug_smooth(gmg_handle *h, int32_t level, const double *b, double *x, int32_t x0_zero) {

@@ -1801,6 +1801,76 @@ __global__ __launch_bounds__(NT_FIN) void k_finalize(const double *__restrict__ 
     }
 }
 
+// Dense Cholesky factor of the coarsest operator by one workgroup: assemble
+// the m x m matrix (m interior unknowns, natural order) from the level's
+// links (or its 27 Galerkin coefficients), then factor it in place, right-
+// looking: per column, the pivot's square root, the column scaled by it, and
+// the trailing lower triangle updated.  Each entry of the trailing block gets
+// one update per column, so the parallel order rounds like a serial loop.
+// A pivot that is not positive sets st->status = 3 (the operator is not
+// positive definite) and the factor is left unusable.  The strict upper
+// triangle is zeroed.  m <= MAX_COARSE.
+__global__ __launch_bounds__(1024) void k_chol_factor(int n, int pitch, long long plane, const double *__restrict__ kx,
+                                                      const double *__restrict__ ky, const double *__restrict__ kz,
+                                                      const double *__restrict__ a27, long long nel, double s, int m,
+                                                      double *__restrict__ A, PcgState *__restrict__ st) {
+    const int nn = n - 2;
+    const int tid = (int)threadIdx.x, nth = (int)blockDim.x;
+    const long long mm = (long long)m * m;
+    for (long long e = tid; e < mm; e += nth) A[e] = 0.0;
+    __syncthreads();
+    auto unk = [nn](int i, int j, int k) { return ((k - 1) * nn + (j - 1)) * nn + (i - 1); };
+    auto in = [n](int i, int j, int k) { return i >= 1 && j >= 1 && k >= 1 && i <= n - 2 && j <= n - 2 && k <= n - 2; };
+    for (int p = tid; p < m; p += nth) {  // row p is written by one thread only
+        const int i = 1 + p % nn, j = 1 + (p / nn) % nn, k = 1 + p / (nn * nn);
+        const long long o = (long long)k * plane + (long long)j * pitch + i;
+        double *row = A + (long long)p * m;
+        if (a27) {
+            for (int d = 0; d < 27; ++d) {
+                const int di = d % 3 - 1, dj = (d / 3) % 3 - 1, dk = d / 9 - 1;
+                if (in(i + di, j + dj, k + dk)) row[unk(i + di, j + dj, k + dk)] = a27[(long long)d * nel + o];
+            }
+        } else {
+            const double lk[6] = {kx[o - 1], kx[o], ky[o - pitch], ky[o], kz[o - plane], kz[o]};
+            const int nb[6][3] = {{i - 1, j, k}, {i + 1, j, k}, {i, j - 1, k}, {i, j + 1, k}, {i, j, k - 1}, {i, j, k + 1}};
+            for (int f = 0; f < 6; ++f) {
+                row[p] += s * lk[f];
+                if (in(nb[f][0], nb[f][1], nb[f][2])) row[unk(nb[f][0], nb[f][1], nb[f][2])] -= s * lk[f];
+            }
+        }
+    }
+    __syncthreads();
+    __shared__ int bad;
+    if (tid == 0) bad = 0;
+    for (int col = 0; col < m; ++col) {
+        if (tid == 0) {
+            const double piv = A[(long long)col * m + col];
+            if (!(piv > 0.0)) bad = 1;
+            A[(long long)col * m + col] = bad ? 1.0 : sqrt(piv);
+        }
+        __syncthreads();
+        const double piv = A[(long long)col * m + col];
+        for (int r = col + 1 + tid; r < m; r += nth) A[(long long)r * m + col] /= piv;
+        __syncthreads();
+        const int cnt = m - col - 1;
+        for (long long e = tid; e < (long long)cnt * cnt; e += nth) {
+            const int r = col + 1 + (int)(e / cnt), cc = col + 1 + (int)(e % cnt);
+            if (cc <= r)
+                A[(long long)r * m + cc] = A[(long long)r * m + cc] - A[(long long)r * m + col] * A[(long long)cc * m + col];
+        }
+        __syncthreads();
+    }
+    for (long long e = tid; e < mm; e += nth)
+        if (e % m > e / m) A[e] = 0.0;
+    if (tid == 0 && bad) st->status = 3;
+}
+
+// zero a state record (a kernel, not a memset, so the clearing is an ordinary
+// launch on the stream)
+__global__ void k_clear_state(PcgState *st) {
+    if (threadIdx.x == 0) *st = PcgState{};
+}
+
 // clear the restart flag after a p-update has consumed it
 __global__ void k_clear_restart(PcgState *st) {
     if (threadIdx.x == 0 && !st->done) st->restart = 0;

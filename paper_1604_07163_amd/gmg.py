@@ -86,8 +86,10 @@ def lib():
     L.gmg_adjoint_gradient.restype = st
     L.gmg_level_n.argtypes = [P, I32]
     L.gmg_level_n.restype = I32
-    L.gmg_apply_operator.argtypes = [P, I32, I32, P, P]
+    L.gmg_apply_operator.argtypes = [P, I32, P, P]
     L.gmg_apply_operator.restype = st
+    L.gmg_apply_outer_operator.argtypes = [P, P, P]
+    L.gmg_apply_outer_operator.restype = st
     L.gmg_debug_smooth.argtypes = [P, I32, P, P, I32]
     L.gmg_debug_smooth.restype = st
     L.gmg_debug_residual_restrict.argtypes = [P, I32, P, P, P]
@@ -236,6 +238,8 @@ class Solver:
         return lib().gmg_level_n(self._h, level)
 
     def set_coefficients(self, kx, ky, kz):
+        """Rebuild the hierarchy from new coefficients (enqueued on the stream;
+        a bad k is reported by the next solve as GMG_ERR_COEFF)."""
         self._check_faces(kx, ky, kz)
         self._sync_stream()
         s = lib().gmg_set_coefficients(self._h, _dev(kx, "kx"), _dev(ky, "ky"), _dev(kz, "kz"))
@@ -274,10 +278,18 @@ class Solver:
 
     # ------------------------------------------------------------------ test hooks
     def apply_operator(self, level, x, use_fp64=False):
+        """y = A_l x in the V-cycle precision; use_fp64 (level 0 only): the
+        outer FP64 operator of the CG iteration."""
         self._sync_stream()
         y = self._empty(self.level_n(level))
-        s = lib().gmg_apply_operator(self._h, level, 1 if use_fp64 else 0, self._vec(x, "x", level),
-                                     _dev(y, "y"))
+        if use_fp64:
+            if level != 0:
+                raise ValueError("the outer FP64 operator exists on level 0 only")
+            s = lib().gmg_apply_outer_operator(self._h, self._vec(x, "x"), _dev(y, "y"))
+            if s != OK:
+                self._err(s, "gmg_apply_outer_operator")
+            return y
+        s = lib().gmg_apply_operator(self._h, level, self._vec(x, "x", level), _dev(y, "y"))
         if s != OK:
             self._err(s, "gmg_apply_operator")
         return y

@@ -77,8 +77,10 @@ def test_level_operations_fp64(n, levels):
         assert rel_max(to_np(s.prolong(l, to_gpu(e), to_gpu(x0))), oracle.prolong_add(e, x0)) <= 1e-15
 
 
-@pytest.mark.parametrize("n,levels", [(17, 3), (33, 4), (81, 4), (161, 5)])
+@pytest.mark.parametrize("n,levels", [(17, 3), (33, 4), (81, 4), (161, 5), (33, 2)])
 def test_coarsest_cholesky(n, levels):
+    """The coarsest solve by the device-built Cholesky factor against the
+    oracle's dense solve; (33, 2) has a 17^3 coarsest level, 3375 unknowns."""
     k, s, H = make(n, levels)
     nc = H.level_n(levels - 1)
     b = rand_vec(nc, 5)
@@ -140,6 +142,27 @@ def test_mixed_level_operations(n, levels):
         assert rel_max(to_np(s.smooth(l, to_gpu(b), to_gpu(x0))), ref) <= 2e-6
         ref = oracle.restrict(b - oracle.apply(*kl, x0))
         assert rel_max(to_np(s.residual_restrict(l, to_gpu(b), to_gpu(x0))), ref) <= 2e-6
+
+
+def test_bad_coefficients_after_set_are_reported_by_the_next_solve():
+    """gmg_set_coefficients enqueues its checks without waiting; the next solve
+    (and every one after it) returns GMG_ERR_COEFF until valid coefficients
+    are set again."""
+    n = 17
+    k = inputs.const_k(n)
+    kg = [to_gpu(a) for a in k]
+    f = to_gpu(inputs.uniform_rhs(n, 1))
+    s = gmg.Solver(*kg, levels=3)
+    bad = kg[1].clone()
+    bad[5, 3, 7] = 0.0
+    s.set_coefficients(kg[0], bad, kg[2])  # returns: nothing checked yet on the host
+    for _ in range(2):
+        with pytest.raises(gmg.GmgError) as e:
+            s.solve(f)
+        assert e.value.status == 3
+    s.set_coefficients(*kg)
+    x, info = s.solve(f, rtol=1e-10)
+    assert info["status"] == "GMG_OK" and info["rel_res_true"] <= 1e-10
 
 
 def test_errors_are_reported():

@@ -186,6 +186,27 @@ gmg_status gmg_adjoint_gradient(gmg_handle *h, const double *phi, const double *
                                 double *g_y, double *g_z, double *lambda, double rtol, int32_t max_it,
                                 gmg_info *info);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the solve
+ * of gmg_create + gmg_solve + gmg_destroy in one call that allocates nothing.
+ * The hierarchy is built in a static device workspace of 64 MiB that each GPU
+ * the library runs on holds until the process ends (enough for N <= 65 in
+ * either precision at any level count); the handle and its host state
+ * records are static too, and no event, pinned buffer or heap object is
+ * created.  Options as gmg_create except galerkin, which must be 0.  k, f, x,
+ * x0 (may be NULL), rtol, max_it, info as gmg_create / gmg_solve; stream as
+ * gmg_create.  Results equal those of gmg_solve with the same options.
+ * The workspace keeps the last call's contents and every call clears what it
+ * uses; calls that overlap on one GPU (other threads, other streams) race.
+ * Errors: GMG_ERR_ARG (null pointer, option out of range, galerkin != 0),
+ * GMG_ERR_DIMS (also: the hierarchy does not fit the workspace),
+ * GMG_ERR_COEFF, GMG_ERR_HIP, and the solve statuses of gmg_solve;
+ * gmg_last_error(NULL) gives the message of the last call on the current
+ * device.  Timings in info are host-clock figures. */
+gmg_status gmg_solve_static(const gmg_options *opt, const double *kx, const double *ky, const double *kz,
+                            const double *f, double *x, const double *x0, double rtol, int32_t max_it, void *stream,
+                            gmg_info *info);
+
 /* ---- test hooks: each runs one step of the V-cycle of Sec. 2.1.1 (Alg. 1:
  * smoothing, residual restriction, prolongation and correction, coarse solve)
  * on level `level`, in the handle's V-cycle precision (FP32/BF16 in MIXED
@@ -271,6 +292,8 @@ gmg_status gmg_calibration_copy(void *dst, const void *src, uint64_t bytes, void
 
 void gmg_destroy(gmg_handle *h);
 const char *gmg_status_string(gmg_status s);
+/* The message of the handle's last error; with h = NULL, that of the last
+ * gmg_solve_static call on the current device. */
 const char *gmg_last_error(const gmg_handle *h);
 
 #ifdef __cplusplus

@@ -8,7 +8,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -91,8 +93,12 @@ struct gmg_handle {
     size_t lds_bytes = 0;         // its dynamic LDS size
     gmg::GridBar *bar = nullptr;  // device barrier of the persistent team
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    std::vector<void *> allocs;
-    std::string err;
+    std::vector<void *> allocs;   // device buffers to free (none for a static-workspace handle)
+    char err[256] = "";           // last error message (fixed storage: setting it allocates nothing)
+    // static workspace (gmg_solve_static): buffers are carved from `arena`
+    // instead of allocated, and no event, pinned buffer or heap object is made
+    char *arena = nullptr;
+    size_t arena_cap = 0, arena_used = 0;
     double setup_ms = 0;
     // kernel timing: event pairs per kernel class
     bool prof_on = false;
@@ -102,8 +108,23 @@ struct gmg_handle {
 
 namespace {
 
-gmg_status fail(gmg_handle *h, gmg_status s, const std::string &msg) {
-    if (h) h->err = msg;
+// The static workspace of gmg_solve_static (see there).
+constexpr size_t kStaticBytes = 64ull << 20;  // holds the hierarchy of a 65^3 grid in either precision
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+void *g_scratch[kMaxDevices];  // address of `scratch` on each device
+gmg_handle g_static_handle[kMaxDevices];
+PcgState g_static_state[kMaxDevices][4];  // st_in, st_out, cst_out, vst_out (pageable host memory)
+int g_static_last_device = 0;
+
+gmg_status fail(gmg_handle *h, gmg_status s, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+gmg_status fail(gmg_handle *h, gmg_status s, const char *fmt, ...) {
+    if (h) {
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(h->err, sizeof(h->err), fmt, ap);
+        va_end(ap);
+    }
     return s;
 }
 
@@ -111,13 +132,13 @@ gmg_status fail(gmg_handle *h, gmg_status s, const std::string &msg) {
     do {                                                                                       \
         hipError_t e_ = (call);                                                                \
         if (e_ != hipSuccess)                                                                  \
-            return fail(h, GMG_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));    \
+            return fail(h, GMG_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_));                  \
     } while (0)
 #define LAUNCHCHK()                                                                            \
     do {                                                                                       \
         hipError_t e_ = hipGetLastError();                                                     \
         if (e_ != hipSuccess)                                                                  \
-            return fail(h, GMG_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e_)); \
+            return fail(h, GMG_ERR_HIP, "kernel launch: %s", hipGetErrorString(e_));              \
     } while (0)
 #define STCHK(expr)                   \
     do {                              \
@@ -201,16 +222,28 @@ gmg::Rows make_rows(int n, int pitch, long long plane) {
     return r;
 }
 
+// A zero-filled device buffer of `count` elements: hipMalloc'd (freed by
+// gmg_destroy), or, for a static-workspace handle, the next 256-byte aligned
+// piece of the arena (zeroed in one pass once every piece is assigned).
 template <typename T>
 gmg_status dalloc(gmg_handle *h, T **p, long long count) {
+    const size_t bytes = (size_t)count * sizeof(T);
+    if (h->arena) {
+        const size_t off = (h->arena_used + 255) & ~(size_t)255;
+        if (off + bytes > h->arena_cap)
+            return fail(h, GMG_ERR_DIMS, "the hierarchy needs more than the %zu-byte static workspace", h->arena_cap);
+        *p = (T *)(h->arena + off);
+        h->arena_used = off + bytes;
+        return GMG_OK;
+    }
     void *q = nullptr;
-    hipError_t e = hipMalloc(&q, (size_t)count * sizeof(T));
+    hipError_t e = hipMalloc(&q, bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
-        return fail(h, GMG_ERR_NOMEM, "hipMalloc of " + std::to_string((size_t)count * sizeof(T)) + " bytes failed");
+        return fail(h, GMG_ERR_NOMEM, "hipMalloc of %zu bytes failed", bytes);
     }
     h->allocs.push_back(q);
-    e = hipMemsetAsync(q, 0, (size_t)count * sizeof(T), h->stream);
+    e = hipMemsetAsync(q, 0, bytes, h->stream);
     if (e != hipSuccess) return fail(h, GMG_ERR_HIP, "hipMemsetAsync failed");
     *p = (T *)q;
     return GMG_OK;
@@ -780,13 +813,24 @@ gmg_status pcg_loop(gmg_handle *h) {
 }
 
 // Solve A X = F with the result left in h->X (padded).  f, x0: caller arrays.
+// zero `bytes` (a multiple of 16) of device memory with a kernel launch
+gmg_status zero_dev(gmg_handle *h, void *p, size_t bytes) {
+    const long long n16 = (long long)(bytes / 16);
+    gmg::k_fill_zero<<<(unsigned)std::min<long long>(std::max<long long>((n16 + 255) / 256, 1), 65535), 256, 0,
+                       h->stream>>>(n16, (uint4 *)p);
+    LAUNCHCHK();
+    return GMG_OK;
+}
+
 gmg_status solve_core(gmg_handle *h, const double *f, const double *x0, double rtol, int max_it, gmg_info *info) {
     LevelHost &l0 = h->lv[0];
     const long long nv = (long long)l0.n * l0.n * l0.n;
     h->coarse_its = 0;
     if (h->persist && h->opt.persistent_wgs > 1)  // a clean team barrier for this solve
-        HIPCHK(hipMemsetAsync(h->bar, 0, sizeof(gmg::GridBar), h->stream));
-    HIPCHK(hipEventRecord(h->ev0, h->stream));
+        STCHK(zero_dev(h, h->bar, sizeof(gmg::GridBar)));
+    // solve time: HIP events, or the host clock for a static-workspace handle (no events)
+    const auto host0 = std::chrono::steady_clock::now();
+    if (h->ev0) HIPCHK(hipEventRecord(h->ev0, h->stream));
     gmg::k_to_padded<double><<<blocks_for(nv, 256), 256, 0, h->stream>>>(l0.n, l0.pitch, f, h->F);
     LAUNCHCHK();
     PcgState s0{};
@@ -803,7 +847,7 @@ gmg_status solve_core(gmg_handle *h, const double *f, const double *x0, double r
                                                                                      nullptr);
         LAUNCHCHK();
     } else {
-        HIPCHK(hipMemsetAsync(h->X, 0, l0.nel * sizeof(double), h->stream));
+        STCHK(zero_dev(h, h->X, l0.nel * sizeof(double)));
         HIPCHK(hipMemcpyAsync(h->R, h->F, l0.nel * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
     }
     STCHK(dot64(h, h->F, h->F, gmg::ST_BB, nullptr));
@@ -822,7 +866,7 @@ gmg_status solve_core(gmg_handle *h, const double *f, const double *x0, double r
     gmg_status status = GMG_OK;
     if (!(bb == bb) || bb > 1.7e308) return fail(h, GMG_ERR_ARG, "right-hand side is not finite");
     if (bb == 0.0) {  // f = 0: x = 0
-        HIPCHK(hipMemsetAsync(h->X, 0, l0.nel * sizeof(double), h->stream));
+        STCHK(zero_dev(h, h->X, l0.nel * sizeof(double)));
         h->st_out->rr = h->st_out->tt = 0;
         h->st_out->its = 0;
     } else {
@@ -860,10 +904,15 @@ gmg_status solve_core(gmg_handle *h, const double *f, const double *x0, double r
         if (status == GMG_OK && !(h->st_out->tt <= h->st_out->rtol2 * h->st_out->bb) && mixed(h))
             status = GMG_ERR_NOT_CONVERGED;
     }
-    HIPCHK(hipEventRecord(h->ev1, h->stream));
-    HIPCHK(hipEventSynchronize(h->ev1));
     float ms = 0;
-    HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+    if (h->ev1) {
+        HIPCHK(hipEventRecord(h->ev1, h->stream));
+        HIPCHK(hipEventSynchronize(h->ev1));
+        HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+    } else {
+        HIPCHK(hipStreamSynchronize(h->stream));
+        ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - host0).count();
+    }
     if (h->persist && h->opt.persistent_wgs > 1) {
         gmg::GridBar gb{};
         HIPCHK(hipMemcpy(&gb, h->bar, sizeof(gb), hipMemcpyDeviceToHost));
@@ -879,8 +928,8 @@ gmg_status solve_core(gmg_handle *h, const double *f, const double *x0, double r
         info->solve_ms = ms;
         info->coarse_iterations = (int32_t)h->coarse_its;
     }
-    if (status == GMG_ERR_BREAKDOWN) h->err = "breakdown: p.Ap <= 0 or non-finite residual";
-    if (status == GMG_ERR_NOT_CONVERGED) h->err = "not converged within max_it";
+    if (status == GMG_ERR_BREAKDOWN) fail(h, status, "breakdown: p.Ap <= 0 or non-finite residual");
+    if (status == GMG_ERR_NOT_CONVERGED) fail(h, status, "not converged within max_it");
     return status;
 }
 
@@ -897,7 +946,7 @@ gmg_status factor_coarsest(gmg_handle *h) {
 
 template <typename V, typename K>
 gmg_status upload_levels(gmg_handle *h) {
-    std::vector<LevBuf<V, K>> lb(h->L);
+    LevBuf<V, K> lb[gmg::MAX_LEVELS];
     for (int l = 0; l < h->L; ++l) {
         lb[l].L = view<V, K>(h->lv[l]);
         lb[l].b = (V *)h->lv[l].b;
@@ -905,10 +954,10 @@ gmg_status upload_levels(gmg_handle *h) {
         lb[l].t1 = (V *)h->lv[l].t1;
         lb[l].t2 = nullptr;
     }
-    HIPCHK(hipMemcpyAsync(h->dev_levels, lb.data(), sizeof(LevBuf<V, K>) * h->L, hipMemcpyHostToDevice, h->stream));
-    std::vector<ChebCoef<V>> cc(h->L);
+    HIPCHK(hipMemcpyAsync(h->dev_levels, lb, sizeof(LevBuf<V, K>) * h->L, hipMemcpyHostToDevice, h->stream));
+    ChebCoef<V> cc[gmg::MAX_LEVELS];
     for (int l = 0; l < h->L; ++l) cc[l] = cheb<V>(h, l);
-    HIPCHK(hipMemcpyAsync(h->dev_cheb, cc.data(), sizeof(ChebCoef<V>) * h->L, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(h->dev_cheb, cc, sizeof(ChebCoef<V>) * h->L, hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     return GMG_OK;
 }
@@ -1082,10 +1131,22 @@ gmg_status load_coefficients(gmg_handle *h, const double *kx, const double *ky, 
 // The result of the checks enqueued by the last load_coefficients (waits).
 gmg_status coefficient_status(gmg_handle *h, const PcgState &v) {
     if (v.tt != 0.0)
-        return fail(h, GMG_ERR_COEFF,
-                    std::to_string((long long)v.tt) + " active link coefficients are not positive and finite");
+        return fail(h, GMG_ERR_COEFF, "%lld active link coefficients are not positive and finite", (long long)v.tt);
     if (v.status == 3) return fail(h, GMG_ERR_COEFF, "coarsest operator is not positive definite");
     return GMG_OK;
+}
+
+// A solve with its result copied out to x (natural layout); waits for the stream.
+gmg_status solve_out(gmg_handle *h, const double *f, double *x, const double *x0, double rtol, int32_t max_it,
+                     gmg_info *info) {
+    const gmg_status st = solve_core(h, f, x0, rtol, max_it, info);
+    if (st != GMG_OK && st != GMG_ERR_NOT_CONVERGED && st != GMG_ERR_BREAKDOWN) return st;
+    LevelHost &l0 = h->lv[0];
+    gmg::k_to_natural<double><<<blocks_for((long long)l0.n * l0.n * l0.n, 256), 256, 0, h->stream>>>(l0.n, l0.pitch,
+                                                                                                     h->X, x);
+    LAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return st;
 }
 
 gmg_status check_level(gmg_handle *h, int level) {
@@ -1139,7 +1200,7 @@ const char *gmg_status_string(gmg_status s) {
     return "GMG_ERR_UNKNOWN";
 }
 
-const char *gmg_last_error(const gmg_handle *h) { return h ? h->err.c_str() : "null handle"; }
+const char *gmg_last_error(const gmg_handle *h) { return h ? h->err : g_static_handle[g_static_last_device].err; }
 
 void gmg_destroy(gmg_handle *h) {
     if (!h) return;
@@ -1158,12 +1219,12 @@ void gmg_destroy(gmg_handle *h) {
     delete h;
 }
 
-gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky, const double *kz, void *stream,
-                      gmg_handle **out) {
-    if (!out) return GMG_ERR_ARG;
-    *out = nullptr;
-    if (!opt || !kx || !ky || !kz) return GMG_ERR_ARG;
-    const gmg_options o = *opt;
+}  // extern "C"
+
+namespace {
+
+// The option checks of gmg_create (GMG_ERR_ARG / GMG_ERR_DIMS).
+gmg_status check_options(const gmg_options &o) {
     if (o.n < 3 || o.levels < 1 || o.levels > gmg::MAX_LEVELS) return GMG_ERR_DIMS;
     if (o.cheb_degree < 1 || o.cheb_degree > gmg::MAX_DEGREE || !(o.cheb_lo > 0.0) || !(o.cheb_hi > o.cheb_lo) ||
         (o.precision != GMG_FP64 && o.precision != GMG_MIXED) ||
@@ -1179,27 +1240,38 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
     if (nc < 3 || (o.coarse_solver == 0 && (long long)(nc - 2) * (nc - 2) * (nc - 2) > gmg::MAX_COARSE))
         return GMG_ERR_DIMS;
 
-    gmg_handle *h = new gmg_handle();
-    h->opt = o;
-    h->stream = (hipStream_t)stream;
+    return GMG_OK;
+}
+
+struct EventPair {  // setup-timing events, destroyed on every exit of build()
+    hipEvent_t a = nullptr, b = nullptr;
+    ~EventPair() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+// Everything gmg_create does after the option check, on a fresh handle whose
+// opt and stream are set (and, for the static workspace, arena and host
+// state records).  On failure the caller releases what the handle holds.
+gmg_status build(gmg_handle *h, const double *kx, const double *ky, const double *kz) {
+    const gmg_options o = h->opt;
+    const bool arena = h->arena != nullptr;
     h->L = o.levels;
-    hipEvent_t t0 = nullptr, t1 = nullptr;  // setup timing
-    auto bail = [&](gmg_status s) {
-        if (t0) (void)hipEventDestroy(t0);
-        if (t1) (void)hipEventDestroy(t1);
-        gmg_destroy(h);
-        return s;
-    };
-    if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess ||
-        hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess)
-        return bail(GMG_ERR_HIP);
-    (void)hipEventRecord(t0, h->stream);
-    if (hipHostMalloc((void **)&h->st_in, sizeof(PcgState)) != hipSuccess ||
-        hipHostMalloc((void **)&h->st_out, sizeof(PcgState)) != hipSuccess ||
-        hipHostMalloc((void **)&h->cst_out, sizeof(PcgState)) != hipSuccess ||
-        hipHostMalloc((void **)&h->vst_out, sizeof(PcgState)) != hipSuccess)
-        return bail(GMG_ERR_NOMEM);
-    if (hipEventCreate(&h->es0) != hipSuccess || hipEventCreate(&h->es1) != hipSuccess) return bail(GMG_ERR_HIP);
+    EventPair tm;  // setup timing (host clock for the static workspace, which creates no events)
+    const auto host0 = std::chrono::steady_clock::now();
+    if (!arena) {
+        if (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess ||
+            hipEventCreate(&tm.a) != hipSuccess || hipEventCreate(&tm.b) != hipSuccess ||
+            hipEventCreate(&h->es0) != hipSuccess || hipEventCreate(&h->es1) != hipSuccess)
+            return fail(h, GMG_ERR_HIP, "hipEventCreate failed");
+        (void)hipEventRecord(tm.a, h->stream);
+        if (hipHostMalloc((void **)&h->st_in, sizeof(PcgState)) != hipSuccess ||
+            hipHostMalloc((void **)&h->st_out, sizeof(PcgState)) != hipSuccess ||
+            hipHostMalloc((void **)&h->cst_out, sizeof(PcgState)) != hipSuccess ||
+            hipHostMalloc((void **)&h->vst_out, sizeof(PcgState)) != hipSuccess)
+            return fail(h, GMG_ERR_NOMEM, "hipHostMalloc failed");
+    }
     const bool mx = o.precision == GMG_MIXED;
     // level geometry
     int n = o.n;
@@ -1252,7 +1324,7 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
     LevelHost &l0 = h->lv[0];
 #define ALLOC(ptr, cnt)                                   \
     do {                                                  \
-        if ((s = dalloc(h, &(ptr), (cnt))) != GMG_OK) return bail(s); \
+        if ((s = dalloc(h, &(ptr), (cnt))) != GMG_OK) return s;        \
     } while (0)
     ALLOC(h->F, l0.nel);
     ALLOC(h->X, l0.nel);
@@ -1348,6 +1420,12 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
         h->dev_levels = dl;
     }
 #undef ALLOC
+    if (arena) {  // the workspace keeps the previous call's contents: clear the part in use
+        const long long n16 = (long long)((h->arena_used + 15) / 16);
+        gmg::k_fill_zero<<<(unsigned)std::min<long long>((n16 + 255) / 256, 65535), 256, 0, h->stream>>>(
+            n16, (uint4 *)h->arena);
+        LAUNCHCHK();
+    }
     // persistent team placement: 8 = one workgroup in eight launched, so the
     // active ones share an XCD; 1 if the packed launch would not fit
     if (h->persist && o.persistent_wgs > 1) {
@@ -1355,7 +1433,7 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev);
         (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-        if (!coop) return (h->err = "cooperative launch unsupported", bail(GMG_ERR_HIP));
+        if (!coop) return fail(h, GMG_ERR_HIP, "cooperative launch unsupported");
         if (mx)
             (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gmg::k_persistent<float, bf16>, gmg::NT_PERSIST, 0);
         else
@@ -1363,7 +1441,7 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
                                                                gmg::NT_PERSIST, 0);
         const long long cap = (long long)occ * ncu;
         h->persist_spread = (8LL * o.persistent_wgs <= cap) ? 8 : 1;
-        if ((long long)o.persistent_wgs > cap) return (h->err = "persistent team cannot be co-resident", bail(GMG_ERR_ARG));
+        if ((long long)o.persistent_wgs > cap) return fail(h, GMG_ERR_ARG, "persistent team cannot be co-resident");
     }
     // one-workgroup persistent levels in LDS when they all fit (link levels only)
     if (h->persist && o.persistent_wgs == 1 && o.persistent_lds) {
@@ -1389,20 +1467,43 @@ gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky
     // Chebyshev coefficients: the default interval on every level (Galerkin
     // levels get their own in load_coefficients)
     for (int l = 0; l < h->L; ++l) set_cheb(h->lv[l], o.cheb_degree, o.cheb_lo, o.cheb_hi);
-    if ((s = load_coefficients(h, kx, ky, kz, true)) != GMG_OK) return bail(s);
-    (void)hipEventRecord(t1, h->stream);
-    if (hipMemcpyAsync(h->vst_out, h->vst, sizeof(PcgState), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
-        hipStreamSynchronize(h->stream) != hipSuccess)
-        return bail(GMG_ERR_HIP);
-    if ((s = coefficient_status(h, *h->vst_out)) != GMG_OK) return bail(s);
+    if ((s = load_coefficients(h, kx, ky, kz, true)) != GMG_OK) return s;
+    if (tm.b) (void)hipEventRecord(tm.b, h->stream);
+    HIPCHK(hipMemcpyAsync(h->vst_out, h->vst, sizeof(PcgState), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    STCHK(coefficient_status(h, *h->vst_out));
     float ms = 0;
-    (void)hipEventElapsedTime(&ms, t0, t1);
-    (void)hipEventDestroy(t0);
-    (void)hipEventDestroy(t1);
+    if (tm.a)
+        (void)hipEventElapsedTime(&ms, tm.a, tm.b);
+    else
+        ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - host0).count();
     h->setup_ms = ms;
+    return GMG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gmg_status gmg_create(const gmg_options *opt, const double *kx, const double *ky, const double *kz, void *stream,
+                      gmg_handle **out) {
+    if (!out) return GMG_ERR_ARG;
+    *out = nullptr;
+    if (!opt || !kx || !ky || !kz) return GMG_ERR_ARG;
+    const gmg_status c = check_options(*opt);
+    if (c != GMG_OK) return c;
+    gmg_handle *h = new gmg_handle();
+    h->opt = *opt;
+    h->stream = (hipStream_t)stream;
+    const gmg_status s = build(h, kx, ky, kz);
+    if (s != GMG_OK) {
+        gmg_destroy(h);
+        return s;
+    }
     *out = h;
     return GMG_OK;
 }
+
 
 gmg_status gmg_set_coefficients(gmg_handle *h, const double *kx, const double *ky, const double *kz) {
     if (!h || !kx || !ky || !kz) return GMG_ERR_ARG;
@@ -1425,14 +1526,7 @@ gmg_status gmg_solve(gmg_handle *h, const double *f, double *x, const double *x0
                      gmg_info *info) {
     if (!h || !f || !x) return h ? fail(h, GMG_ERR_ARG, "null vector") : GMG_ERR_ARG;
     if (!(rtol >= 0.0) || max_it < 1) return fail(h, GMG_ERR_ARG, "rtol must be >= 0 and max_it >= 1");
-    gmg_status st = solve_core(h, f, x0, rtol, max_it, info);
-    if (st != GMG_OK && st != GMG_ERR_NOT_CONVERGED && st != GMG_ERR_BREAKDOWN) return st;
-    LevelHost &l0 = h->lv[0];
-    gmg::k_to_natural<double><<<blocks_for((long long)l0.n * l0.n * l0.n, 256), 256, 0, h->stream>>>(l0.n, l0.pitch,
-                                                                                                     h->X, x);
-    LAUNCHCHK();
-    HIPCHK(hipStreamSynchronize(h->stream));
-    return st;
+    return solve_out(h, f, x, x0, rtol, max_it, info);
 }
 
 gmg_status gmg_adjoint_gradient(gmg_handle *h, const double *phi, const double *dl_dphi, double *g_x, double *g_y,
@@ -1455,6 +1549,46 @@ gmg_status gmg_adjoint_gradient(gmg_handle *h, const double *phi, const double *
     }
     HIPCHK(hipStreamSynchronize(h->stream));
     return st;
+}
+
+// ------------------------------------------------------------------ static workspace
+// gmg_solve_static: the solve of gmg_create + gmg_solve with no allocation.
+// Every device buffer of the hierarchy comes from `scratch` (one copy per
+// GPU, held until the process ends; its address on each device is taken once
+// with hipGetSymbolAddress, and only that address is handed to kernels), the
+// handle and its host state records are static, and no event, pinned buffer
+// or heap object is created.  Calls on one GPU share all of it: calls that
+// overlap on one GPU race.
+gmg_status gmg_solve_static(const gmg_options *opt, const double *kx, const double *ky, const double *kz,
+                            const double *f, double *x, const double *x0, double rtol, int32_t max_it, void *stream,
+                            gmg_info *info) {
+    if (!opt || !kx || !ky || !kz || !f || !x || !(rtol >= 0.0) || max_it < 1) return GMG_ERR_ARG;
+    gmg_status s = check_options(*opt);
+    if (s != GMG_OK) return s;
+    if (opt->galerkin != 0) return GMG_ERR_ARG;  // Galerkin intervals need host work buffers
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return GMG_ERR_HIP;
+    g_static_last_device = dev;
+    gmg_handle *h = &g_static_handle[dev];
+    *h = gmg_handle{};
+    if (!g_scratch[dev]) {  // once per device, with the device current
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(h, GMG_ERR_HIP, "hipGetSymbolAddress of the static workspace failed");
+        }
+        g_scratch[dev] = p;
+    }
+    h->opt = *opt;
+    h->stream = (hipStream_t)stream;
+    h->arena = (char *)g_scratch[dev];
+    h->arena_cap = kStaticBytes;
+    h->st_in = &g_static_state[dev][0];
+    h->st_out = &g_static_state[dev][1];
+    h->cst_out = &g_static_state[dev][2];
+    h->vst_out = &g_static_state[dev][3];
+    if ((s = build(h, kx, ky, kz)) != GMG_OK) return s;
+    return solve_out(h, f, x, x0, rtol, max_it, info);
 }
 
 int32_t gmg_level_n(const gmg_handle *h, int32_t level) {

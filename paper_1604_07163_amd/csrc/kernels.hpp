@@ -1865,6 +1865,13 @@ __global__ __launch_bounds__(1024) void k_chol_factor(int n, int pitch, long lon
     if (tid == 0 && bad) st->status = 3;
 }
 
+// zero n16 16-byte units (a kernel rather than a memset node: the solve path
+// clears its buffers with ordinary launches)
+__global__ __launch_bounds__(256) void k_fill_zero(long long n16, uint4 *__restrict__ p) {
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n16; e += (long long)gridDim.x * blockDim.x)
+        p[e] = make_uint4(0u, 0u, 0u, 0u);
+}
+
 // zero a state record (a kernel, not a memset, so the clearing is an ordinary
 // launch on the stream)
 __global__ void k_clear_state(PcgState *st) {

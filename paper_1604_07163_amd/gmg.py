@@ -118,6 +118,8 @@ def lib():
     L.gmg_kernel_class_name.restype = ctypes.c_char_p
     L.gmg_calibration_copy.argtypes = [P, P, ctypes.c_uint64, P]
     L.gmg_calibration_copy.restype = st
+    L.gmg_solve_static.argtypes = [ctypes.POINTER(Options), P, P, P, P, P, P, D, I32, P, ctypes.POINTER(Info)]
+    L.gmg_solve_static.restype = st
     L.gmg_destroy.argtypes = [P]
     L.gmg_destroy.restype = None
     L.gmg_status_string.argtypes = [st]
@@ -406,6 +408,38 @@ class Profile:
             if n.value:
                 self.result[name] = {"launches": n.value, "total_ms": ms.value, "avg_ms": ms.value / n.value}
         return False
+
+
+def solve_static(kx, ky, kz, f, *, levels=None, precision="fp64", switch_n=0, persistent_wgs=1, rtol=1e-8,
+                 max_it=500, x0=None, out=None, cheb_degree=2, coarse_rule="arithmetic"):
+    """gmg_solve_static: build the hierarchy in the library's static device
+    workspace and solve, allocating nothing in the library (N <= 65).
+    Returns (x, info); raises GmgError for statuses other than the solve's."""
+    n = int(kx.shape[0])
+    for t, shp, nm in zip((kx, ky, kz), face_shapes(n), ("kx", "ky", "kz")):
+        if tuple(t.shape) != shp:
+            raise ValueError(f"{nm} must have shape {shp}, got {tuple(t.shape)}")
+    for t, nm in ((f, "f"), (out, "x"), (x0, "x0")):
+        if t is not None and tuple(t.shape) != (n, n, n):
+            raise ValueError(f"{nm} must have shape {(n, n, n)}")
+    L = lib()
+    o = Options()
+    L.gmg_default_options(ctypes.byref(o), n)
+    o.levels = default_levels(n) if levels is None else int(levels)
+    o.precision = {"fp64": FP64, "mixed": MIXED}[precision]
+    o.switch_n = int(switch_n)
+    o.persistent_wgs = int(persistent_wgs)
+    o.cheb_degree = int(cheb_degree)
+    o.coarse_rule = {"arithmetic": COARSE_ARITHMETIC, "harmonic": COARSE_HARMONIC}[coarse_rule]
+    x = torch.empty((n, n, n), dtype=torch.float64, device="cuda") if out is None else out
+    info = Info()
+    s = L.gmg_solve_static(ctypes.byref(o), _dev(kx, "kx"), _dev(ky, "ky"), _dev(kz, "kz"), _dev(f, "f"),
+                           _dev(x, "x"), None if x0 is None else _dev(x0, "x0"), float(rtol), int(max_it),
+                           ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), ctypes.byref(info))
+    if s not in (OK, ERR_NOT_CONVERGED, ERR_BREAKDOWN):
+        msg = L.gmg_last_error(None)
+        raise GmgError(s, f"gmg_solve_static: {msg.decode() if msg else ''}")
+    return x, info.as_dict(s)
 
 
 def calibration_copy(dst: torch.Tensor, src: torch.Tensor):

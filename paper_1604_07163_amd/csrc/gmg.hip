@@ -185,6 +185,21 @@ Tiling make_tiling(int n, int target, int width = gmg::TX, int rows = gmg::TY) {
     return t;
 }
 
+// A tiling with z-chunks of `chunk` planes, shortened (down to one plane)
+// where that would launch fewer than kMinWorkgroups workgroups.
+Tiling chunk_tiling(int n, int chunk, int width, int rows) {
+    Tiling t;
+    t.tiles_x = (n - 2) / width + 1;
+    t.tiles_y = (n - 2 + rows - 1) / rows;
+    const int planes = n - 2, tiles = t.tiles_x * t.tiles_y;
+    int nch = (planes + chunk - 1) / chunk;
+    if ((long long)tiles * nch < kMinWorkgroups) nch = std::min(planes, (kMinWorkgroups + tiles - 1) / tiles);
+    t.zchunk = (planes + nch - 1) / nch;
+    nch = (planes + t.zchunk - 1) / t.zchunk;
+    t.nblocks = t.tiles_x * t.tiles_y * nch;
+    return t;
+}
+
 // The same tiling with an even number of planes per z-chunk (so every chunk
 // starts on an odd plane), for the residual with z-reduction.
 Tiling even_chunks(Tiling t, int n) {
@@ -462,19 +477,30 @@ gmg_status smooth_grid(gmg_handle *h, int l, bool from_zero, const double *r64_c
         cur = 1;
         prev = -1;
     } else if (lh.post1) {
-        // both steps in one sweep, x0 in x, the result in t1
+        // both steps in one sweep, x0 in x, the result in t1 (the LDS-history
+        // kernel in FP32, the register-history one in FP64: measured faster)
         Prof pf(h, GMG_K_CHEB_POST2, fin);
         constexpr int rows = sizeof(V) == 4 ? gmg::TY_POST32 : gmg::TY_POST64;
         const dim3 gq(lh.tilq.nblocks), bq(gmg::TX * rows);
-        if (dot_r64) {
-            gmg::k_post2<V, K, true, rows><<<gq, bq, 0, h->stream>>>(L, lh.tilq, b, bufs[0], bufs[1], cc.cfirst,
-                                                                      cc.c1[1], cc.c2[1], dot_r64, h->partial, skip,
-                                                                      dot_q64);
-            if (nparts) *nparts = lh.tilq.nblocks;
+        const V c0 = cc.cfirst, c1 = cc.c1[1], c2 = cc.c2[1];
+        if constexpr (sizeof(V) == 4) {
+            if (dot_r64 && dot_q64)
+                gmg::k_post2<V, K, 2, rows><<<gq, bq, 0, h->stream>>>(L, lh.tilq, b, bufs[0], bufs[1], c0, c1, c2,
+                                                                       dot_r64, h->partial, skip, dot_q64);
+            else if (dot_r64)
+                gmg::k_post2<V, K, 1, rows><<<gq, bq, 0, h->stream>>>(L, lh.tilq, b, bufs[0], bufs[1], c0, c1, c2,
+                                                                       dot_r64, h->partial, skip);
+            else
+                gmg::k_post2<V, K, 0, rows><<<gq, bq, 0, h->stream>>>(L, lh.tilq, b, bufs[0], bufs[1], c0, c1, c2,
+                                                                       nullptr, nullptr, skip);
+        } else if (dot_r64) {
+            gmg::k_post2_rh<V, K, true, rows><<<gq, bq, 0, h->stream>>>(L, lh.tilq, b, bufs[0], bufs[1], c0, c1, c2,
+                                                                         dot_r64, h->partial, skip, dot_q64);
         } else {
-            gmg::k_post2<V, K, false, rows><<<gq, bq, 0, h->stream>>>(L, lh.tilq, b, bufs[0], bufs[1], cc.cfirst,
-                                                                       cc.c1[1], cc.c2[1], nullptr, nullptr, skip);
+            gmg::k_post2_rh<V, K, false, rows><<<gq, bq, 0, h->stream>>>(L, lh.tilq, b, bufs[0], bufs[1], c0, c1, c2,
+                                                                          nullptr, nullptr, skip);
         }
+        if (dot_r64 && nparts) *nparts = lh.tilq.nblocks;
         LAUNCHCHK();
         return GMG_OK;
     } else {
@@ -1288,9 +1314,10 @@ gmg_status build(gmg_handle *h, const double *kx, const double *ky, const double
         lh.til2 = make_tiling(n, t64, gmg::TX2);
         lh.tilp = make_tiling(n, env_int("GMG_TARGET_WGS_V", 1 << 20), gmg::TX, gmg::TY_PRE);
         lh.tilr = even_chunks(lh.til, n);
-        // one-sweep post-smoothing: 32-plane chunks at 513^3 (measured best for
-        // both precisions; its two extra x1 planes per chunk favour long chunks)
-        lh.tilq = mx ? make_tiling(n, env_int("GMG_TARGET_WGS_POST", 8192), gmg::TX, gmg::TY_POST32)
+        // one-sweep post-smoothing (measured at 513^3): FP32 16-plane chunks
+        // (18-plane chunks 2 % faster than 32-plane ones and than 9-plane
+        // ones); FP64 2048 workgroups (64-plane chunks; 32 measured the same)
+        lh.tilq = mx ? chunk_tiling(n, env_int("GMG_POST_CHUNK", 16), gmg::TX, gmg::TY_POST32)
                      : make_tiling(n, env_int("GMG_TARGET_WGS_POST", 2048), gmg::TX, gmg::TY_POST64);
         lh.rows = make_rows(n, lh.pitch, lh.plane);
         lh.g27 = o.galerkin > 0 && l >= o.galerkin;

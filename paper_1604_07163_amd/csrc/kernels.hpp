@@ -18,6 +18,7 @@
 // identically.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <type_traits>
 #include <stdint.h>
 
 namespace gmg {
@@ -219,6 +220,53 @@ __device__ __forceinline__ V apply_at(const Lev<V, K> &L, const V *u, long long 
     load_u(L, u, o, q);
     return apply7(q.up, q.uw, q.ue, q.us, q.un, q.ub, q.ut, q.kw, q.ke, q.ks, q.kn, q.kb, q.kt, L.s);
 }
+
+// ---------------------------------------------------------------- buffer addressing
+// Raw buffer resources (CDNA "buffer" instructions): an array's base address
+// for the current plane lives in scalar registers, each thread keeps a fixed
+// 32-bit byte offset, so a load costs no vector address arithmetic.  A load
+// whose offset is at or beyond the resource's byte count returns 0 and
+// touches no memory (a store is dropped); kernels give vertices outside the
+// grid the offset kOutside for that.
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+constexpr int kBufDword3 = 0x00020000;      // raw buffer, 32-bit data format (descriptor word 3)
+constexpr uint32_t kOutside = 0x80000000u;  // beyond every resource, also after small displacements
+__device__ __forceinline__ Rsrc rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, kBufDword3);
+}
+constexpr int kNT = 2;  // cache-policy bits of a streaming (nontemporal) access
+template <typename T>
+struct Buf;
+template <>
+struct Buf<float> {
+    template <int AUX = 0>
+    static __device__ __forceinline__ float ld(Rsrc r, uint32_t v, uint32_t s) {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, v, s, AUX));
+    }
+    template <int AUX = 0>
+    static __device__ __forceinline__ void st(float x, Rsrc r, uint32_t v, uint32_t s) {
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), r, v, s, AUX);
+    }
+};
+template <>
+struct Buf<double> {
+    template <int AUX = 0>
+    static __device__ __forceinline__ double ld(Rsrc r, uint32_t v, uint32_t s) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, AUX));
+    }
+    template <int AUX = 0>
+    static __device__ __forceinline__ void st(double x, Rsrc r, uint32_t v, uint32_t s) {
+        typedef decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)) U64;
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U64, x), r, v, s, AUX);
+    }
+};
+template <>
+struct Buf<uint16_t> {
+    template <int AUX = 0>
+    static __device__ __forceinline__ uint16_t ld(Rsrc r, uint32_t v, uint32_t s) {
+        return __builtin_amdgcn_raw_buffer_load_b16(r, v, s, AUX);
+    }
+};
 
 // ---------------------------------------------------------------- reductions
 // Deterministic workgroup sum: wave64 butterfly, then the per-wave values in
@@ -556,18 +604,262 @@ __global__ __launch_bounds__(NT) void k_cheb_step(Lev<V, K> L, Tiling t, const V
 // link levels):
 //   x1 = x0 + c0 D^-1 (b - A x0),   x2 = x1 + c1 (x1 - x0) + c2 D^-1 (b - A x1),
 // with the arithmetic of a k_cheb_step with PM = 0 followed by one with PM = 2,
-// so x2 is the same to the bit.  x1 never goes to memory: marching up its
-// z-chunk, the workgroup computes x1 one plane ahead on its 64 x 8 tile plus a
-// one-point ring (the ring is recomputed by the neighbouring tiles too) into
-// LDS, from x0 of that plane staged in LDS with a two-point ring; x2 of the
-// plane below then takes its in-plane x1 neighbours from LDS and x1 above and
-// below from registers.  One read of x0, b and the links and one write of x2
-// replace the two sweeps' reads of x0 (twice), b and the links (twice) and
-// the write and read of x1.  out must not alias x0 (other tiles read x0 in
-// their rings).  DOTR: partial[wg] = sum r64 . x2 (and q64 . x2 after it).
-// A tile is 64 x ROWS points, one thread each.
-template <typename V, typename K, bool DOTR, int ROWS>
+// so x2 is the same to the bit.  x1 never goes to memory.  A workgroup owns a
+// 64 x ROWS tile (one vertex per thread, one tile row per wave) and marches up
+// its z-chunk in phases m = k0-1 .. k1, one barrier each.  In phase m it
+//   * computes x1 of plane m at its own vertex from x0 of planes m-1 .. m+1,
+//   * on the last waves, computes x1 of plane m on a one-point ring around
+//     the tile (recomputed by the neighbouring tiles too),
+//   * computes x2 of plane m-1 from x1 of planes m-2 .. m,
+//   * stages x0 of plane m+2 (tile and a two-point ring).
+// x0 and x1 are kept in four-plane LDS ring buffers, so a thread holds no
+// plane history in registers: what it holds are the loads in flight for the
+// next phase (the links and b of plane m+1, x0 of plane m+3), which keeps the
+// register count, and with it the number of resident workgroups, up.  The
+// phase body is unrolled four times, so every LDS slot and register set is
+// named at compile time (slot = plane - k0 + 1 mod 4).  Loads go through one
+// buffer resource per array and chunk, the plane chosen by the scalar offset,
+// each thread with a fixed byte offset: no vector address arithmetic; a
+// vertex outside the grid gets an offset beyond every resource and reads 0.
+// The diagonal of a vertex is formed once and serves both steps.  One read of
+// x0, b and the links and one write of x2 replace the two sweeps' reads of x0
+// (twice), b and the links (twice) and the write and read of x1.  out must not
+// alias x0 (other tiles read x0 in their rings).  DOTR 1: partial[wg] =
+// sum r64 . x2; DOTR 2: and sum q64 . x2 after it.
+template <typename V, typename K, int DOTR, int ROWS>
 __global__ __launch_bounds__(TX * ROWS) void k_post2(Lev<V, K> L, Tiling t, const V *__restrict__ b,
+                                                   const V *__restrict__ x0, V *__restrict__ out, V c0, V c1, V c2,
+                                                   const double *__restrict__ r64, double *__restrict__ partial,
+                                                   const int *__restrict__ skip,
+                                                   const double *__restrict__ q64 = nullptr) {
+    constexpr int W = TX, H = ROWS, NTH = TX * ROWS;
+    constexpr int XW = W + 4, YW = W + 2;       // row lengths of the x0 and x1 tiles
+    constexpr int HALO0 = 4 * XW + 4 * H;       // two-point ring of the x0 tile
+    constexpr int RING = 2 * YW + 2 * H;        // one-point ring of the x1 tile
+    constexpr int RING0 = NTH - RING;           // first thread of the ring
+    static_assert(HALO0 <= NTH && RING <= NTH, "one pass per ring");
+    constexpr uint32_t SV = sizeof(V), SK = sizeof(K);
+    __shared__ V sx0[4][H + 4][XW];  // x0 by plane slot, tile at [2, H+1] x [2, W+1]
+    __shared__ V sx1[4][H + 2][YW];  // x1 by plane slot, tile at [1, H] x [1, W]
+    if (skip && *skip) return;
+    int tx, ty, cz;
+    tile_of(blockIdx.x, t, tx, ty, cz);
+    const int lx = (int)(threadIdx.x & (W - 1)), ly = (int)(threadIdx.x >> 6);
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int i0 = tx * W, j0 = 1 + ty * H;  // grid position of tile point (0, 0)
+    const int i = i0 + lx, j = j0 + ly;
+    const int n = L.n, pitch = L.pitch;
+    const long long plane = L.plane;
+    const int k0 = 1 + cz * t.zchunk, k1 = min(k0 + t.zchunk, n - 1);
+    if (k0 >= k1) return;  // uniform over the workgroup
+    const int np = k1 - k0 + 2;  // phases
+    auto in_xy = [n](int a, int c) { return (unsigned)a < (unsigned)n && (unsigned)c < (unsigned)n; };
+    auto inner_xy = [n](int a, int c) { return a >= 1 && a <= n - 2 && c >= 1 && c <= n - 2; };
+    const bool own_inner = inner_xy(i, j);
+    const uint32_t own = (uint32_t)(j * pitch + i);
+    const uint32_t ox0 = in_xy(i, j) ? own * SV : kOutside;     // x0 of the own vertex
+    const uint32_t ok = own_inner ? own * SK : kOutside;         // its links
+    const uint32_t ov = own_inner ? own * SV : kOutside;         // its b and x2
+    const uint32_t o8 = own_inner ? own * 8u : kOutside;         // its r64, q64
+    // x0 ring slot of this thread (threads 0 .. HALO0-1): two rows above and
+    // below the tile, two columns left and right of it
+    const int h = (int)threadIdx.x;
+    int hy = 0, hx = 0;
+    if (h < 4 * XW) {
+        const int r = h / XW;
+        hy = r < 2 ? r : r + H;
+        hx = h % XW;
+    } else {
+        const int r = h - 4 * XW;
+        hy = 2 + r / 4;
+        hx = (r & 3) < 2 ? (r & 3) : (r & 3) + W;
+    }
+    const bool hal = h < HALO0;
+    const uint32_t ohal =
+        (hal && in_xy(i0 - 2 + hx, j0 - 2 + hy)) ? (uint32_t)((j0 - 2 + hy) * pitch + (i0 - 2 + hx)) * SV : kOutside;
+    // x1 ring slot (threads RING0 .. NTH-1): one row above and below, one
+    // column left and right
+    const int g = h - RING0;
+    int gy = 1, gx = 1;  // a valid slot for threads outside the ring
+    if (g < 0) {
+    } else if (g < 2 * YW) {
+        gy = g < YW ? 0 : H + 1;
+        gx = g % YW;
+    } else {
+        const int q = g - 2 * YW;
+        gy = 1 + q / 2;
+        gx = (q & 1) ? W + 1 : 0;
+    }
+    const bool rng = g >= 0;
+    const bool rng_inner = rng && inner_xy(i0 - 1 + gx, j0 - 1 + gy);
+    const uint32_t rpt = (uint32_t)((j0 - 1 + gy) * pitch + (i0 - 1 + gx));
+    const uint32_t rk = rng_inner ? rpt * SK : kOutside, rv = rng_inner ? rpt * SV : kOutside;
+    const bool ring_wave = wave >= RING0 / 64;  // uniform: this wave holds ring threads
+
+    // One resource per array for the whole chunk, based at plane mb = k0-2
+    // (kx one element back: kx[o-1] at offset o; ky one row back: ky[o-pitch]
+    // at o); plane m is reached through the scalar offset (m - mb) * plane
+    // bytes.  The byte count admits every offset below kOutside.
+    const long long mb = (long long)(k0 - 2) * plane;
+    constexpr uint32_t kAll = 0x7fffffffu;
+    const Rsrc rx0 = rsrc(x0 + mb, kAll), rb = rsrc(b + mb, kAll), rout = rsrc(out + mb, kAll);
+    const Rsrc rkx = rsrc(L.kx + (mb - 1), kAll), rky = rsrc(L.ky + (mb - pitch), kAll), rkz = rsrc(L.kz + mb, kAll);
+    const Rsrc rr64 = rsrc(r64 + mb, kAll), rq64 = rsrc(q64 ? q64 + mb : r64 + mb, kAll);
+    const uint32_t pbv = (uint32_t)plane * SV, pbk = (uint32_t)plane * SK, pb8 = (uint32_t)plane * 8u;
+    auto uni = [](uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); };  // keep in a scalar
+    // x0 of plane m (0 outside the grid); planes are passed as m - mb
+    auto x0_at = [&](int m, uint32_t off) -> V {
+        return (m >= 0 && m < n) ? Buf<V>::ld(rx0, off, uni((uint32_t)(m - k0 + 2)) * pbv) : V(0);
+    };
+    struct Raw {  // a vertex's links (without the one below) and b at one plane, as stored
+        K kw, ke, ks, kn, kt;
+        V bv;
+    };
+    auto load_raw = [&](int m, uint32_t okk, uint32_t ovv, Raw &r) {
+        const uint32_t pl = uni((uint32_t)(m - k0 + 2)), sk = pl * pbk, sv = pl * pbv;
+        r.kw = Buf<K>::ld(rkx, okk, sk);
+        r.ke = Buf<K>::template ld<kNT>(rkx, okk + SK, sk);
+        r.ks = Buf<K>::ld(rky, okk, sk);
+        r.kn = Buf<K>::ld(rky, okk + (uint32_t)pitch * SK, sk);
+        r.kt = Buf<K>::template ld<kNT>(rkz, okk, sk);
+        r.bv = Buf<V>::template ld<kNT>(rb, ovv, sv);
+    };
+    struct Lk {  // the same widened, with the link below and the diagonal
+        V kw, ke, ks, kn, kb, kt, bv, d;
+    };
+    auto widen = [&](const Raw &r, V kb, Lk &w) {
+        w.kw = kval(r.kw);
+        w.ke = kval(r.ke);
+        w.ks = kval(r.ks);
+        w.kn = kval(r.kn);
+        w.kb = kb;
+        w.kt = kval(r.kt);
+        w.bv = r.bv;
+        w.d = diag7(w.kw, w.ke, w.ks, w.kn, w.kb, w.kt, L.s);
+    };
+
+    // plane-indexed state: x0 and x1 of plane m live in LDS slot
+    // (m - k0 + 1) & 3, the links and b of plane m in register set & 1
+    Lk lk[2];   // own links, b and diagonal
+    double R64[2] = {0.0, 0.0}, Q64[2] = {0.0, 0.0};
+    V rkt[2];   // ring vertex: its upper z-link, widened
+    Raw ro, rr;  // own / ring raw links and b of the next plane
+    V xp, hp;   // the thread's x0 (own, ring slot) of the next plane to stage
+    double dot = 0.0, dotq = 0.0;
+
+    // prologue: x0 of planes k0-2 .. k0 into LDS (the ring from k0-1), x0 of
+    // plane k0+1 into registers, the links of plane k0-1 (own) and k0 (ring)
+    {
+        const V a0 = x0_at(k0 - 2, ox0), a1 = x0_at(k0 - 1, ox0), a2 = x0_at(k0, ox0);
+        const V h1 = x0_at(k0 - 1, ohal), h2 = x0_at(k0, ohal);
+        sx0[3][ly + 2][lx + 2] = a0;
+        sx0[0][ly + 2][lx + 2] = a1;
+        sx0[1][ly + 2][lx + 2] = a2;
+        if (hal) {
+            sx0[0][hy][hx] = h1;
+            sx0[1][hy][hx] = h2;
+        }
+    }
+    xp = x0_at(k0 + 1, ox0);
+    hp = x0_at(k0 + 1, ohal);
+    load_raw(k0 - 1, ok, ov, ro);
+    lk[1].kt = (k0 - 2 >= 0) ? kval(Buf<K>::ld(rkz, ok, 0)) : V(0);
+    rkt[0] = kval(Buf<K>::ld(rkz, rk, pbk));
+    load_raw(k0, rk, rv, rr);
+    __syncthreads();
+
+    // phase p = m - k0 + 1 with slot index Q = p & 3; returns true after the last phase
+    auto phase = [&](auto QQ, int p) __attribute__((always_inline)) -> bool {
+        constexpr int Q = decltype(QQ)::value;
+        constexpr int P = Q & 1, QB = (Q + 3) & 3, QT = (Q + 1) & 3, QBB = (Q + 2) & 3;
+        const int m = k0 - 1 + p;
+        // x1 of plane m at the own vertex (0 on boundary planes and vertices)
+        Lk &cw = lk[P];
+        widen(ro, lk[P ^ 1].kt, cw);
+        V x1m;
+        {
+            const V(*t0)[XW] = sx0[Q];
+            const V xc = t0[ly + 2][lx + 2];
+            const V ax = apply7(xc, t0[ly + 2][lx + 1], t0[ly + 2][lx + 3], t0[ly + 1][lx + 2], t0[ly + 3][lx + 2],
+                                sx0[QB][ly + 2][lx + 2], sx0[QT][ly + 2][lx + 2], cw.kw, cw.ke, cw.ks, cw.kn, cw.kb,
+                                cw.kt, L.s);
+            const V v = cheb_step_val(xc, V(0), cw.bv, ax, cw.d, V(0), c0);
+            x1m = (own_inner && m >= 1 && m <= n - 2) ? v : V(0);
+        }
+        if (p + 1 < np) load_raw(m + 1, ok, ov, ro);
+        // r64 (q64) of plane m for the dot of x2(m) in the next phase
+        if (DOTR && p >= 1 && p + 1 < np) {
+            R64[P] = Buf<double>::template ld<kNT>(rr64, o8, uni((uint32_t)(p + 1)) * pb8);
+            if (DOTR == 2) Q64[P] = Buf<double>::template ld<kNT>(rq64, o8, uni((uint32_t)(p + 1)) * pb8);
+        }
+        // planes k0-1 .. k1-1: own x1 into LDS (the history of x2 and, from
+        // k0 on, the in-plane neighbours with the ring)
+        if (p + 1 < np) sx1[Q][ly + 1][lx + 1] = x1m;
+        if (p >= 1 && p + 1 < np && ring_wave) {
+            Lk w;
+            widen(rr, rkt[P ^ 1], w);
+            rkt[P] = w.kt;
+            const V(*t0)[XW] = sx0[Q];
+            const int ry = gy + 1, rx = gx + 1;
+            const V xc = t0[ry][rx];
+            const V ax = apply7(xc, t0[ry][rx - 1], t0[ry][rx + 1], t0[ry - 1][rx], t0[ry + 1][rx], sx0[QB][ry][rx],
+                                sx0[QT][ry][rx], w.kw, w.ke, w.ks, w.kn, w.kb, w.kt, L.s);
+            const V v = cheb_step_val(xc, V(0), w.bv, ax, w.d, V(0), c0);
+            if (rng) sx1[Q][gy][gx] = rng_inner ? v : V(0);
+            if (p + 2 < np) load_raw(m + 1, rk, rv, rr);
+        }
+        // x2 of plane m-1
+        if (p >= 2) {
+            const Lk &pw = lk[P ^ 1];
+            const V(*t1)[YW] = sx1[QB];
+            const V x1c = t1[ly + 1][lx + 1];
+            const V ax = apply7(x1c, t1[ly + 1][lx], t1[ly + 1][lx + 2], t1[ly][lx + 1], t1[ly + 2][lx + 1],
+                                sx1[QBB][ly + 1][lx + 1], x1m, pw.kw, pw.ke, pw.ks, pw.kn, pw.kb, pw.kt, L.s);
+            const V diff = x1c - sx0[QB][ly + 2][lx + 2];
+            const V v = own_inner ? cheb_step_val(x1c, diff, pw.bv, ax, pw.d, c1, c2) : V(0);
+            Buf<V>::template st<kNT>(v, rout, ov, uni((uint32_t)p) * pbv);
+            if (DOTR) {
+                dot = fmaT(R64[P ^ 1], (double)v, dot);
+                if (DOTR == 2) dotq = fmaT(Q64[P ^ 1], (double)v, dotq);
+            }
+        }
+        // x0 of plane m+2 into LDS (its ring only up to plane k1), x0 of
+        // plane m+3 into registers
+        if (p + 3 <= np + 1) sx0[QBB][ly + 2][lx + 2] = xp;
+        if (p + 3 <= np && hal) sx0[QBB][hy][hx] = hp;
+        if (p + 4 <= np + 1) xp = x0_at(m + 3, ox0);
+        if (p + 4 <= np) hp = x0_at(m + 3, ohal);
+        __syncthreads();
+        return p + 1 == np;
+    };
+    for (int p = 0;; p += 4) {
+        if (phase(std::integral_constant<int, 0>{}, p)) break;
+        if (phase(std::integral_constant<int, 1>{}, p + 1)) break;
+        if (phase(std::integral_constant<int, 2>{}, p + 2)) break;
+        if (phase(std::integral_constant<int, 3>{}, p + 3)) break;
+    }
+    if (DOTR) {
+        const double sm = block_sum<NTH>(dot);
+        if (threadIdx.x == 0) partial[blockIdx.x] = sm;
+        if (DOTR == 2) {
+            const double sq = block_sum<NTH>(dotq);
+            if (threadIdx.x == 0) partial[gridDim.x + blockIdx.x] = sq;
+        }
+    }
+}
+
+// The same one-sweep post-smoothing with the plane history in registers
+// (register-history form, used for FP64 levels): the thread keeps its x0 of
+// planes m-1, m and its x1 of planes m-2, m-1 in registers, x0 of a plane is
+// staged in LDS with a two-point ring and x1 with a one-point ring (two
+// buffers each, by plane parity), all loads of a plane issued at the start of
+// its phase.  Measured on MI355X at 513^3 in FP64 it is 7 % faster than the
+// LDS-history kernel above, whose eight-byte LDS traffic and larger register
+// count (one 1024-thread workgroup per CU either way) cost more than its
+// prefetch gains; in FP32/BF16 the LDS-history kernel is 7 % faster.
+// Arithmetic, results and argument meaning are those of k_post2.
+template <typename V, typename K, bool DOTR, int ROWS>
+__global__ __launch_bounds__(TX * ROWS) void k_post2_rh(Lev<V, K> L, Tiling t, const V *__restrict__ b,
                                                    const V *__restrict__ x0, V *__restrict__ out, V c0, V c1, V c2,
                                                    const double *__restrict__ r64, double *__restrict__ partial,
                                                    const int *__restrict__ skip,

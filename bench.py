@@ -167,17 +167,18 @@ def error_vs_oracle(x, workload):
             "oracle_iterations": g["iterations"], "oracle_rel_res_true": g["rel_res_true"]}
 
 
-def copy_bandwidth(nbytes=2 << 30, reps=5):
-    """Achievable HBM bandwidth of a plain streaming copy (read + write bytes / time)."""
+def copy_bandwidth(nbytes=2 << 30, reps=5, planes=1):
+    """Achievable HBM bandwidth of a streaming copy (read + write bytes / time);
+    planes > 1: the z-march pattern of the stencil kernels."""
     import torch
     from paper_1604_07163_amd import gmg
     a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
-    gmg.calibration_copy(b, a)
+    gmg.calibration_copy(b, a, planes)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
-        gmg.calibration_copy(b, a)
+        gmg.calibration_copy(b, a, planes)
     e1.record()
     e1.synchronize()
     ms = e0.elapsed_time(e1) / reps
@@ -433,7 +434,7 @@ CLASS_KERNELS = {
     "cheb_pre2": "k_cheb_pre2<float, bf16, false>",
     "cheb_step": "k_cheb_step<float, bf16, 0, false>",
     "cheb_step_dot": "k_cheb_step<float, bf16, 2, true>",
-    "cheb_post2": "k_post2<float, bf16, true, 8>",
+    "cheb_post2": "k_post2<float, bf16, 1, 8>",
     "level_residual": "k_residual_zr<float, bf16>",
     "restrict": "k_restrict_xy<float>",
     "prolong": "k_prolong<float>",
@@ -477,10 +478,10 @@ def pmc_traffic(fetch_dir, write_dir, n=513):
         vals[counter] = per
     scale = {}
     for c in ("FETCH_SIZE", "WRITE_SIZE"):
-        cp = vals[c]["k_copy_flat"]
+        cp = vals[c]["k_copy_march"]
         scale[c] = COPY_BYTES / (1024.0 * sum(cp) / len(cp))
     lines = [f"source_digest: {source_digest()}",
-             f"calibration: k_copy_flat of {COPY_BYTES} bytes; FETCH_SIZE x {scale['FETCH_SIZE']:.4f}, "
+             f"calibration: k_copy_march of {COPY_BYTES} bytes; FETCH_SIZE x {scale['FETCH_SIZE']:.4f}, "
              f"WRITE_SIZE x {scale['WRITE_SIZE']:.4f}", "",
              "| class | kernel | level-0 dispatches | read GB | written GB | traffic GB | algorithmic GB | ratio |",
              "|---|---|---:|---:|---:|---:|---:|---:|"]
@@ -502,6 +503,46 @@ def pmc_traffic(fetch_dir, write_dir, n=513):
                      f"{alg / 1e9:.3f} | {(rd + wr) / alg:.3f} |")
         figures.append(f"traffic_bytes {cls}: {rd + wr:.6e}")
     print("\n".join(lines + [""] + figures))
+
+
+def sq_summary(d, n=513):
+    """Markdown table of rocprofv3 SQ counter passes (CSV folders under d):
+    per kernel, the dispatches with the largest grid averaged.  Per-wave
+    figures for every kernel; per-unknown figures (x 64 lanes, i.e. wave
+    instructions per 64 unknowns) only for the finest-level kernels of the
+    MIXED step (CLASS_KERNELS), divided by the finest level's (n-2)^3
+    unknowns.  Host only."""
+    import csv
+    import glob
+    from collections import defaultdict
+    res = defaultdict(lambda: defaultdict(list))
+    for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(path)):
+            grid = int(float(r.get("Grid_Size") or r.get("Grid_Size_X") or "0"))
+            res[(_short(r["Kernel_Name"]), grid)][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    largest = {}
+    for nm, g in res:
+        largest[nm] = max(g, largest.get(nm, 0))
+    finest = set(CLASS_KERNELS.values())
+    wp = (n - 2) ** 3 / 64.0
+    cols = ["SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_VMEM", "SQ_INSTS_LDS"]
+    out = ["| kernel | grid (threads) | dispatches | waves | VALU/wave | SALU/wave | VMEM/wave | LDS/wave | "
+           "VALU per 64 finest unknowns | wait any | wait inst | VALU active |",
+           "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for nm in sorted(largest):
+        g = largest[nm]
+        c = {k: sum(v) / len(v) for k, v in res[(nm, g)].items()}
+        waves = c.get("SQ_WAVES")
+        if not waves:
+            continue
+        disp = len(res[(nm, g)]["SQ_WAVES"])
+        per = [f"{c[k] / waves:.0f}" if k in c else "" for k in cols]
+        pu = f"{c['SQ_INSTS_VALU'] / wp:.1f}" if nm in finest and "SQ_INSTS_VALU" in c else "(not finest)"
+        wc = c.get("SQ_WAVE_CYCLES")
+        fr = [f"{c[k] / wc:.3f}" if wc and k in c else "" for k in ("SQ_WAIT_ANY", "SQ_WAIT_INST_ANY",
+                                                                     "SQ_ACTIVE_INST_VALU")]
+        out.append(f"| `{nm}` | {g} | {disp} | {waves:.0f} | " + " | ".join(per) + f" | {pu} | " + " | ".join(fr) + " |")
+    print("\n".join(out))
 
 
 def traffic_for(cls, workload):
@@ -541,6 +582,8 @@ def main():
     ap.add_argument("--pmc-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="print HBM traffic per finest-level launch from rocprofv3 FETCH_SIZE / WRITE_SIZE "
                          "folders and exit (host only)")
+    ap.add_argument("--sq-summary", metavar="DIR",
+                    help="print a table of rocprofv3 SQ counter folders under DIR and exit (host only)")
     ap.add_argument("--galerkin", type=int, nargs="*", default=[],
                     help="with --sweep: also time Galerkin coarse operators from these first levels")
     ap.add_argument("--no-agglomeration", action="store_true",
@@ -554,6 +597,9 @@ def main():
         return
     if args.pmc_traffic:
         pmc_traffic(*args.pmc_traffic)
+        return
+    if args.sq_summary:
+        sq_summary(args.sq_summary)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1).", flush=True)
@@ -579,7 +625,8 @@ def main():
     del kobs_in
 
     copy_gbs = copy_bandwidth()
-    log(f"plain copy: {copy_gbs:.0f} GB/s")
+    copy_march = {str(pl): copy_bandwidth(planes=pl) for pl in (8, 32)}
+    log(f"streaming copy: {copy_gbs:.0f} GB/s one element per thread; z-march copy {copy_march} GB/s")
     legs = {}
     results = {}
     for prec in (["mixed"] if args.no_fp64 else ["mixed", "fp64"]):
@@ -636,7 +683,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(dom, args.workload),
                      "bytes_per_launch": bytes_per_launch, "avg_ms": cands[dom]["avg_ms"],
-                     "copy_GBs": copy_gbs},
+                     "copy_GBs": copy_gbs, "copy_march_GBs": copy_march},
         "T_solve": {"definition": "median of 5 forward solves from x0 = 0, setup excluded (HIP events)",
                     "mixed_ms": mixed["T_solve_ms"], "mixed_unknowns_per_s": n_unk / (mixed["T_solve_ms"] / 1e3)},
         "forward": {"iterations": mixed["forward"]["iterations"], "rel_res_true": mixed["forward"]["rel_res_true"],

@@ -283,12 +283,15 @@ gmg_status gmg_profile_stop(gmg_handle *h);   /* stop recording, wait for the st
 gmg_status gmg_profile_get(gmg_handle *h, int32_t kclass, int32_t *launches, double *total_ms);
 const char *gmg_kernel_class_name(int32_t kclass);
 
-/* Plain device-to-device copy of `bytes` (a multiple of 16) with a streaming
- * kernel (one 16-byte element per thread) on `stream`; returns after it
- * completes; GMG_ERR_ARG for null pointers, a size that is not a multiple of
- * 16 or needs more than 2^31 - 1 workgroups.  Used to calibrate the
- * profiler's HBM byte counters and to measure achievable copy bandwidth. */
-gmg_status gmg_calibration_copy(void *dst, const void *src, uint64_t bytes, void *stream);
+/* Plain device-to-device copy of `bytes` on `stream` with nontemporal 16-byte
+ * loads and stores; returns after it completes.  planes = 1: one element per
+ * thread.  planes > 1: the buffers are `planes` equal slabs and each thread
+ * copies its element of every slab in turn, the access pattern of the
+ * z-marching stencil kernels.  GMG_ERR_ARG for null pointers, planes < 1, a
+ * size that is not a multiple of 16 * planes or needs more than 2^31 - 1
+ * workgroups.  Used to calibrate the profiler's HBM byte counters and to
+ * measure achievable copy bandwidth. */
+gmg_status gmg_calibration_copy(void *dst, const void *src, uint64_t bytes, int32_t planes, void *stream);
 
 void gmg_destroy(gmg_handle *h);
 const char *gmg_status_string(gmg_status s);

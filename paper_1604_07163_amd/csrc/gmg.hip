@@ -1854,13 +1854,14 @@ const char *gmg_kernel_class_name(int32_t c) {
 
 }  // extern "C"
 
-extern "C" gmg_status gmg_calibration_copy(void *dst, const void *src, uint64_t bytes, void *stream) {
-    if (!dst || !src || (bytes % 16) != 0) return GMG_ERR_ARG;
-    const long long n16 = (long long)(bytes / 16);
+extern "C" gmg_status gmg_calibration_copy(void *dst, const void *src, uint64_t bytes, int32_t planes,
+                                           void *stream) {
+    if (!dst || !src || planes < 1 || (bytes % (16ull * (uint64_t)planes)) != 0) return GMG_ERR_ARG;
+    const long long n16 = (long long)(bytes / 16 / (uint64_t)planes);
     const long long nb = (n16 + 255) / 256;
     if (nb > 0x7fffffffLL) return GMG_ERR_ARG;
-    gmg::k_copy_flat<<<(unsigned)(nb > 0 ? nb : 1), 256, 0, (hipStream_t)stream>>>(n16, (const uint4 *)src,
-                                                                                   (uint4 *)dst);
+    gmg::k_copy_march<<<(unsigned)(nb > 0 ? nb : 1), 256, 0, (hipStream_t)stream>>>(
+        n16, planes, (const gmg::u32x4 *)src, (gmg::u32x4 *)dst);
     if (hipGetLastError() != hipSuccess) return GMG_ERR_HIP;
     if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return GMG_ERR_HIP;
     return GMG_OK;

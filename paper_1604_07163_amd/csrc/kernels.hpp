@@ -1874,10 +1874,19 @@ __global__ __launch_bounds__(NT_FLAT) void k_dot(Rows R, const double *__restric
 }
 
 // Plain streaming copy for counter calibration: one 16-byte element per thread.
-__global__ __launch_bounds__(256) void k_copy_flat(long long n16, const uint4 *__restrict__ src,
-                                                   uint4 *__restrict__ dst) {
+// Streaming copy of `planes` slabs of n16 16-byte elements each: thread e of
+// the grid copies element e of every slab in turn (planes = 1: one element
+// per thread; planes > 1: the z-march of the stencil kernels, one slab per
+// step), with nontemporal loads and stores.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_copy_march(long long n16, int planes, const u32x4 *__restrict__ src,
+                                                    u32x4 *__restrict__ dst) {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < n16) dst[e] = src[e];
+    if (e >= n16) return;
+    for (int k = 0; k < planes; ++k) {
+        const long long o = (long long)k * n16 + e;
+        __builtin_nontemporal_store(__builtin_nontemporal_load(&src[o]), &dst[o]);
+    }
 }
 
 // ---------------------------------------------------------------- inexact coarse CG

@@ -116,7 +116,7 @@ def lib():
     L.gmg_profile_get.restype = st
     L.gmg_kernel_class_name.argtypes = [I32]
     L.gmg_kernel_class_name.restype = ctypes.c_char_p
-    L.gmg_calibration_copy.argtypes = [P, P, ctypes.c_uint64, P]
+    L.gmg_calibration_copy.argtypes = [P, P, ctypes.c_uint64, ctypes.c_int32, P]
     L.gmg_calibration_copy.restype = st
     L.gmg_solve_static.argtypes = [ctypes.POINTER(Options), P, P, P, P, P, P, D, I32, P, ctypes.POINTER(Info)]
     L.gmg_solve_static.restype = st
@@ -442,13 +442,14 @@ def solve_static(kx, ky, kz, f, *, levels=None, precision="fp64", switch_n=0, pe
     return x, info.as_dict(s)
 
 
-def calibration_copy(dst: torch.Tensor, src: torch.Tensor):
-    """dst <- src with the library's plain streaming copy kernel (same byte count)."""
+def calibration_copy(dst: torch.Tensor, src: torch.Tensor, planes: int = 1):
+    """dst <- src with the library's streaming copy kernel (same byte count);
+    planes > 1 copies in the z-march pattern of the stencil kernels."""
     nbytes = src.numel() * src.element_size()
     if dst.numel() * dst.element_size() != nbytes or not (dst.is_cuda and src.is_cuda):
         raise ValueError("calibration_copy: device tensors of equal byte size required")
     s = lib().gmg_calibration_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nbytes,
-                                   ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+                                   int(planes), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
     if s != OK:
         raise GmgError(s, "gmg_calibration_copy")
 

@@ -62,4 +62,4 @@ def test_kernel_class_names_match_binding():
     L = gmg.lib()
     assert [L.gmg_kernel_class_name(i).decode() for i in range(len(gmg.KERNEL_CLASSES))] == gmg.KERNEL_CLASSES
     assert L.gmg_kernel_class_name(len(gmg.KERNEL_CLASSES)).decode() == "unknown"
-    assert L.gmg_calibration_copy(None, None, 16, None) == 1
+    assert L.gmg_calibration_copy(None, None, 16, 1, None) == 1

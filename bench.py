@@ -41,10 +41,10 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 BYTES_PER_POINT = {
     "fp64": {"apply_dot": 40, "residual": 48, "update_r": 24, "update_xp": 40, "update_p": 16, "cheb_first": 24, "cheb_pre2": 48,
              "cheb_step": 48, "cheb_step_prev": 56, "cheb_step_dot": 56, "level_residual": 44,
-             "restrict": 5, "prolong": 17, "face_gradient": 64, "cheb_post2": 56},
+             "restrict": 5, "prolong": 17, "face_gradient": 64, "cheb_post2": 56, "pre2_res": 52},
     "mixed": {"apply_dot": 36, "residual": 48, "update_r": 28, "update_xp": 28, "update_p": 8, "cheb_first": 20, "cheb_pre2": 18,
               "cheb_step": 18, "cheb_step_prev": 22, "cheb_step_dot": 30, "level_residual": 16,
-              "restrict": 2.5, "prolong": 8.5, "face_gradient": 64, "cheb_post2": 26},
+              "restrict": 2.5, "prolong": 8.5, "face_gradient": 64, "cheb_post2": 26, "pre2_res": 20},
 }
 
 WORKLOADS = {

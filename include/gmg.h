@@ -276,7 +276,8 @@ typedef enum {
     GMG_K_UPDATE_XP = 14,     /* x += alpha p, p = z + beta p */
     GMG_K_CHEB_PRE2 = 15,     /* first two Chebyshev steps from zero, fused */
     GMG_K_CHEB_POST2 = 16,    /* post-smoothing, both Chebyshev steps in one sweep (+ partial r.z) */
-    GMG_K_COUNT = 17
+    GMG_K_PRE2_RES = 17,      /* pre-smoothing (two Chebyshev steps from zero) and the residual in one sweep */
+    GMG_K_COUNT = 18
 } gmg_kernel_class;
 gmg_status gmg_profile_start(gmg_handle *h);  /* clear counters, start recording */
 gmg_status gmg_profile_stop(gmg_handle *h);   /* stop recording, wait for the stream */

@@ -48,6 +48,8 @@ struct LevelHost {
     Tiling tilp{};   // pre-smoothing kernel, two rows per thread
     Tiling tilq{};   // one-sweep post-smoothing kernel
     Tiling tilr{};   // residual with z-reduction (even z-chunks)
+    Tiling tilf{};   // pre-smoothing + residual in one sweep (64 x 8 tiles, even z-chunks)
+    bool pre1 = false;   // pre-smoothing and residual in one sweep
     bool post1 = false;  // post-smoothing in one sweep, its result in t1 (else in x)
     gmg::Rows rows{};
     // the buffer that holds the level's V-cycle result after post-smoothing
@@ -618,6 +620,25 @@ gmg_status residual_restrict(gmg_handle *h, int l, const int *skip) {
     return GMG_OK;
 }
 
+// Pre-smoothing from zero and the residual's z-sums in one sweep (x2 into x,
+// the z-sums into t1), then the in-plane restriction to the coarse b.
+template <typename V, typename K>
+gmg_status pre_residual_restrict(gmg_handle *h, int l, const int *skip) {
+    LevelHost &f = h->lv[l], &c = h->lv[l + 1];
+    const ChebCoef<V> &cc = cheb<V>(h, l);
+    {
+        Prof pf(h, GMG_K_PRE2_RES, l == 0);
+        gmg::k_pre2_res<V, K, gmg::TY_POST32><<<f.tilf.nblocks, gmg::TX * gmg::TY_POST32, 0, h->stream>>>(
+            view<V, K>(f), f.tilf, (const V *)f.b, (V *)f.x, (V *)f.t1, cc.cfirst, cc.c1[1], cc.c2[1], skip);
+        LAUNCHCHK();
+    }
+    Prof pf(h, GMG_K_RESTRICT, l == 0);
+    gmg::k_restrict_xy<V><<<c.til.nblocks, gmg::NT, 0, h->stream>>>(c.n, c.pitch, c.plane, c.til, f.pitch, f.plane,
+                                                                    (const V *)f.t1, (V *)c.b, skip);
+    LAUNCHCHK();
+    return GMG_OK;
+}
+
 template <typename V, typename K>
 gmg_status coarse_part(gmg_handle *h, const int *skip) {
     const int last = h->L - 1;
@@ -692,8 +713,13 @@ gmg_status vcycle(gmg_handle *h, const int *skip, bool want_dot, int *nparts, bo
     }
     const int s = h->s_persist;  // levels 0..s-1 on the grid path
     for (int l = 0; l < s; ++l) {
-        STCHK((smooth_grid<V, K>(h, l, true, (l == 0 && mx && !b_ready) ? h->R : nullptr, nullptr, skip, nullptr)));
-        STCHK((residual_restrict<V, K>(h, l, skip)));
+        const double *cvt = (l == 0 && mx && !b_ready) ? h->R : nullptr;
+        if (h->lv[l].pre1 && !cvt) {
+            STCHK((pre_residual_restrict<V, K>(h, l, skip)));
+        } else {
+            STCHK((smooth_grid<V, K>(h, l, true, cvt, nullptr, skip, nullptr)));
+            STCHK((residual_restrict<V, K>(h, l, skip)));
+        }
     }
     STCHK((coarse_part<V, K>(h, skip)));
     for (int l = s - 1; l >= 0; --l) {
@@ -1314,6 +1340,9 @@ gmg_status build(gmg_handle *h, const double *kx, const double *ky, const double
         lh.til2 = make_tiling(n, t64, gmg::TX2);
         lh.tilp = make_tiling(n, env_int("GMG_TARGET_WGS_V", 1 << 20), gmg::TX, gmg::TY_PRE);
         lh.tilr = even_chunks(lh.til, n);
+        // pre-smoothing + residual in one sweep (FP64 only): 64-plane chunks at 513^3
+        // (2.25 ms; 32-plane 2.28 ms, 16-plane 2.40 ms, 8-plane 2.68 ms)
+        lh.tilf = even_chunks(chunk_tiling(n, env_int("GMG_PRE_CHUNK", 64), gmg::TX, gmg::TY_POST32), n);
         // one-sweep post-smoothing (measured at 513^3): FP32 16-plane chunks
         // (18-plane chunks 2 % faster than 32-plane ones and than 9-plane
         // ones); FP64 2048 workgroups (64-plane chunks; 32 measured the same)
@@ -1346,6 +1375,16 @@ gmg_status build(gmg_handle *h, const double *kx, const double *ky, const double
     // one-sweep post-smoothing on the grid-path link levels (degree 2)
     for (int l = 0; l < h->s_persist; ++l)
         h->lv[l].post1 = (o.post_fused == 1 || o.post_fused == 2) && !h->lv[l].g27 && o.cheb_degree == 2;
+    {
+        // pre-smoothing and residual in one sweep on the FP64 grid levels (at 513^3
+        // 2.25 ms against 1.38 + 1.31 ms for the two sweeps; in FP32/BF16 the one
+        // sweep measured 1.15 ms against 0.56 + 0.46 ms, so MIXED keeps two);
+        // GMG_PRE_FUSED=0 selects the two sweeps in FP64 too
+        const char *e = getenv("GMG_PRE_FUSED");
+        const bool pre_on = !(e && e[0] == '0');
+        for (int l = 0; l < h->s_persist; ++l)
+            h->lv[l].pre1 = pre_on && !mx && !h->lv[l].g27 && o.cheb_degree == 2;
+    }
     // allocations
     gmg_status s;
     LevelHost &l0 = h->lv[0];
@@ -1848,7 +1887,7 @@ const char *gmg_kernel_class_name(int32_t c) {
                                              "cheb_first",     "cheb_step", "cheb_step_prev", "cheb_step_dot",
                                              "level_residual", "prolong",   "persistent",     "coarse_solve",
                                              "face_gradient",  "restrict",  "update_xp",      "cheb_pre2",
-                                             "cheb_post2"};
+                                             "cheb_post2",     "pre2_res"};
     return (c >= 0 && c < GMG_K_COUNT) ? names[c] : "unknown";
 }
 

@@ -1002,6 +1002,255 @@ __global__ __launch_bounds__(TX * ROWS) void k_post2_rh(Lev<V, K> L, Tiling t, c
     }
 }
 
+// Pre-smoothing by a degree-2 Chebyshev polynomial from x0 = 0 and the
+// residual that follows it, in one sweep (7-point link levels):
+//   x1 = c0 D^-1 b,   x2 = x1 + c1 x1 + c2 D^-1 (b - A x1),   r = b - A x2,
+// with the arithmetic of k_cheb_pre2 (x1 from the stored D^-1, x2's diagonal
+// from the links) and of k_residual_zr (r reduced along z on the fly: for each
+// coarse plane K of the chunk, s(i,j,K) = r(2K-1)/4 + r(2K)/2 + r(2K+1)/4), so
+// x2 and s are the same to the bit.  x1 never goes to memory and x2 is only
+// written, never read back.  A workgroup owns a 64 x ROWS tile (one vertex per
+// thread, one tile row per wave) and marches its z-chunk (even length, first
+// plane odd, one residual plane beyond its end as in k_residual_zr) in phases
+// m = k0-1 .. kend+1, one barrier each.  In phase m it
+//   * computes x2 of plane m at its own vertex, and on the last waves on a
+//     one-point ring around the tile (recomputed by the neighbouring tiles),
+//     from x1 of planes m-1 .. m+1,
+//   * computes r of plane m-1 at its own vertex from x2 of planes m-2 .. m
+//     and adds it to the z-sum,
+//   * stages x1 of plane m+2 (tile and a two-point ring; pointwise from b and
+//     D^-1).
+// x1 and x2 live in four-plane LDS ring buffers (slot = plane - k0 + 1 mod 4),
+// the own vertex's b in a four-plane register ring; the links and b of the
+// next plane and b, D^-1 two planes up are loaded a phase ahead.  The phase
+// body is unrolled four times so that every slot is named at compile time;
+// loads go through one buffer resource per array and chunk.  x2 planes k0-1,
+// k1 and k1+1 belong to the neighbouring chunks and are recomputed, not
+// stored.  One read of b, D^-1 and the links and one write of x2 and the
+// z-sums replace the two sweeps' reads of b (twice), D^-1, the links (twice)
+// and x2 and the write of x2.
+template <typename V, typename K, int ROWS>
+__global__ __launch_bounds__(TX * ROWS) void k_pre2_res(Lev<V, K> L, Tiling t, const V *__restrict__ b,
+                                                      V *__restrict__ out, V *__restrict__ zs, V c0, V c1, V c2,
+                                                      const int *__restrict__ skip) {
+    constexpr int W = TX, H = ROWS, NTH = TX * ROWS;
+    constexpr int XW = W + 4, YW = W + 2;       // row lengths of the x1 and x2 tiles
+    constexpr int HALO1 = 4 * XW + 4 * H;       // two-point ring of the x1 tile
+    constexpr int RING = 2 * YW + 2 * H;        // one-point ring of the x2 tile
+    constexpr int RING0 = NTH - RING;           // first thread of the ring
+    static_assert(HALO1 <= NTH && RING <= NTH, "one pass per ring");
+    constexpr uint32_t SV = sizeof(V), SK = sizeof(K);
+    __shared__ V sx1[4][H + 4][XW];  // x1 by plane slot, tile at [2, H+1] x [2, W+1]
+    __shared__ V sx2[4][H + 2][YW];  // x2 by plane slot, tile at [1, H] x [1, W]
+    if (skip && *skip) return;
+    int tx, ty, cz;
+    tile_of(blockIdx.x, t, tx, ty, cz);
+    const int lx = (int)(threadIdx.x & (W - 1)), ly = (int)(threadIdx.x >> 6);
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int i0 = tx * W, j0 = 1 + ty * H;  // grid position of tile point (0, 0)
+    const int i = i0 + lx, j = j0 + ly;
+    const int n = L.n, pitch = L.pitch;
+    const long long plane = L.plane;
+    const int k0 = 1 + cz * t.zchunk, k1 = min(k0 + t.zchunk, n - 1);
+    if (k0 >= k1) return;  // uniform over the workgroup
+    const int kend = min(k1, n - 2);  // last residual plane (odd)
+    const int np = kend - k0 + 3;     // phases: m = k0-1 .. kend+1
+    auto in_xy = [n](int a, int c) { return (unsigned)a < (unsigned)n && (unsigned)c < (unsigned)n; };
+    auto inner_xy = [n](int a, int c) { return a >= 1 && a <= n - 2 && c >= 1 && c <= n - 2; };
+    const bool own_inner = inner_xy(i, j);
+    const uint32_t own = (uint32_t)(j * pitch + i);
+    const uint32_t ovx = in_xy(i, j) ? own * SV : kOutside;  // own b, D^-1 for x1 (0 outside the grid)
+    const uint32_t ok = own_inner ? own * SK : kOutside;     // own links
+    const uint32_t ov = own_inner ? own * SV : kOutside;     // own x2, z-sums
+    // x1 ring slot of this thread (threads 0 .. HALO1-1)
+    const int h = (int)threadIdx.x;
+    int hy = 0, hx = 0;
+    if (h < 4 * XW) {
+        const int r = h / XW;
+        hy = r < 2 ? r : r + H;
+        hx = h % XW;
+    } else {
+        const int r = h - 4 * XW;
+        hy = 2 + r / 4;
+        hx = (r & 3) < 2 ? (r & 3) : (r & 3) + W;
+    }
+    const bool hal = h < HALO1;
+    const uint32_t ohal =
+        (hal && in_xy(i0 - 2 + hx, j0 - 2 + hy)) ? (uint32_t)((j0 - 2 + hy) * pitch + (i0 - 2 + hx)) * SV : kOutside;
+    // x2 ring slot (threads RING0 .. NTH-1)
+    const int g = h - RING0;
+    int gy = 1, gx = 1;  // a valid slot for threads outside the ring
+    if (g < 0) {
+    } else if (g < 2 * YW) {
+        gy = g < YW ? 0 : H + 1;
+        gx = g % YW;
+    } else {
+        const int q = g - 2 * YW;
+        gy = 1 + q / 2;
+        gx = (q & 1) ? W + 1 : 0;
+    }
+    const bool rng = g >= 0;
+    const bool rng_inner = rng && inner_xy(i0 - 1 + gx, j0 - 1 + gy);
+    const uint32_t rpt = (uint32_t)((j0 - 1 + gy) * pitch + (i0 - 1 + gx));
+    const uint32_t rk = rng_inner ? rpt * SK : kOutside, rv = rng_inner ? rpt * SV : kOutside;
+    const bool ring_wave = wave >= RING0 / 64;  // uniform: this wave holds ring threads
+
+    // One resource per array for the chunk, based at plane k0-2; plane m at
+    // the scalar offset (m - k0 + 2) * plane bytes
+    const long long mb = (long long)(k0 - 2) * plane;
+    constexpr uint32_t kAll = 0x7fffffffu;
+    const Rsrc rb = rsrc(b + mb, kAll), rdv = rsrc(L.dinv + mb, kAll), rout = rsrc(out + mb, kAll);
+    const Rsrc rkx = rsrc(L.kx + (mb - 1), kAll), rky = rsrc(L.ky + (mb - pitch), kAll), rkz = rsrc(L.kz + mb, kAll);
+    const uint32_t pbv = (uint32_t)plane * SV, pbk = (uint32_t)plane * SK;
+    auto uni = [](uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); };
+    auto pl = [&](int m) { return uni((uint32_t)(m - k0 + 2)); };
+    // x1 of plane m at in-plane offset off (0 outside the grid or on planes past it)
+    struct BD {
+        V bv, dv;
+    };
+    auto load_bd = [&](int m, uint32_t off) -> BD {
+        BD r{V(0), V(0)};
+        if (m >= 0 && m < n) {
+            r.bv = Buf<V>::template ld<kNT>(rb, off, pl(m) * pbv);
+            r.dv = Buf<V>::template ld<kNT>(rdv, off, pl(m) * pbv);
+        }
+        return r;
+    };
+    struct Raw {  // a vertex's links (without the one below) at one plane, as stored
+        K kw, ke, ks, kn, kt;
+    };
+    auto load_raw = [&](int m, uint32_t okk, Raw &r) {
+        const uint32_t sk = pl(m) * pbk;
+        r.kw = Buf<K>::ld(rkx, okk, sk);
+        r.ke = Buf<K>::template ld<kNT>(rkx, okk + SK, sk);
+        r.ks = Buf<K>::ld(rky, okk, sk);
+        r.kn = Buf<K>::ld(rky, okk + (uint32_t)pitch * SK, sk);
+        r.kt = Buf<K>::template ld<kNT>(rkz, okk, sk);
+    };
+    struct Lk {  // widened, with the link below and the diagonal
+        V kw, ke, ks, kn, kb, kt, d;
+    };
+    auto widen = [&](const Raw &r, V kb, Lk &w) {
+        w.kw = kval(r.kw);
+        w.ke = kval(r.ke);
+        w.ks = kval(r.ks);
+        w.kn = kval(r.kn);
+        w.kb = kb;
+        w.kt = kval(r.kt);
+        w.d = diag7(w.kw, w.ke, w.ks, w.kn, w.kb, w.kt, L.s);
+    };
+
+    // plane-indexed state: x1, x2 of plane m in LDS slot (m - k0 + 1) & 3, the
+    // own b of plane m in bq[(m - k0 + 1) & 3], links in lk[(m - k0 + 1) & 1]
+    V bq[4];
+    Lk lk[2];
+    V rkt[2];          // ring vertex: its upper z-link, widened
+    Raw ro, rr;        // own / ring raw links of the next plane
+    V rbv = V(0);      // ring vertex: b of the next plane
+    BD xp, hp;         // b, D^-1 of the plane to stage next (own, x1 ring slot)
+    V acc = V(0);      // z-sum of the open coarse plane
+
+    // prologue: x1 of planes k0-2 .. k0 (own; ring from k0-1), b, D^-1 of
+    // plane k0+1, the links of plane k0-1 (own) and k0 (ring)
+    {
+        const BD a0 = load_bd(k0 - 2, ovx), a1 = load_bd(k0 - 1, ovx), a2 = load_bd(k0, ovx);
+        const BD h1 = load_bd(k0 - 1, ohal), h2 = load_bd(k0, ohal);
+        sx1[3][ly + 2][lx + 2] = cheb_first_val(a0.bv, a0.dv, c0);
+        sx1[0][ly + 2][lx + 2] = cheb_first_val(a1.bv, a1.dv, c0);
+        sx1[1][ly + 2][lx + 2] = cheb_first_val(a2.bv, a2.dv, c0);
+        if (hal) {
+            sx1[0][hy][hx] = cheb_first_val(h1.bv, h1.dv, c0);
+            sx1[1][hy][hx] = cheb_first_val(h2.bv, h2.dv, c0);
+        }
+        bq[0] = a1.bv;
+        bq[1] = a2.bv;
+    }
+    xp = load_bd(k0 + 1, ovx);
+    hp = load_bd(k0 + 1, ohal);
+    load_raw(k0 - 1, ok, ro);
+    lk[1].kt = (k0 - 2 >= 0) ? kval(Buf<K>::ld(rkz, ok, 0)) : V(0);
+    rkt[0] = kval(Buf<K>::ld(rkz, rk, pbk));
+    load_raw(k0, rk, rr);
+    rbv = Buf<V>::template ld<kNT>(rb, rv, pl(k0) * pbv);
+    __syncthreads();
+
+    auto phase = [&](auto QQ, int p) __attribute__((always_inline)) -> bool {
+        constexpr int Q = decltype(QQ)::value;
+        constexpr int P = Q & 1, QB = (Q + 3) & 3, QT = (Q + 1) & 3, QBB = (Q + 2) & 3;
+        const int m = k0 - 1 + p;
+        const bool mz = m >= 1 && m <= n - 2;
+        // x2 of plane m at the own vertex
+        Lk &cw = lk[P];
+        widen(ro, lk[P ^ 1].kt, cw);
+        V x2m;
+        {
+            const V(*t1)[XW] = sx1[Q];
+            const V xc = t1[ly + 2][lx + 2];
+            const V ax = apply7(xc, t1[ly + 2][lx + 1], t1[ly + 2][lx + 3], t1[ly + 1][lx + 2], t1[ly + 3][lx + 2],
+                                sx1[QB][ly + 2][lx + 2], sx1[QT][ly + 2][lx + 2], cw.kw, cw.ke, cw.ks, cw.kn, cw.kb,
+                                cw.kt, L.s);
+            const V v = cheb_step_val(xc, xc, bq[Q], ax, cw.d, c1, c2);
+            x2m = (own_inner && mz) ? v : V(0);
+        }
+        if (p + 1 < np) load_raw(m + 1, ok, ro);
+        sx2[Q][ly + 1][lx + 1] = x2m;
+        if (m >= k0 && m < k1) Buf<V>::template st<kNT>(x2m, rout, ov, pl(m) * pbv);
+        // x2 of plane m on the ring (planes k0 .. kend: the in-plane neighbours of the residual)
+        if (p >= 1 && p + 1 < np && ring_wave) {
+            Lk w;
+            widen(rr, rkt[P ^ 1], w);
+            rkt[P] = w.kt;
+            const V(*t1)[XW] = sx1[Q];
+            const int ry = gy + 1, rx = gx + 1;
+            const V xc = t1[ry][rx];
+            const V ax = apply7(xc, t1[ry][rx - 1], t1[ry][rx + 1], t1[ry - 1][rx], t1[ry + 1][rx], sx1[QB][ry][rx],
+                                sx1[QT][ry][rx], w.kw, w.ke, w.ks, w.kn, w.kb, w.kt, L.s);
+            const V v = cheb_step_val(xc, xc, rbv, ax, w.d, c1, c2);
+            if (rng) sx2[Q][gy][gx] = rng_inner ? v : V(0);
+            if (p + 2 < np) {
+                load_raw(m + 1, rk, rr);
+                rbv = Buf<V>::template ld<kNT>(rb, rv, pl(m + 1) * pbv);
+            }
+        }
+        // r of plane m-1 at the own vertex, into the z-sum
+        if (p >= 2) {
+            const int k = m - 1;
+            const Lk &pw = lk[P ^ 1];
+            const V(*t2)[YW] = sx2[QB];
+            const V xc = t2[ly + 1][lx + 1];
+            const V r = bq[QB] - apply7(xc, t2[ly + 1][lx], t2[ly + 1][lx + 2], t2[ly][lx + 1], t2[ly + 2][lx + 1],
+                                        sx2[QBB][ly + 1][lx + 1], x2m, pw.kw, pw.ke, pw.ks, pw.kn, pw.kb, pw.kt, L.s);
+            if (k & 1) {
+                if (k > k0)  // closes coarse plane (k-1)/2
+                    Buf<V>::template st<kNT>(fmaT(V(0.25), r, acc), rsrc(zs + (long long)((k - 1) >> 1) * plane, kAll),
+                                             ov, 0);
+                acc = fmaT(V(0.25), r, V(0));  // opens coarse plane (k+1)/2
+            } else {
+                acc = fmaT(V(0.5), r, acc);
+            }
+        }
+        // x1 of plane m+2 into LDS (own b kept for x2 and r), b, D^-1 of plane m+3
+        if (p + 2 <= np) {
+            V(*t1)[XW] = sx1[QBB];
+            t1[ly + 2][lx + 2] = cheb_first_val(xp.bv, xp.dv, c0);
+            if (hal) t1[hy][hx] = cheb_first_val(hp.bv, hp.dv, c0);
+            bq[QBB] = xp.bv;
+        }
+        if (p + 3 <= np) {
+            xp = load_bd(m + 3, ovx);
+            hp = load_bd(m + 3, ohal);
+        }
+        __syncthreads();
+        return p + 1 == np;
+    };
+    for (int p = 0;; p += 4) {
+        if (phase(std::integral_constant<int, 0>{}, p)) break;
+        if (phase(std::integral_constant<int, 1>{}, p + 1)) break;
+        if (phase(std::integral_constant<int, 2>{}, p + 2)) break;
+        if (phase(std::integral_constant<int, 3>{}, p + 3)) break;
+    }
+}
+
 // ---------------------------------------------------------------- transfer operators
 // Full-weighting restriction b_c = R r, weights (1/4, 1/2, 1/4) per axis,
 // summed in one fixed order on every path: z first (the three fine planes of

@@ -379,7 +379,7 @@ class Solver:
 
 KERNEL_CLASSES = ["apply_dot", "residual", "update_r", "update_p", "cheb_first", "cheb_step", "cheb_step_prev",
                   "cheb_step_dot", "level_residual", "prolong", "persistent", "coarse_solve", "face_gradient",
-                  "restrict", "update_xp", "cheb_pre2", "cheb_post2"]
+                  "restrict", "update_xp", "cheb_pre2", "cheb_post2", "pre2_res"]
 
 
 class Profile:

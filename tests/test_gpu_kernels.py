@@ -144,6 +144,32 @@ def test_mixed_level_operations(n, levels):
         assert rel_max(to_np(s.residual_restrict(l, to_gpu(b), to_gpu(x0))), ref) <= 2e-6
 
 
+@pytest.mark.parametrize("n,levels", [(17, 4), (33, 5), (81, 5), (161, 6), (257, 5)])
+def test_pre_smoothing_and_residual_one_sweep_bitwise(n, levels, monkeypatch):
+    """Pre-smoothing and the residual's z-sums in one sweep (x1 and x2 kept in
+    LDS; the FP64 path) give the V-cycle of the separate sweeps to the bit,
+    with and without agglomerated coarse levels, and the same solve."""
+    precision = "fp64"
+    k = inputs.lognormal_k(n, 9, width=3.0)
+    kg = [to_gpu(a) for a in k]
+    for sw in (0, 9):
+        say(f"  pre-smoothing + residual n={n} levels={levels} {precision} switch={sw}")
+        sf = gmg.Solver(*kg, levels=levels, precision=precision, switch_n=sw)
+        monkeypatch.setenv("GMG_PRE_FUSED", "0")
+        su = gmg.Solver(*kg, levels=levels, precision=precision, switch_n=sw)
+        monkeypatch.delenv("GMG_PRE_FUSED")
+        r = to_gpu(rand_vec(n, 15))
+        zf, zu = to_np(sf.vcycle(r)), to_np(su.vcycle(r))
+        say(f"    V-cycle bitwise {np.array_equal(zf, zu)}")
+        np.testing.assert_array_equal(zf, zu)
+        f = to_gpu(inputs.uniform_rhs(n, 16))
+        xf, i_f = sf.solve(f, rtol=1e-10)
+        xu, i_u = su.solve(f, rtol=1e-10)
+        assert i_f["iterations"] == i_u["iterations"] and torch.equal(xf, xu)
+        sf.close()
+        su.close()
+
+
 def test_bad_coefficients_after_set_are_reported_by_the_next_solve():
     """gmg_set_coefficients enqueues its checks without waiting; the next solve
     (and every one after it) returns GMG_ERR_COEFF until valid coefficients

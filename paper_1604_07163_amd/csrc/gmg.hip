@@ -628,7 +628,7 @@ gmg_status pre_residual_restrict(gmg_handle *h, int l, const int *skip) {
     const ChebCoef<V> &cc = cheb<V>(h, l);
     {
         Prof pf(h, GMG_K_PRE2_RES, l == 0);
-        constexpr int rows = sizeof(V) == 4 ? gmg::TY_POST32 : gmg::TY_POST64;
+        constexpr int rows = gmg::TY_PRE_RES;
         gmg::k_pre2_res<V, K, rows><<<f.tilf.nblocks, gmg::TX * rows, 0, h->stream>>>(
             view<V, K>(f), f.tilf, (const V *)f.b, (V *)f.x, (V *)f.t1, cc.cfirst, cc.c1[1], cc.c2[1], skip);
         LAUNCHCHK();
@@ -1341,10 +1341,10 @@ gmg_status build(gmg_handle *h, const double *kx, const double *ky, const double
         lh.til2 = make_tiling(n, t64, gmg::TX2);
         lh.tilp = make_tiling(n, env_int("GMG_TARGET_WGS_V", 1 << 20), gmg::TX, gmg::TY_PRE);
         lh.tilr = even_chunks(lh.til, n);
-        // pre-smoothing + residual in one sweep (FP64 only): 64 x 16 tiles and
-        // 64-plane chunks at 513^3 (1.97 ms; 32-plane 2.04 ms; 64 x 8 tiles with
-        // 64 / 32 / 16 / 8-plane chunks 2.25 / 2.28 / 2.40 / 2.68 ms)
-        lh.tilf = even_chunks(chunk_tiling(n, env_int("GMG_PRE_CHUNK", 64), gmg::TX, mx ? gmg::TY_POST32 : gmg::TY_POST64), n);
+        // pre-smoothing + residual in one sweep: 64 x 16 tiles and 64-plane chunks
+        // (513^3 FP64 1.97 ms, 32-plane 2.04 ms, 64 x 8 tiles 2.25 ms; FP32 0.85 ms,
+        // 16-plane 0.94 ms, 64 x 8 tiles 1.15 ms)
+        lh.tilf = even_chunks(chunk_tiling(n, env_int("GMG_PRE_CHUNK", 64), gmg::TX, gmg::TY_PRE_RES), n);
         // one-sweep post-smoothing (measured at 513^3): FP32 16-plane chunks
         // (18-plane chunks 2 % faster than 32-plane ones and than 9-plane
         // ones); FP64 2048 workgroups (64-plane chunks; 32 measured the same)
@@ -1378,14 +1378,13 @@ gmg_status build(gmg_handle *h, const double *kx, const double *ky, const double
     for (int l = 0; l < h->s_persist; ++l)
         h->lv[l].post1 = (o.post_fused == 1 || o.post_fused == 2) && !h->lv[l].g27 && o.cheb_degree == 2;
     {
-        // pre-smoothing and residual in one sweep on the FP64 grid levels (at 513^3
-        // 2.25 ms against 1.38 + 1.31 ms for the two sweeps; in FP32/BF16 the one
-        // sweep measured 1.15 ms against 0.56 + 0.46 ms, so MIXED keeps two);
-        // GMG_PRE_FUSED=0 selects the two sweeps in FP64 too
+        // pre-smoothing and residual in one sweep on the grid levels (at 513^3
+        // FP64 1.97 ms against 1.38 + 1.31 ms for the two sweeps, FP32/BF16 0.85 ms
+        // against 0.56 + 0.46 ms); GMG_PRE_FUSED=0 selects the two sweeps
         const char *e = getenv("GMG_PRE_FUSED");
         const bool pre_on = !(e && e[0] == '0');
         for (int l = 0; l < h->s_persist; ++l)
-            h->lv[l].pre1 = pre_on && !mx && !h->lv[l].g27 && o.cheb_degree == 2;
+            h->lv[l].pre1 = pre_on && !h->lv[l].g27 && o.cheb_degree == 2;
     }
     // allocations
     gmg_status s;

@@ -34,6 +34,7 @@ constexpr int TY_PRE = 2 * TY;  // rows per tile of the two-rows-per-thread pre-
 // at 513^3: FP32 fastest with 8, FP64 with 16)
 constexpr int TY_POST32 = 8;
 constexpr int TY_POST64 = 16;
+constexpr int TY_PRE_RES = 16;  // rows per tile of the one-sweep pre-smoothing + residual kernel
 constexpr int NT_FLAT = 256;    // threads per workgroup of the flat vector kernels
 constexpr int NB_FLAT = 2048;   // workgroups of the flat vector kernels (fixed => deterministic sums)
 constexpr int NT_PERSIST = 1024;

@@ -145,11 +145,11 @@ def test_mixed_level_operations(n, levels):
 
 
 @pytest.mark.parametrize("n,levels", [(17, 4), (33, 5), (81, 5), (161, 6), (257, 5)])
-def test_pre_smoothing_and_residual_one_sweep_bitwise(n, levels, monkeypatch):
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_pre_smoothing_and_residual_one_sweep_bitwise(n, levels, precision, monkeypatch):
     """Pre-smoothing and the residual's z-sums in one sweep (x1 and x2 kept in
-    LDS; the FP64 path) give the V-cycle of the separate sweeps to the bit,
-    with and without agglomerated coarse levels, and the same solve."""
-    precision = "fp64"
+    LDS) give the V-cycle of the separate sweeps to the bit, with and without
+    agglomerated coarse levels, and the same solve."""
     k = inputs.lognormal_k(n, 9, width=3.0)
     kg = [to_gpu(a) for a in k]
     for sw in (0, 9):

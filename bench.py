@@ -435,6 +435,7 @@ CLASS_KERNELS = {
     "cheb_step": "k_cheb_step<float, bf16, 0, false>",
     "cheb_step_dot": "k_cheb_step<float, bf16, 2, true>",
     "cheb_post2": "k_post2<float, bf16, 1, 8>",
+    "pre2_res": "k_pre2_res<float, bf16, 16>",
     "level_residual": "k_residual_zr<float, bf16>",
     "restrict": "k_restrict_xy<float>",
     "prolong": "k_prolong<float>",

@@ -1022,8 +1022,9 @@ __global__ __launch_bounds__(TX * ROWS) void k_post2_rh(Lev<V, K> L, Tiling t, c
 //   * stages x1 of plane m+2 (tile and a two-point ring; pointwise from b and
 //     D^-1).
 // x1 and x2 live in four-plane LDS ring buffers (slot = plane - k0 + 1 mod 4),
-// the own vertex's b in a four-plane register ring; the links and b of the
-// next plane and b, D^-1 two planes up are loaded a phase ahead.  The phase
+// the own vertex's b in a four-plane register ring; the links of the next
+// plane (and the ring vertex's b) and b, D^-1 of the plane staged next are
+// loaded a phase before their use.  The phase
 // body is unrolled four times so that every slot is named at compile time;
 // loads go through one buffer resource per array and chunk.  x2 planes k0-1,
 // k1 and k1+1 belong to the neighbouring chunks and are recomputed, not

@@ -479,29 +479,20 @@ gmg_status smooth_grid(gmg_handle *h, int l, bool from_zero, const double *r64_c
         cur = 1;
         prev = -1;
     } else if (lh.post1) {
-        // both steps in one sweep, x0 in x, the result in t1 (the LDS-history
-        // kernel in FP32, the register-history one in FP64: measured faster)
+        // both steps in one sweep, x0 in x, the result in t1
         Prof pf(h, GMG_K_CHEB_POST2, fin);
-        constexpr int rows = sizeof(V) == 4 ? gmg::TY_POST32 : gmg::TY_POST64;
+        constexpr int rows = gmg::TY_POST;
         const dim3 gq(lh.tilq.nblocks), bq(gmg::TX * rows);
         const V c0 = cc.cfirst, c1 = cc.c1[1], c2 = cc.c2[1];
-        if constexpr (sizeof(V) == 4) {
-            if (dot_r64 && dot_q64)
-                gmg::k_post2<V, K, 2, rows><<<gq, bq, 0, h->stream>>>(L, lh.tilq, b, bufs[0], bufs[1], c0, c1, c2,
-                                                                       dot_r64, h->partial, skip, dot_q64);
-            else if (dot_r64)
-                gmg::k_post2<V, K, 1, rows><<<gq, bq, 0, h->stream>>>(L, lh.tilq, b, bufs[0], bufs[1], c0, c1, c2,
-                                                                       dot_r64, h->partial, skip);
-            else
-                gmg::k_post2<V, K, 0, rows><<<gq, bq, 0, h->stream>>>(L, lh.tilq, b, bufs[0], bufs[1], c0, c1, c2,
-                                                                       nullptr, nullptr, skip);
-        } else if (dot_r64) {
-            gmg::k_post2_rh<V, K, true, rows><<<gq, bq, 0, h->stream>>>(L, lh.tilq, b, bufs[0], bufs[1], c0, c1, c2,
-                                                                         dot_r64, h->partial, skip, dot_q64);
-        } else {
-            gmg::k_post2_rh<V, K, false, rows><<<gq, bq, 0, h->stream>>>(L, lh.tilq, b, bufs[0], bufs[1], c0, c1, c2,
-                                                                          nullptr, nullptr, skip);
-        }
+        if (dot_r64 && dot_q64)
+            gmg::k_post2<V, K, 2, rows><<<gq, bq, 0, h->stream>>>(L, lh.tilq, b, bufs[0], bufs[1], c0, c1, c2,
+                                                                   dot_r64, h->partial, skip, dot_q64);
+        else if (dot_r64)
+            gmg::k_post2<V, K, 1, rows><<<gq, bq, 0, h->stream>>>(L, lh.tilq, b, bufs[0], bufs[1], c0, c1, c2,
+                                                                   dot_r64, h->partial, skip);
+        else
+            gmg::k_post2<V, K, 0, rows><<<gq, bq, 0, h->stream>>>(L, lh.tilq, b, bufs[0], bufs[1], c0, c1, c2,
+                                                                   nullptr, nullptr, skip);
         if (dot_r64 && nparts) *nparts = lh.tilq.nblocks;
         LAUNCHCHK();
         return GMG_OK;
@@ -1342,14 +1333,13 @@ gmg_status build(gmg_handle *h, const double *kx, const double *ky, const double
         lh.tilp = make_tiling(n, env_int("GMG_TARGET_WGS_V", 1 << 20), gmg::TX, gmg::TY_PRE);
         lh.tilr = even_chunks(lh.til, n);
         // pre-smoothing + residual in one sweep: 64 x 16 tiles and 64-plane chunks
-        // (513^3 FP64 1.97 ms, 32-plane 2.04 ms, 64 x 8 tiles 2.25 ms; FP32 0.85 ms,
-        // 16-plane 0.94 ms, 64 x 8 tiles 1.15 ms)
+        // (513^3 FP64 1.58 ms, 32-plane 1.63 ms, 64 x 8 tiles 1.64 ms; FP32
+        // 0.67 ms, 32-plane 0.70 ms, 64 x 8 tiles 0.75 ms)
         lh.tilf = even_chunks(chunk_tiling(n, env_int("GMG_PRE_CHUNK", 64), gmg::TX, gmg::TY_PRE_RES), n);
-        // one-sweep post-smoothing (measured at 513^3): FP32 16-plane chunks
-        // (18-plane chunks 2 % faster than 32-plane ones and than 9-plane
-        // ones); FP64 2048 workgroups (64-plane chunks; 32 measured the same)
-        lh.tilq = mx ? chunk_tiling(n, env_int("GMG_POST_CHUNK", 16), gmg::TX, gmg::TY_POST32)
-                     : make_tiling(n, env_int("GMG_TARGET_WGS_POST", 2048), gmg::TX, gmg::TY_POST64);
+        // one-sweep post-smoothing: 64 x 8 tiles, 32-plane chunks (513^3 FP32
+        // 0.80 ms, 16-plane 0.81 ms, 8-plane 0.87 ms; FP64 1.60 ms, 16-plane
+        // 1.62 ms, 64-plane 1.60 ms)
+        lh.tilq = chunk_tiling(n, env_int("GMG_POST_CHUNK", 32), gmg::TX, gmg::TY_POST);
         lh.rows = make_rows(n, lh.pitch, lh.plane);
         lh.g27 = o.galerkin > 0 && l >= o.galerkin;
         n = (n - 1) / 2 + 1;

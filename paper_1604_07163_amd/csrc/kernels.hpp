@@ -30,10 +30,7 @@ constexpr int TY = 4;           // rows per tile
 constexpr int NT = TX * TY;     // threads per stencil workgroup
 constexpr int TX2 = 2 * TX;     // x extent of a tile of the two-points-per-lane apply
 constexpr int TY_PRE = 2 * TY;  // rows per tile of the two-rows-per-thread pre-smoothing kernel
-// rows per tile of the one-sweep post-smoothing kernel, FP32 and FP64 (measured
-// at 513^3: FP32 fastest with 8, FP64 with 16)
-constexpr int TY_POST32 = 8;
-constexpr int TY_POST64 = 16;
+constexpr int TY_POST = 8;      // rows per tile of the one-sweep post-smoothing kernel
 constexpr int TY_PRE_RES = 16;  // rows per tile of the one-sweep pre-smoothing + residual kernel
 constexpr int NT_FLAT = 256;    // threads per workgroup of the flat vector kernels
 constexpr int NB_FLAT = 2048;   // workgroups of the flat vector kernels (fixed => deterministic sums)
@@ -235,7 +232,13 @@ constexpr uint32_t kOutside = 0x80000000u;  // beyond every resource, also after
 __device__ __forceinline__ Rsrc rsrc(const void *base, uint32_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, kBufDword3);
 }
-constexpr int kNT = 2;  // cache-policy bits of a streaming (nontemporal) access
+// Cache-policy bits of a streaming (nontemporal) access.  Only for data no
+// other thread of the launch reads: L2 evicts such lines first, so a halo line
+// that a neighbouring tile reads a little later is fetched again.  Measured on
+// the one-sweep smoothers at 513^3: with the bit on their halo-bearing loads
+// (links, b, D^-1, x) they fetched 1.3-1.9x their algorithmic reads; without
+// it 1.1x, and ran 14-22 % faster.
+constexpr int kNT = 2;
 template <typename T>
 struct Buf;
 template <>
@@ -719,11 +722,11 @@ __global__ __launch_bounds__(TX * ROWS) void k_post2(Lev<V, K> L, Tiling t, cons
     auto load_raw = [&](int m, uint32_t okk, uint32_t ovv, Raw &r) {
         const uint32_t pl = uni((uint32_t)(m - k0 + 2)), sk = pl * pbk, sv = pl * pbv;
         r.kw = Buf<K>::ld(rkx, okk, sk);
-        r.ke = Buf<K>::template ld<kNT>(rkx, okk + SK, sk);
+        r.ke = Buf<K>::ld(rkx, okk + SK, sk);
         r.ks = Buf<K>::ld(rky, okk, sk);
         r.kn = Buf<K>::ld(rky, okk + (uint32_t)pitch * SK, sk);
-        r.kt = Buf<K>::template ld<kNT>(rkz, okk, sk);
-        r.bv = Buf<V>::template ld<kNT>(rb, ovv, sv);
+        r.kt = Buf<K>::ld(rkz, okk, sk);
+        r.bv = Buf<V>::ld(rb, ovv, sv);
     };
     struct Lk {  // the same widened, with the link below and the diagonal
         V kw, ke, ks, kn, kb, kt, bv, d;
@@ -849,160 +852,6 @@ __global__ __launch_bounds__(TX * ROWS) void k_post2(Lev<V, K> L, Tiling t, cons
     }
 }
 
-// The same one-sweep post-smoothing with the plane history in registers
-// (register-history form, used for FP64 levels): the thread keeps its x0 of
-// planes m-1, m and its x1 of planes m-2, m-1 in registers, x0 of a plane is
-// staged in LDS with a two-point ring and x1 with a one-point ring (two
-// buffers each, by plane parity), all loads of a plane issued at the start of
-// its phase.  Measured on MI355X at 513^3 in FP64 it is 7 % faster than the
-// LDS-history kernel above, whose eight-byte LDS traffic and larger register
-// count (one 1024-thread workgroup per CU either way) cost more than its
-// prefetch gains; in FP32/BF16 the LDS-history kernel is 7 % faster.
-// Arithmetic, results and argument meaning are those of k_post2.
-template <typename V, typename K, bool DOTR, int ROWS>
-__global__ __launch_bounds__(TX * ROWS) void k_post2_rh(Lev<V, K> L, Tiling t, const V *__restrict__ b,
-                                                   const V *__restrict__ x0, V *__restrict__ out, V c0, V c1, V c2,
-                                                   const double *__restrict__ r64, double *__restrict__ partial,
-                                                   const int *__restrict__ skip,
-                                                   const double *__restrict__ q64 = nullptr) {
-    constexpr int W = TX, H = ROWS, NTH = TX * ROWS;
-    constexpr int HALO0 = 4 * (W + 4) + 4 * H;  // two-point ring of the x0 tile
-    constexpr int RING = 2 * (W + 2) + 2 * H;   // one-point ring of the x1 tile
-    static_assert(HALO0 <= NTH && RING <= NTH, "one pass per ring");
-    __shared__ V sx0[2][H + 4][W + 4];  // x0 of a plane, 2-point ring (tile at [2, H+1] x [2, W+1]), by parity
-    __shared__ V sx1[2][H + 2][W + 2];  // x1 of a plane, 1-point ring (tile at [1, H] x [1, W]), by parity
-    if (skip && *skip) return;
-    int tx, ty, cz;
-    tile_of(blockIdx.x, t, tx, ty, cz);
-    const int lx = (int)(threadIdx.x & (W - 1)), ly = (int)(threadIdx.x >> 6);
-    const int i0 = tx * W, j0 = 1 + ty * H;  // grid position of tile point (0, 0)
-    const int i = i0 + lx, j = j0 + ly;
-    const int n = L.n, pitch = L.pitch;
-    const long long plane = L.plane;
-    const int k0 = 1 + cz * t.zchunk, k1 = min(k0 + t.zchunk, n - 1);
-    if (k0 >= k1) return;  // uniform over the workgroup
-    // Every staged value sits at an in-plane offset that is fixed per thread
-    // (its own vertex, its slot in the x0 ring, its slot in the x1 ring); only
-    // the plane index m, uniform over the workgroup, changes.
-    auto in_xy = [n](int a, int c) { return (unsigned)a < (unsigned)n && (unsigned)c < (unsigned)n; };
-    auto inner_xy = [n](int a, int c) { return a >= 1 && a <= n - 2 && c >= 1 && c <= n - 2; };
-    const bool own_xy = in_xy(i, j), own_inner = inner_xy(i, j);
-    const int own_off = j * pitch + i;
-    const int h = (int)threadIdx.x;
-    int hy = 0, hx = 0;
-    if (h < 4 * (W + 4)) {
-        const int r = h / (W + 4);
-        hy = r < 2 ? r : r + H;
-        hx = h % (W + 4);
-    } else {
-        const int r = h - 4 * (W + 4);
-        hy = 2 + r / 4;
-        hx = (r & 3) < 2 ? (r & 3) : (r & 3) + W;
-    }
-    const bool hal = h < HALO0, hal_xy = hal && in_xy(i0 - 2 + hx, j0 - 2 + hy);
-    const int hal_off = (j0 - 2 + hy) * pitch + (i0 - 2 + hx);
-    int gy = 0, gx = 0;
-    if (h < 2 * (W + 2)) {
-        gy = h < W + 2 ? 0 : H + 1;
-        gx = h % (W + 2);
-    } else {
-        const int q = h - 2 * (W + 2);
-        gy = 1 + q / 2;
-        gx = (q & 1) ? W + 1 : 0;
-    }
-    const bool rng = h < RING, rng_inner = rng && inner_xy(i0 - 1 + gx, j0 - 1 + gy);
-    const int rng_off = (j0 - 1 + gy) * pitch + (i0 - 1 + gx);
-    auto zin = [n](int m) { return (unsigned)m < (unsigned)n; };
-    auto zinner = [n](int m) { return m >= 1 && m <= n - 2; };
-    auto x0_at = [&](int m, bool xy, int off) -> V { return (xy && zin(m)) ? x0[(long long)m * plane + off] : V(0); };
-    // x1 of the interior vertex at in-plane offset off of plane m; its in-plane
-    // x0 neighbours are staged at sx0[m & 1][ry][rx] +- 1
-    struct Own {
-        V kw, ke, ks, kn, kb, kt, bv;
-    };
-    auto x1_at = [&](int m, int off, int ry, int rx, V xb, V xt, Own &w) -> V {
-        const long long q = (long long)m * plane + off;
-        w.kw = kval(L.kx[q - 1]);
-        w.ke = kval(L.kx[q]);
-        w.ks = kval(L.ky[q - pitch]);
-        w.kn = kval(L.ky[q]);
-        w.kb = kval(L.kz[q - plane]);
-        w.kt = kval(L.kz[q]);
-        w.bv = b[q];
-        const V(*t0)[W + 4] = sx0[m & 1];
-        const V xc = t0[ry][rx];
-        const V ax = apply7(xc, t0[ry][rx - 1], t0[ry][rx + 1], t0[ry - 1][rx], t0[ry + 1][rx], xb, xt, w.kw, w.ke,
-                            w.ks, w.kn, w.kb, w.kt, L.s);
-        const V d = diag7(w.kw, w.ke, w.ks, w.kn, w.kb, w.kt, L.s);
-        return cheb_step_val(xc, V(0), w.bv, ax, d, V(0), c0);
-    };
-    auto stage_x0 = [&](int m, V own) {
-        V(*t0)[W + 4] = sx0[m & 1];
-        t0[ly + 2][lx + 2] = own;
-        if (hal) t0[hy][hx] = x0_at(m, hal_xy, hal_off);
-    };
-    auto ring_x1 = [&](int m) {
-        if (rng) {
-            V v = V(0);
-            if (rng_inner && zinner(m)) {
-                Own w;
-                v = x1_at(m, rng_off, gy + 1, gx + 1, x0_at(m - 1, true, rng_off), x0_at(m + 1, true, rng_off), w);
-            }
-            sx1[m & 1][gy][gx] = v;
-        }
-    };
-    // Phase m (m = k0-1 .. k1), one barrier each: x1 of plane m (from m = k0
-    // on with its ring) from sx0[m & 1]; x2 of plane m-1 from sx1[(m-1) & 1];
-    // x0 of plane m+1 staged into the other sx0 buffer.
-    V xb0 = x0_at(k0 - 2, own_xy, own_off), xc0 = x0_at(k0 - 1, own_xy, own_off);  // the thread's x0 at m-1, m
-    V x1b = V(0), x1c = V(0);                                                        // its x1 at m-2, m-1
-    Own wc{}, wt{};
-    double dot = 0.0, dotq = 0.0;
-    stage_x0(k0 - 1, xc0);
-    __syncthreads();
-    for (int m = k0 - 1; m <= k1; ++m) {
-        const V xn0 = x0_at(m + 1, own_xy, own_off);
-        V x1t = V(0);
-        if (own_inner && zinner(m))
-            x1t = x1_at(m, own_off, ly + 2, lx + 2, xb0, xn0, wt);
-        else
-            wt = Own{V(0), V(0), V(0), V(0), V(0), V(0), V(0)};
-        if (m >= k0 && m < k1) {
-            sx1[m & 1][ly + 1][lx + 1] = x1t;
-            ring_x1(m);
-        }
-        const int k = m - 1;
-        if (k >= k0 && own_inner) {
-            const long long o = (long long)k * plane + own_off;
-            const V(*t1)[W + 2] = sx1[k & 1];
-            const V ax = apply7(x1c, t1[ly + 1][lx], t1[ly + 1][lx + 2], t1[ly][lx + 1], t1[ly + 2][lx + 1], x1b, x1t,
-                                wc.kw, wc.ke, wc.ks, wc.kn, wc.kb, wc.kt, L.s);
-            const V d = diag7(wc.kw, wc.ke, wc.ks, wc.kn, wc.kb, wc.kt, L.s);
-            const V v = cheb_step_val(x1c, x1c - xb0, wc.bv, ax, d, c1, c2);
-            stnt(v, &out[o]);
-            if (DOTR) {
-                dot = fmaT(ldnt(&r64[o]), (double)v, dot);
-                if (q64) dotq = fmaT(ldnt(&q64[o]), (double)v, dotq);
-            }
-        }
-        if (m < k1) stage_x0(m + 1, xn0);
-        __syncthreads();
-        x1b = x1c;
-        x1c = x1t;
-        xb0 = xc0;
-        xc0 = xn0;
-        wc = wt;
-    }
-    if (DOTR) {
-        const double sm = block_sum<NTH>(dot);
-        if (threadIdx.x == 0) partial[blockIdx.x] = sm;
-        if (q64) {
-            const double sq = block_sum<NTH>(dotq);
-            if (threadIdx.x == 0) partial[gridDim.x + blockIdx.x] = sq;
-        }
-    }
-}
-
 // Pre-smoothing by a degree-2 Chebyshev polynomial from x0 = 0 and the
 // residual that follows it, in one sweep (7-point link levels):
 //   x1 = c0 D^-1 b,   x2 = x1 + c1 x1 + c2 D^-1 (b - A x1),   r = b - A x2,
@@ -1113,8 +962,8 @@ __global__ __launch_bounds__(TX * ROWS) void k_pre2_res(Lev<V, K> L, Tiling t, c
     auto load_bd = [&](int m, uint32_t off) -> BD {
         BD r{V(0), V(0)};
         if (m >= 0 && m < n) {
-            r.bv = Buf<V>::template ld<kNT>(rb, off, pl(m) * pbv);
-            r.dv = Buf<V>::template ld<kNT>(rdv, off, pl(m) * pbv);
+            r.bv = Buf<V>::ld(rb, off, pl(m) * pbv);
+            r.dv = Buf<V>::ld(rdv, off, pl(m) * pbv);
         }
         return r;
     };
@@ -1124,10 +973,10 @@ __global__ __launch_bounds__(TX * ROWS) void k_pre2_res(Lev<V, K> L, Tiling t, c
     auto load_raw = [&](int m, uint32_t okk, Raw &r) {
         const uint32_t sk = pl(m) * pbk;
         r.kw = Buf<K>::ld(rkx, okk, sk);
-        r.ke = Buf<K>::template ld<kNT>(rkx, okk + SK, sk);
+        r.ke = Buf<K>::ld(rkx, okk + SK, sk);
         r.ks = Buf<K>::ld(rky, okk, sk);
         r.kn = Buf<K>::ld(rky, okk + (uint32_t)pitch * SK, sk);
-        r.kt = Buf<K>::template ld<kNT>(rkz, okk, sk);
+        r.kt = Buf<K>::ld(rkz, okk, sk);
     };
     struct Lk {  // widened, with the link below and the diagonal
         V kw, ke, ks, kn, kb, kt, d;
@@ -1173,7 +1022,7 @@ __global__ __launch_bounds__(TX * ROWS) void k_pre2_res(Lev<V, K> L, Tiling t, c
     lk[1].kt = (k0 - 2 >= 0) ? kval(Buf<K>::ld(rkz, ok, 0)) : V(0);
     rkt[0] = kval(Buf<K>::ld(rkz, rk, pbk));
     load_raw(k0, rk, rr);
-    rbv = Buf<V>::template ld<kNT>(rb, rv, pl(k0) * pbv);
+    rbv = Buf<V>::ld(rb, rv, pl(k0) * pbv);
     __syncthreads();
 
     auto phase = [&](auto QQ, int p) __attribute__((always_inline)) -> bool {
@@ -1211,7 +1060,7 @@ __global__ __launch_bounds__(TX * ROWS) void k_pre2_res(Lev<V, K> L, Tiling t, c
             if (rng) sx2[Q][gy][gx] = rng_inner ? v : V(0);
             if (p + 2 < np) {
                 load_raw(m + 1, rk, rr);
-                rbv = Buf<V>::template ld<kNT>(rb, rv, pl(m + 1) * pbv);
+                rbv = Buf<V>::ld(rb, rv, pl(m + 1) * pbv);
             }
         }
         // r of plane m-1 at the own vertex, into the z-sum

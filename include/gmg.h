@@ -38,9 +38,15 @@
  *      GMG_TARGET_WGS_V     workgroups targeted by the V-cycle stencil sweeps
  *                           (smoothing, residual; both precisions)
  *      GMG_TARGET_WGS_64    the same for the outer FP64 apply and true residual
- *      GMG_TARGET_WGS_POST  the same for the one-sweep post-smoother
  *    A target sets the z-chunk length of a launch (at least 8 planes where
  *    that still yields 1024 workgroups).
+ *      GMG_POST_CHUNK       z-chunk length of the one-sweep post-smoother (32)
+ *      GMG_PRE_CHUNK        z-chunk length of the one-sweep pre-smoothing and
+ *                           residual (64)
+ *    Both are shortened on small levels to keep 1024 workgroups.
+ *      GMG_PRE_FUSED=0      the separate pre-smoothing and residual sweeps in
+ *                           place of the one-sweep kernel (same results to the
+ *                           bit; for tests and measurements)
  */
 #ifndef GMG_H
 #define GMG_H

@@ -80,7 +80,7 @@ typedef enum { GMG_FP64 = 0, GMG_MIXED = 1 } gmg_precision;
 typedef enum { GMG_COARSE_ARITHMETIC = 0, GMG_COARSE_HARMONIC = 1 } gmg_coarse_rule;
 
 typedef struct {
-    int32_t n;              /* vertices per side; n >= 3 and (n-1) % 2^(levels-1) == 0 */
+    int32_t n;              /* vertices per side; n >= 3, n <= 5440 and (n-1) % 2^(levels-1) == 0 */
     int32_t levels;         /* >= 1; coarsest level has at most 4096 interior unknowns */
     int32_t cheb_degree;    /* Chebyshev steps per smoothing (pre and post), 1..8; default 2 */
     double cheb_lo;         /* Chebyshev interval of D^-1 A, default [0.25, 2.0] */

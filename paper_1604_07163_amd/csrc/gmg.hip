@@ -190,6 +190,12 @@ Tiling make_tiling(int n, int target, int width = gmg::TX, int rows = gmg::TY) {
 // A tiling with z-chunks of `chunk` planes, shortened (down to one plane)
 // where that would launch fewer than kMinWorkgroups workgroups.
 Tiling chunk_tiling(int n, int chunk, int width, int rows) {
+    // the one-sweep kernels address a chunk by 32-bit buffer offsets from its
+    // lowest halo plane: the chunk with its halo and look-ahead planes (at
+    // most zchunk + 7 planes of 8-byte elements, zchunk possibly made even)
+    // stays below 2^31 bytes (check_options rejects n where 1 plane cannot)
+    const long long plane_bytes = 8LL * n * round_up(n, 64);
+    chunk = (int)std::min<long long>(chunk, std::max(1LL, 0x7fffffffLL / plane_bytes - 8));
     Tiling t;
     t.tiles_x = (n - 2) / width + 1;
     t.tiles_y = (n - 2 + rows - 1) / rows;
@@ -1283,6 +1289,8 @@ gmg_status check_options(const gmg_options &o) {
     const int nc = (o.n - 1) / (1 << (o.levels - 1)) + 1;
     if (nc < 3 || (o.coarse_solver == 0 && (long long)(nc - 2) * (nc - 2) * (nc - 2) > gmg::MAX_COARSE))
         return GMG_ERR_DIMS;
+    // 32-bit in-chunk offsets of the one-sweep kernels (chunk_tiling)
+    if (9LL * 8 * o.n * round_up(o.n, 64) > 0x7fffffffLL) return GMG_ERR_DIMS;
 
     return GMG_OK;
 }

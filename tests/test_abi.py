@@ -52,6 +52,22 @@ def test_create_rejects_null_arguments_without_touching_the_device():
     assert not h.value
 
 
+def test_create_rejects_grids_beyond_the_32_bit_chunk_offsets():
+    """The one-sweep kernels address a z-chunk through 32-bit buffer offsets;
+    gmg_create refuses an n whose planes cannot fit that range (GMG_ERR_DIMS)
+    before it reads the coefficient pointers or touches the device."""
+    L = gmg.lib()
+    o = gmg.Options()
+    L.gmg_default_options(ctypes.byref(o), 5441)
+    o.levels = 7              # 5440 = 64 * 85
+    o.coarse_solver = 1       # inexact coarse CG: no limit on the coarsest level
+    o.switch_n = 0
+    dummy = ctypes.c_void_p(256)  # never dereferenced: the option check comes first
+    h = ctypes.c_void_p()
+    assert L.gmg_create(ctypes.byref(o), dummy, dummy, dummy, None, ctypes.byref(h)) == 2
+    assert not h.value
+
+
 def test_header_cites_no_missing_type():
     src = open(gmg.HEADER).read()
     for t in ("gmg_options", "gmg_info", "gmg_status", "gmg_handle"):

@@ -170,6 +170,38 @@ def test_pre_smoothing_and_residual_one_sweep_bitwise(n, levels, precision, monk
         su.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_one_sweep_kernels_independent_of_chunk_length(precision, monkeypatch):
+    """The one-sweep kernels recompute x1 (and x2) on the halo planes of each
+    z-chunk, so their results must not depend on where the chunks start: odd
+    and even post-smoothing chunks and short pre-smoothing chunks give the
+    default chunks' V-cycle to the bit, and the solve (whose r.z partial sums
+    are grouped by chunk) to FP64 rounding."""
+    n, levels = 257, 5
+    k = inputs.lognormal_k(n, 13, width=3.0)
+    kg = [to_gpu(a) for a in k]
+    r = to_gpu(rand_vec(n, 17))
+    f = to_gpu(inputs.uniform_rhs(n, 18))
+    s0 = gmg.Solver(*kg, levels=levels, precision=precision, switch_n=9)
+    z0 = to_np(s0.vcycle(r))
+    x0, i0 = s0.solve(f, rtol=1e-10)
+    x0 = to_np(x0)
+    s0.close()
+    for post, pre in ((5, 6), (7, 10), (13, 2)):
+        say(f"  chunks n={n} {precision} post={post} pre={pre}")
+        monkeypatch.setenv("GMG_POST_CHUNK", str(post))
+        monkeypatch.setenv("GMG_PRE_CHUNK", str(pre))
+        s = gmg.Solver(*kg, levels=levels, precision=precision, switch_n=9)
+        monkeypatch.delenv("GMG_POST_CHUNK")
+        monkeypatch.delenv("GMG_PRE_CHUNK")
+        np.testing.assert_array_equal(to_np(s.vcycle(r)), z0)
+        x, i = s.solve(f, rtol=1e-10)
+        d = rel_max(to_np(x), x0)
+        say(f"    V-cycle bitwise; solve its {i['iterations']} / {i0['iterations']}, max rel diff {d:.1e}")
+        assert i["iterations"] == i0["iterations"] and d <= 1e-12
+        s.close()
+
+
 def test_bad_coefficients_after_set_are_reported_by_the_next_solve():
     """gmg_set_coefficients enqueues its checks without waiting; the next solve
     (and every one after it) returns GMG_ERR_COEFF until valid coefficients

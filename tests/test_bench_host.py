@@ -101,6 +101,23 @@ def test_pmc_traffic_is_calibrated_by_the_copy(tmp_path, monkeypatch):
     assert bench.traffic_for("apply_dot", "test") is None
 
 
+def test_source_digest_ignores_comments_but_not_code(tmp_path, monkeypatch):
+    """The counter figures are tied to the code, not to its comments."""
+    import shutil
+    d = tmp_path / "paper_1604_07163_amd" / "csrc"
+    d.mkdir(parents=True)
+    for f in ("kernels.hpp", "gmg.hip"):
+        shutil.copy(os.path.join(ROOT, "paper_1604_07163_amd", "csrc", f), d / f)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    base = bench.source_digest()
+    k = d / "kernels.hpp"
+    src = k.read_text()
+    k.write_text(src.replace("namespace gmg {", "// a new remark\nnamespace gmg {  /* and\n another */", 1))
+    assert bench.source_digest() == base
+    k.write_text(src.replace("constexpr int kNT = 2;", "constexpr int kNT = 0;"))
+    assert bench.source_digest() != base
+
+
 def test_full_size_tests_use_the_benchmark_switch_level():
     import re
 

@@ -625,7 +625,10 @@ __global__ __launch_bounds__(NT) void k_cheb_step(Lev<V, K> L, Tiling t, const V
 // buffer resource per array and chunk, the plane chosen by the scalar offset,
 // each thread with a fixed byte offset: no vector address arithmetic; a
 // vertex outside the grid gets an offset beyond every resource and reads 0.
-// The diagonal of a vertex is formed once and serves both steps.  One read of
+// The loads the ring and halo share with neighbouring tiles use the plain
+// cache policy, so those tiles find the lines in L2; only r64 and q64 are
+// streamed nontemporal.  The diagonal of a vertex is formed once and serves
+// both steps.  One read of
 // x0, b and the links and one write of x2 replace the two sweeps' reads of x0
 // (twice), b and the links (twice) and the write and read of x1.  out must not
 // alias x0 (other tiles read x0 in their rings).  DOTR 1: partial[wg] =
@@ -875,7 +878,9 @@ __global__ __launch_bounds__(TX * ROWS) void k_post2(Lev<V, K> L, Tiling t, cons
 // plane (and the ring vertex's b) and b, D^-1 of the plane staged next are
 // loaded a phase before their use.  The phase
 // body is unrolled four times so that every slot is named at compile time;
-// loads go through one buffer resource per array and chunk.  x2 planes k0-1,
+// loads go through one buffer resource per array and chunk, with the plain
+// cache policy (neighbouring tiles re-read the ring and halo lines from L2).
+// x2 planes k0-1,
 // k1 and k1+1 belong to the neighbouring chunks and are recomputed, not
 // stored.  One read of b, D^-1 and the links and one write of x2 and the
 // z-sums replace the two sweeps' reads of b (twice), D^-1, the links (twice)

@@ -44,6 +44,8 @@
  *      GMG_PRE_CHUNK        z-chunk length of the one-sweep pre-smoothing and
  *                           residual (64)
  *    Both are shortened on small levels to keep 1024 workgroups.
+ *      GMG_APPLY_WIDTH=128  the outer apply in 128 x 4 tiles also on rows of
+ *                           384 points or more (default there: 512 x 1)
  *      GMG_PRE_FUSED=0      the separate pre-smoothing and residual sweeps in
  *                           place of the one-sweep kernel (same results to the
  *                           bit; for tests and measurements)

@@ -45,6 +45,7 @@ struct LevelHost {
     Tiling til{};    // V-cycle stencil kernels
     Tiling til64{};  // FP64 outer operator (residual)
     Tiling til2{};   // FP64 outer apply, two points per lane
+    int wx2 = 1;     // its waves along x (tiles of 128 wx2 x 4 / wx2 points)
     Tiling tilp{};   // pre-smoothing kernel, two rows per thread
     Tiling tilq{};   // one-sweep post-smoothing kernel
     Tiling tilr{};   // residual with z-reduction (even z-chunks)
@@ -169,14 +170,19 @@ constexpr int kMinWorkgroups = 1024;
 
 // width: x extent of a tile (TX, or TX2 for the two-points-per-lane apply);
 // rows: y extent (TY, or TY_PRE for the two-rows-per-thread pre-smoothing)
-Tiling make_tiling(int n, int target, int width = gmg::TX, int rows = gmg::TY) {
+// min_chunk: shortest z-chunk while kMinWorkgroups are launched anyway;
+// pad8: round the tile rows up to a multiple of 8 (empty tiles exit at once)
+// so that the XCD y-slab order of tile_of applies.
+Tiling make_tiling(int n, int target, int width = gmg::TX, int rows = gmg::TY, int min_chunk = kMinChunk,
+                   bool pad8 = false) {
     Tiling t;
     t.tiles_x = (n - 2) / width + 1;  // covers i = 0 .. n-2
     t.tiles_y = (n - 2 + rows - 1) / rows;
+    if (pad8) t.tiles_y = (t.tiles_y + 7) & ~7;
     const int planes = n - 2;
     const int tiles = t.tiles_x * t.tiles_y;
     int nch = (target + tiles - 1) / tiles;
-    if (nch > planes / kMinChunk) nch = planes / kMinChunk;
+    if (nch > planes / min_chunk) nch = planes / min_chunk;
     // small levels: too few workgroups to hide the latency of a long z-march,
     // so chunks shorten (down to one plane) until kMinWorkgroups are launched
     if ((long long)tiles * nch < kMinWorkgroups) nch = std::min(planes, (kMinWorkgroups + tiles - 1) / tiles);
@@ -807,9 +813,15 @@ gmg_status pcg_iteration(gmg_handle *h) {
     const bool mx = mixed(h);
     {
         Prof pf(h, GMG_K_APPLY_DOT, true);
-        if (mx)
+        if (mx && l0.wx2 == 4)
+            gmg::k_apply_x2<true, float, 4><<<l0.til2.nblocks, gmg::NT, 0, h->stream>>>(
+                view<double, double>(l0), l0.til2, h->P32, h->Q, h->partial, skip);
+        else if (mx)
             gmg::k_apply_x2<true, float><<<l0.til2.nblocks, gmg::NT, 0, h->stream>>>(
                 view<double, double>(l0), l0.til2, h->P32, h->Q, h->partial, skip);
+        else if (l0.wx2 == 4)
+            gmg::k_apply_x2<true, double, 4><<<l0.til2.nblocks, gmg::NT, 0, h->stream>>>(
+                view<double, double>(l0), l0.til2, h->P, h->Q, h->partial, skip);
         else
             gmg::k_apply_x2<true, double><<<l0.til2.nblocks, gmg::NT, 0, h->stream>>>(
                 view<double, double>(l0), l0.til2, h->P, h->Q, h->partial, skip);
@@ -1337,7 +1349,12 @@ gmg_status build(gmg_handle *h, const double *kx, const double *ky, const double
         const int t64 = env_int("GMG_TARGET_WGS_64", 1 << 20);
         lh.til = make_tiling(n, env_int("GMG_TARGET_WGS_V", 1 << 20));
         lh.til64 = make_tiling(n, t64);
-        lh.til2 = make_tiling(n, t64, gmg::TX2);
+        // outer apply: 512 x 1 tiles on rows of 384 points or more, with
+        // chunks of at least 4 planes (5 at 513^3: MIXED 872 us against 880 us
+        // for 128 x 4 tiles and 9-plane chunks, FP64 1027 against 1034 us;
+        // 3- to 8-plane chunks within 0.5 %), else 128 x 4 tiles
+        lh.wx2 = (n - 2 >= 384 && env_int("GMG_APPLY_WIDTH", 512) == 512) ? 4 : 1;
+        lh.til2 = lh.wx2 == 4 ? make_tiling(n, t64, 4 * gmg::TX2, 1, 4, true) : make_tiling(n, t64, gmg::TX2);
         lh.tilp = make_tiling(n, env_int("GMG_TARGET_WGS_V", 1 << 20), gmg::TX, gmg::TY_PRE);
         lh.tilr = even_chunks(lh.til, n);
         // pre-smoothing + residual in one sweep: 64 x 16 tiles and 64-plane chunks
@@ -1767,8 +1784,12 @@ gmg_status gmg_apply_outer_operator(gmg_handle *h, const double *x, double *y) {
     LevelHost &l0 = h->lv[0];
     double *u = h->X;  // free between solves (every solve re-initializes it)
     STCHK(in_vec<double>(h, l0, x, u));
-    gmg::k_apply_x2<false, double><<<l0.til2.nblocks, gmg::NT, 0, h->stream>>>(view<double, double>(l0), l0.til2, u,
-                                                                              h->Q, nullptr, nullptr);
+    if (l0.wx2 == 4)
+        gmg::k_apply_x2<false, double, 4><<<l0.til2.nblocks, gmg::NT, 0, h->stream>>>(view<double, double>(l0),
+                                                                                     l0.til2, u, h->Q, nullptr, nullptr);
+    else
+        gmg::k_apply_x2<false, double><<<l0.til2.nblocks, gmg::NT, 0, h->stream>>>(view<double, double>(l0), l0.til2,
+                                                                                  u, h->Q, nullptr, nullptr);
     LAUNCHCHK();
     return out_vec<double>(h, l0, h->Q, y);
 }

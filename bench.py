@@ -428,7 +428,7 @@ def profile_summary(d, top=25):
 
 # Finest-level kernel of each class in the MIXED step, as rocprofv3 names it.
 CLASS_KERNELS = {
-    "apply_dot": "k_apply_x2<true, float>",
+    "apply_dot": "k_apply_x2<true, float, 4>",  # 512 x 1 tiles on long rows
     "update_r": "k_update_r<float>",
     "update_xp": "k_update_xp<float, float>",
     "cheb_pre2": "k_cheb_pre2<float, bf16, false>",

@@ -75,10 +75,10 @@ def test_pmc_traffic_is_calibrated_by_the_copy(tmp_path, monkeypatch):
     # the calibration copy reads half its bytes in FETCH_SIZE and all of them in
     # WRITE_SIZE (the pattern the hardware shows): scales 2 and 1
     fetch = {"k_copy_march": [bench.COPY_BYTES / 1024 / 2] * 2,
-             "k_apply_x2<true, float>": [1000.0, 1000.0, 10.0],  # the small one is a coarse level
+             bench.CLASS_KERNELS["apply_dot"]: [1000.0, 1000.0, 10.0],  # the small one is a coarse level
              "k_update_r<float>": [500.0]}
     write = {"k_copy_march": [bench.COPY_BYTES / 1024] * 2,
-             "k_apply_x2<true, float>": [300.0, 300.0, 3.0],
+             bench.CLASS_KERNELS["apply_dot"]: [300.0, 300.0, 3.0],
              "k_update_r<float>": [200.0]}
     write_csv(str(tmp_path / "f" / "run_counter_collection.csv"), pmc_rows("FETCH_SIZE", fetch))
     write_csv(str(tmp_path / "w" / "run_counter_collection.csv"), pmc_rows("WRITE_SIZE", write))
